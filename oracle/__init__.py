@@ -1,0 +1,46 @@
+"""Plain CPU oracle for the same-level multipole-to-local (M2L) gravity interaction.
+
+TEST INFRASTRUCTURE ONLY. Nothing in the product path imports this package:
+only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may use it. It shares no code with the HIP library (no kernels,
+headers, tables, helpers or generated constants); the only code both sides use
+is the seeded input generator in ``synth/``, which holds none of the method's
+arithmetic.
+
+What it computes follows the gravity solver described in the paper's
+Octo-Tiger subsection (Sec. IV, "Octo-Tiger"): cell moments on N^3 = 8^3
+sub-grids co-located with the hydro grid, and the same-level cell-to-cell
+interaction step of the three-step gravity iteration (Sec. VI, "Usage of
+multiple HPX tasks per Kokkos kernel invocation"). The paper gives no
+formulas; the definitions written out here are textbook Cartesian FMM and are
+listed, with every reading taken where the paper is silent, in the design doc.
+
+Every floating-point step is plain NumPy float64 (float32 only in the
+split-precision emulation, which is an expectation model, not a reference).
+"""
+
+from .fmm import (  # noqa: F401
+    BLOCK,
+    FRAME,
+    FULL_MASK,
+    NCELL,
+    CENTRE_BIT,
+    double_factorial,
+    multi_indices,
+    ncomp,
+    stencil,
+    dtensor,
+    dtensor_all,
+    cell_centres,
+    present_cells,
+    p2m,
+    stencil_tensors,
+    m2l,
+    m2l_abs,
+    m2l_adjoint,
+    m2l_adjoint_abs,
+    p2m_adjoint,
+    direct_sum,
+    m2l_split32_emulated,
+    pair_count,
+)

@@ -1,0 +1,356 @@
+"""Oracle definitions: P2M, derivative tensors of 1/r, M2L, their adjoints.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): slow, plain, float64.
+
+Geometry (one sub-grid, the paper's N = 8 sub-grid of Sec. IV "Octo-Tiger"):
+  * a frame of 24^3 cells j = (x, y, z), x fastest, linear index x + 24 y + 576 z:
+    the 8^3 target sub-grid in the middle plus its 26 same-level neighbours;
+  * cell j spans [j h, (j + 1) h) per axis, centre c_j = (j + 1/2) h;
+  * neighbour block beta(j) = j // 8 in {0,1,2}^3, mask bit bx + 3 by + 9 bz,
+    the centre block is bit 13 and is always present;
+  * targets are the cells of the centre block, t = j - 8 in [0, 8)^3.
+
+Multi-indices k = (kx, ky, kz), |k| = kx + ky + kz, k! = kx! ky! kz!.
+I_p = {k : |k| <= p} in graded order (order 0, then x, y, z, then
+xx, xy, xz, yy, yz, zz, ...), C(p) = |I_p|.
+
+Definitions (Cartesian Taylor expansion of 1/|x - y| in both arguments):
+  M_k(j)  = sum_i m_i a_i^k / k!,  a_i = y_i - c_j                        (P2M)
+  D_m(R)  = d^m (1/|r|) at r = R                                          (Hobson)
+  T_d[k][n] = (-1)^|k| D_{k+n}(R_d),  R_d = c_target - c_source = -d h
+  L_n(t)  = sum_{d in S, beta(t+d) present} sum_k M_k(t + d) T_d[k][n]    (M2L)
+so that Phi(c_t + b) ~ sum_n L_n b^n / n! with Phi(x) = sum m / |x - y|.
+"""
+
+from math import factorial
+
+import numpy as np
+
+FRAME = 24
+BLOCK = 8
+NCELL = FRAME ** 3
+CENTRE_BIT = 13
+FULL_MASK = (1 << 27) - 1
+
+
+# ---------------------------------------------------------------------------
+# index sets, stencil, frame
+# ---------------------------------------------------------------------------
+
+def multi_indices(p):
+    """I_p in graded order: for n = 0..p, kx = n..0, ky = n-kx..0, kz = rest."""
+    out = []
+    for n in range(p + 1):
+        for kx in range(n, -1, -1):
+            for ky in range(n - kx, -1, -1):
+                out.append((kx, ky, n - kx - ky))
+    return out
+
+
+def ncomp(p):
+    """C(p) = (p+1)(p+2)(p+3)/6, the number of multi-indices with |k| <= p."""
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def stencil(rmin2=5, rmax2=36):
+    """Same-level interaction stencil S = {d in Z^3 : rmin2 <= |d|^2 <= rmax2}.
+
+    The default is the spherical shell 2 < |d| <= 6 (|S| = 892), listed with
+    dz slowest, then dy, then dx. d is the source cell minus the target cell.
+    """
+    r = int(np.floor(np.sqrt(rmax2)))
+    out = []
+    for dz in range(-r, r + 1):
+        for dy in range(-r, r + 1):
+            for dx in range(-r, r + 1):
+                q = dx * dx + dy * dy + dz * dz
+                if rmin2 <= q <= rmax2:
+                    out.append((dx, dy, dz))
+    return out
+
+
+def double_factorial(n):
+    """n!! with (-1)!! = 0!! = 1."""
+    out = 1
+    while n > 1:
+        out *= n
+        n -= 2
+    return out
+
+
+def cell_centres(h):
+    """Centres (j + 1/2) h of the 24^3 frame cells, shape [13824, 3] (x, y, z)."""
+    idx = np.arange(NCELL)
+    j = np.stack([idx % FRAME, (idx // FRAME) % FRAME, idx // (FRAME * FRAME)], axis=1)
+    return (j + 0.5) * h
+
+
+def present_cells(mask):
+    """Boolean [24, 24, 24] ([z][y][x]) of cells whose neighbour block is present."""
+    b = np.arange(FRAME) // BLOCK
+    bz, by, bx = np.meshgrid(b, b, b, indexing="ij")
+    bit = bx + 3 * by + 9 * bz
+    return ((int(mask) >> bit) & 1).astype(bool)
+
+
+def _monomials(a, p, with_factorial=True):
+    """a^k (/ k!) for all k in I_p; a has shape [..., 3]; returns [C, ...]."""
+    ks = multi_indices(p)
+    out = np.empty((len(ks),) + a.shape[:-1])
+    for c, (kx, ky, kz) in enumerate(ks):
+        v = a[..., 0] ** kx * a[..., 1] ** ky * a[..., 2] ** kz
+        if with_factorial:
+            v = v / (factorial(kx) * factorial(ky) * factorial(kz))
+        out[c] = v
+    return out
+
+
+# ---------------------------------------------------------------------------
+# derivatives of 1/r (Hobson's closed form)
+# ---------------------------------------------------------------------------
+
+def _hobson_term_coeff(a, i):
+    """a! / (2^i i! (a - 2i)!)."""
+    return factorial(a) // (2 ** i * factorial(i) * factorial(a - 2 * i))
+
+
+def dtensor(m, R):
+    """D_m(R) = d^m (1/|r|) at r = R, for one multi-index m; R has shape [..., 3].
+
+    Hobson's formula: with n = |m| = a + b + c and s = i + j + l,
+      D_m = sum_{i<=a/2, j<=b/2, l<=c/2} (-1)^(n-s) (2n-2s-1)!!
+            [a!/(2^i i!(a-2i)!)] [b!/(2^j j!(b-2j)!)] [c!/(2^l l!(c-2l)!)]
+            x^(a-2i) y^(b-2j) z^(c-2l) / r^(2n-2s+1).
+    """
+    a, b, c = m
+    n = a + b + c
+    R = np.asarray(R, dtype=np.float64)
+    x, y, z = R[..., 0], R[..., 1], R[..., 2]
+    r = np.sqrt(x * x + y * y + z * z)
+    out = np.zeros(R.shape[:-1])
+    for i in range(a // 2 + 1):
+        for j in range(b // 2 + 1):
+            for l in range(c // 2 + 1):
+                s = i + j + l
+                coeff = ((-1) ** (n - s)) * double_factorial(2 * n - 2 * s - 1) \
+                    * _hobson_term_coeff(a, i) * _hobson_term_coeff(b, j) * _hobson_term_coeff(c, l)
+                out = out + float(coeff) * (x ** (a - 2 * i)) * (y ** (b - 2 * j)) * (z ** (c - 2 * l)) \
+                    / r ** (2 * n - 2 * s + 1)
+    return out
+
+
+def dtensor_all(order, R):
+    """{m: D_m(R)} for every multi-index with |m| <= order."""
+    return {m: dtensor(m, R) for m in multi_indices(order)}
+
+
+def stencil_tensors(p, h, offsets=None):
+    """T_d[k][n] = (-1)^|k| D_{k+n}(-d h) for d in offsets; shape [|S|, C, C].
+
+    D is evaluated directly at R = -d h (no power-of-two rescaling here).
+    """
+    offsets = stencil() if offsets is None else offsets
+    ks = multi_indices(p)
+    R = -np.asarray(offsets, dtype=np.float64) * h
+    D = dtensor_all(2 * p, R)
+    C = len(ks)
+    T = np.empty((len(offsets), C, C))
+    for ik, k in enumerate(ks):
+        sign = -1.0 if sum(k) % 2 else 1.0
+        for jn, n in enumerate(ks):
+            T[:, ik, jn] = sign * D[(k[0] + n[0], k[1] + n[1], k[2] + n[2])]
+    return T
+
+
+# ---------------------------------------------------------------------------
+# P2M and its adjoint
+# ---------------------------------------------------------------------------
+
+def p2m(pos, mass, p, h, mask=FULL_MASK):
+    """Cell moments M_k(j) = sum_i m_i a_i^k / k! about the cell centres.
+
+    pos [13824, ppc, 3] absolute frame coordinates, mass [13824, ppc];
+    returns M [C, 24, 24, 24] ([k][z][y][x]); cells of absent blocks are 0.
+    The leaf case of the paper (a cell's mass as one monopole at its centre)
+    is the special case a_i = 0.
+    """
+    pos = np.asarray(pos, dtype=np.float64)
+    mass = np.asarray(mass, dtype=np.float64)
+    a = pos - cell_centres(h)[:, None, :]
+    mono = _monomials(a, p)                       # [C, 13824, ppc]
+    M = np.einsum("cji,ji->cj", mono, mass)        # sum over particles
+    M = M.reshape(-1, FRAME, FRAME, FRAME)
+    return np.where(present_cells(mask)[None], M, 0.0)
+
+
+def p2m_adjoint(pos, G, p, h, mask=FULL_MASK):
+    """dLoss/dm_i = sum_k G_k(j) a_i^k / k!; zero for particles in absent blocks.
+
+    pos [13824, ppc, 3], G [C, 24, 24, 24]; returns [13824, ppc].
+    """
+    pos = np.asarray(pos, dtype=np.float64)
+    a = pos - cell_centres(h)[:, None, :]
+    mono = _monomials(a, p)                       # [C, 13824, ppc]
+    Gc = np.asarray(G, dtype=np.float64).reshape(-1, NCELL)
+    g = np.einsum("cji,cj->ji", mono, Gc)
+    return np.where(present_cells(mask).reshape(NCELL)[:, None], g, 0.0)
+
+
+# ---------------------------------------------------------------------------
+# M2L, its absolute-value bound and its adjoint
+# ---------------------------------------------------------------------------
+
+def _source_window(src, d):
+    dx, dy, dz = d
+    lo = BLOCK
+    return src[:, lo + dz:lo + BLOCK + dz, lo + dy:lo + BLOCK + dy, lo + dx:lo + BLOCK + dx]
+
+
+def _masked(M, mask):
+    # absent blocks are treated as zero moments and their storage is never used
+    return np.where(present_cells(mask)[None], np.asarray(M, dtype=np.float64), 0.0)
+
+
+def m2l(M, p, h, mask=FULL_MASK, offsets=None):
+    """L_n(t) = sum_{d in S} sum_k M_k(t + d) T_d[k][n] for the 512 targets.
+
+    One [512 x C] . [C x C] product per stencil offset. M [C, 24, 24, 24];
+    returns L [C, 8, 8, 8].
+    """
+    offsets = stencil() if offsets is None else offsets
+    C = ncomp(p)
+    src = _masked(M, mask)
+    T = stencil_tensors(p, h, offsets)
+    L = np.zeros((C, BLOCK ** 3))
+    for d, Td in zip(offsets, T):
+        L += Td.T @ _source_window(src, d).reshape(C, -1)
+    return L.reshape(C, BLOCK, BLOCK, BLOCK)
+
+
+def m2l_abs(M, p, h, mask=FULL_MASK, offsets=None):
+    """Labs_n(t) = sum_d sum_k |M_k(t + d)| |T_d[k][n]|: the scale of the rounding
+    error of any summation order of L, used as the tolerance scale."""
+    offsets = stencil() if offsets is None else offsets
+    C = ncomp(p)
+    src = np.abs(_masked(M, mask))
+    T = np.abs(stencil_tensors(p, h, offsets))
+    L = np.zeros((C, BLOCK ** 3))
+    for d, Td in zip(offsets, T):
+        L += Td.T @ _source_window(src, d).reshape(C, -1)
+    return L.reshape(C, BLOCK, BLOCK, BLOCK)
+
+
+def m2l_adjoint(W, p, h, mask=FULL_MASK, offsets=None):
+    """G_k(s) = sum_{d : s - d in target block} sum_n W_n(s - d) T_d[k][n].
+
+    The transpose of m2l with respect to M, written out directly (each
+    offset scatters T_d W into the shifted window), so that T_{-d} = T_d^T
+    is a property to test rather than an assumption. W [C, 8, 8, 8];
+    returns G [C, 24, 24, 24], zero outside the reachable window and on
+    absent blocks.
+    """
+    offsets = stencil() if offsets is None else offsets
+    C = ncomp(p)
+    Wf = np.asarray(W, dtype=np.float64).reshape(C, -1)
+    T = stencil_tensors(p, h, offsets)
+    G = np.zeros((C, FRAME, FRAME, FRAME))
+    for d, Td in zip(offsets, T):
+        _source_window(G, d)[...] += (Td @ Wf).reshape(C, BLOCK, BLOCK, BLOCK)
+    return np.where(present_cells(mask)[None], G, 0.0)
+
+
+def m2l_adjoint_abs(W, p, h, mask=FULL_MASK, offsets=None):
+    """Gabs: m2l_adjoint on |W| and |T|, the tolerance scale of G."""
+    offsets = stencil() if offsets is None else offsets
+    C = ncomp(p)
+    Wf = np.abs(np.asarray(W, dtype=np.float64)).reshape(C, -1)
+    T = np.abs(stencil_tensors(p, h, offsets))
+    G = np.zeros((C, FRAME, FRAME, FRAME))
+    for d, Td in zip(offsets, T):
+        _source_window(G, d)[...] += (Td @ Wf).reshape(C, BLOCK, BLOCK, BLOCK)
+    return np.where(present_cells(mask)[None], G, 0.0)
+
+
+def pair_count(mask, offsets=None):
+    """Number of (target cell, offset) pairs whose source block is present."""
+    offsets = stencil() if offsets is None else offsets
+    pres = present_cells(mask)
+    return int(sum(_source_window(pres[None], d).sum() for d in offsets))
+
+
+# ---------------------------------------------------------------------------
+# direct Newtonian sum (small inputs only)
+# ---------------------------------------------------------------------------
+
+def direct_sum(pos, mass, h, order, mask=FULL_MASK, offsets=None, targets=None):
+    """Exact derivatives of Phi(x) = sum m_i / |x - y_i| at target centres.
+
+    Sources: the particles of the cells t + d, d in offsets, in present
+    blocks. L^exact_n(t) = sum m_i D_n(c_t - y_i) for |n| <= order.
+    targets: list of (tx, ty, tz) in [0, 8)^3 (default: all 512).
+    Returns [len(targets), C(order)].
+    """
+    offsets = stencil() if offsets is None else offsets
+    if targets is None:
+        targets = [(x, y, z) for z in range(BLOCK) for y in range(BLOCK) for x in range(BLOCK)]
+    pos = np.asarray(pos, dtype=np.float64)
+    mass = np.asarray(mass, dtype=np.float64)
+    pres = present_cells(mask)
+    ns = multi_indices(order)
+    out = np.zeros((len(targets), len(ns)))
+    for it, t in enumerate(targets):
+        jt = np.array(t) + BLOCK
+        ct = (jt + 0.5) * h
+        ys, ms = [], []
+        for d in offsets:
+            js = jt + np.array(d)
+            if not pres[js[2], js[1], js[0]]:
+                continue
+            cell = js[0] + FRAME * js[1] + FRAME * FRAME * js[2]
+            ys.append(pos[cell])
+            ms.append(mass[cell])
+        if not ys:
+            continue
+        Y = np.concatenate(ys)
+        Mm = np.concatenate(ms)
+        R = ct[None, :] - Y
+        for c, n in enumerate(ns):
+            out[it, c] = np.sum(Mm * dtensor(n, R))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# split-precision expectation model
+# ---------------------------------------------------------------------------
+
+def m2l_split32_emulated(M, p, h, mask=FULL_MASK, offsets=None, block=64):
+    """Expectation model of the split-FP32 M2L (not a bitwise reference).
+
+    Moments are scaled to unit spacing (M_k h^-|k|), tables taken at h = 1;
+    both are split into float32 hi/lo parts; per block of `block` offsets the
+    three products hi.hi + hi.lo + lo.hi are summed in float32, the block sum
+    is added to a float64 total, and L is scaled by h^(-1-|n|) at the end.
+    """
+    offsets = stencil() if offsets is None else offsets
+    ks = multi_indices(p)
+    C = len(ks)
+    order = np.array([sum(k) for k in ks], dtype=np.float64)
+    src = _masked(M, mask) * (h ** -order)[:, None, None, None]
+    T = stencil_tensors(p, 1.0, offsets)
+    m_hi = src.astype(np.float32)
+    m_lo = (src - m_hi.astype(np.float64)).astype(np.float32)
+    t_hi = T.astype(np.float32)
+    t_lo = (T - t_hi.astype(np.float64)).astype(np.float32)
+    L = np.zeros((C, BLOCK ** 3))
+    for b0 in range(0, len(offsets), block):
+        acc = np.zeros((C, BLOCK ** 3), dtype=np.float32)
+        for i in range(b0, min(b0 + block, len(offsets))):
+            d = offsets[i]
+            wh = _source_window(m_hi, d).reshape(C, -1)
+            wl = _source_window(m_lo, d).reshape(C, -1)
+            acc += t_hi[i].T @ wh
+            acc += t_lo[i].T @ wh
+            acc += t_hi[i].T @ wl
+        L += acc.astype(np.float64)
+    L *= (h ** (-1.0 - order))[:, None]
+    return L.reshape(C, BLOCK, BLOCK, BLOCK)
