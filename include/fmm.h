@@ -1,0 +1,155 @@
+/*
+ * fmm.h -- C ABI of the MI355X (gfx950) same-level FMM interaction library.
+ *
+ * The operations are the steps of the gravity solver's cell-to-cell
+ * interaction on N = 8 sub-grids (paper Sec. IV, "Octo-Tiger": FMM gravity
+ * co-located with the 8^3 hydro sub-grids, cells carrying multipole moments;
+ * Sec. VI, "Usage of multiple HPX tasks per Kokkos kernel invocation": the
+ * three-step gravity iteration whose second step is the same-level
+ * cell-to-cell "Multipole" interaction). The paper gives no formulas; the
+ * definitions below are the Cartesian Taylor expansion of 1/|x - y|:
+ *
+ *   frame      one sub-grid = 24^3 cells j = (x, y, z), x fastest, linear
+ *              index x + 24 y + 576 z: the 8^3 target block plus its 26
+ *              neighbour blocks. Cell j spans [j h, (j+1) h), centre
+ *              c_j = (j + 1/2) h. Block of cell j: j / 8 per axis, mask bit
+ *              bx + 3 by + 9 bz; bit 13 (the centre block) must be set.
+ *   I_p        multi-indices k = (kx, ky, kz), |k| <= p, graded order:
+ *              order 0; x, y, z; xx, xy, xz, yy, yz, zz; xxx, ... C(p) =
+ *              (p+1)(p+2)(p+3)/6 = 10, 20, 35 for p = 2, 3, 4.
+ *   P2M        M_k(j) = sum_i m_i a_i^k / k!,  a_i = y_i - c_j.
+ *   D_m(R)     the m-th Cartesian derivative of 1/|r| at R.
+ *   T_d[k][n]  (-1)^|k| D_{k+n}(-d h): d = source cell - target cell, over
+ *              the shell stencil S = {d in Z^3 : 5 <= |d|^2 <= 36}, |S| = 892.
+ *   M2L        L_n(t) = sum_{d in S} sum_k M_k(t + d) T_d[k][n] for the 512
+ *              target cells t (frame cells [8,16)^3); moments of absent
+ *              blocks count as zero and their storage is never read.
+ *              Phi(c_t + b) ~ sum_n L_n b^n / n! with Phi(x) = sum m / |x - y|.
+ *
+ * Memory layout (all float64, element offsets from the descriptor):
+ *   pos   per sub-grid [13824][ppc][3]  absolute frame coordinates
+ *   mass  per sub-grid [13824][ppc]
+ *   M, dM per sub-grid [C][24][24][24]  (component-major, x fastest)
+ *   L, dL per sub-grid [C][8][8][8]
+ *
+ * Conventions:
+ *   - The caller owns every data buffer (device memory, 8-byte aligned);
+ *     the library never frees caller memory and owns only what a context
+ *     holds (stencil tables, work lists, captured graphs, tuning choices).
+ *   - Compute calls are asynchronous on `stream` (a hipStream_t, NULL for
+ *     the null stream) and never synchronise the device.
+ *   - All argument checks run on the host before any HIP call: a call that
+ *     returns FMM_EINVAL has touched neither the device nor the context's
+ *     caches. HIP failures return FMM_EHIP; fmm_last_error() gives detail.
+ *   - A context is not thread-safe: use one per host thread.
+ *   - Results are deterministic run to run: every output element is owned
+ *     by one work item and summed in a fixed order (no atomics on outputs).
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_ctx fmm_ctx;
+
+typedef int32_t fmm_status;
+#define FMM_OK            0
+#define FMM_EINVAL       -1  /* bad argument; nothing was enqueued */
+#define FMM_ENOMEM       -2  /* a context-internal device/host allocation failed */
+#define FMM_EHIP         -3  /* a HIP runtime call failed (detail in fmm_last_error) */
+#define FMM_EUNSUPPORTED -4  /* valid request this context cannot run (e.g. host-only context) */
+
+typedef int32_t fmm_precision;
+#define FMM_FP64        0  /* float64 products and sums throughout */
+#define FMM_SPLIT_FP32  1  /* hi/lo float32 products, float32 sums per offset block,
+                              float64 across blocks, float64 tables and scaling */
+
+/* One descriptor per sub-grid (host memory). */
+typedef struct {
+    int32_t  p;           /* expansion order, 2, 3 or 4 */
+    int32_t  log2_inv_h;  /* cell spacing h = 2^-log2_inv_h, 0 <= log2_inv_h <= 2 */
+    uint32_t mask;        /* 27-bit present-block mask; bit 13 must be set */
+    int32_t  reserved;    /* must be 0 */
+    int64_t  m_off;       /* element offset of this sub-grid's M (or dM) block */
+    int64_t  l_off;       /* element offset of this sub-grid's L (or dL) block */
+    int64_t  part_off;    /* particle offset: pos at 3*part_off, mass at part_off */
+} fmm_subgrid;
+
+/* Library options (fmm_set_option). */
+#define FMM_OPT_M2L_KERNEL  1  /* 0 auto (default), 1 reference VALU kernel, 2 MFMA kernel */
+#define FMM_OPT_USE_GRAPH   2  /* 1 (default): replay cached hipGraphs for M2L; 0: plain launches */
+#define FMM_OPT_TILE_CONFIG 3  /* -1 (default): autotuned/built-in choice; >= 0 forces a table entry */
+
+/* Create a context on HIP device `device`, or a host-only context with
+ * device = -1 (argument checking and host queries only; compute calls then
+ * return FMM_EUNSUPPORTED after their checks pass). Generates the stencil
+ * tables T_d for p = 2, 3, 4 on the device (derivative recurrence in
+ * float64), which makes this call synchronous. */
+fmm_status fmm_create(fmm_ctx** out, int32_t device);
+
+/* Release everything the context owns; NULL is accepted. Synchronises the device. */
+fmm_status fmm_destroy(fmm_ctx* ctx);
+
+/* Static strings; never NULL. */
+const char* fmm_status_string(fmm_status s);
+const char* fmm_last_error(const fmm_ctx* ctx);
+
+fmm_status fmm_set_option(fmm_ctx* ctx, int32_t option, int64_t value);
+
+/* Host queries (no device work). */
+/* Number of stencil offsets (892) and the offsets (dx, dy, dz) in the
+ * library's order, if `offsets` is not NULL (room for 3 * 892 int32). */
+fmm_status fmm_stencil(int32_t* count, int32_t* offsets);
+/* Number of (target cell, offset) pairs whose source block is present,
+ * summed over the descriptors: the work unit of the throughput metric. */
+fmm_status fmm_pair_count(const fmm_subgrid* desc, int64_t nsub, int64_t* pairs);
+
+/* P2M (row "P2M": leaf moments about the cell centres; the paper's leaf
+ * cells are the a = 0 special case). pos/mass as above, ppc particles per
+ * cell (1..64). Writes all C * 13824 moments of each sub-grid; cells of
+ * absent blocks get 0 and their particles are not read. */
+fmm_status fmm_p2m(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
+                   const double* pos, const double* mass, int32_t ppc,
+                   double* M, void* stream);
+
+/* M2L (the same-level cell-to-cell interaction): writes L of every
+ * sub-grid (overwrites, C * 512 values each). Mixed p, h and masks in one
+ * call are handled by one persistent launch over a cost-sorted work list. */
+fmm_status fmm_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
+                   const double* M, double* L, fmm_precision prec, void* stream);
+
+/* Adjoint of M2L with respect to M: dM_k(s) = sum over (t, d) with
+ * s = t + d of sum_n dL_n(t) T_d[k][n]. dL laid out like L, dM like M;
+ * dM is fully written (zero outside the reachable 20^3 window [2,22)^3
+ * and on absent blocks). */
+fmm_status fmm_m2l_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
+                            const double* dL, double* dM, void* stream);
+
+/* Adjoint of P2M with respect to the masses: dmass_i = sum_k dM_k(j) a_i^k / k!
+ * (positions held fixed). dmass laid out like mass, fully written (zero
+ * for particles of absent blocks). */
+fmm_status fmm_p2m_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
+                            const double* pos, int32_t ppc, const double* dM,
+                            double* dmass, void* stream);
+
+/* Copy the float64 stencil tables T_d[k][n] at unit spacing for order p to
+ * device memory `out` ([892][C][C], offsets in fmm_stencil order). */
+fmm_status fmm_stencil_tables(fmm_ctx* ctx, int32_t p, double* out, void* stream);
+
+/* Time the candidate M2L tile configurations on these descriptors and
+ * buffers (M read, L overwritten) and keep the fastest for later calls
+ * with the same precision; `chosen` (may be NULL) receives its index.
+ * Synchronises the stream. */
+fmm_status fmm_autotune(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
+                        const double* M, double* L, fmm_precision prec,
+                        void* stream, int32_t* chosen);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMM_H */

@@ -1,0 +1,619 @@
+// C ABI of the library: argument checks (host only, before any HIP call),
+// context state (stencil tables, descriptor/work-list caches, captured
+// graphs, tuning choices) and dispatch to the kernels.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "kernels.h"
+#include "m2l_mfma.h"
+
+using namespace fmm;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+const char* kStatusStrings[] = {"FMM_OK", "FMM_EINVAL: invalid argument",
+                                "FMM_ENOMEM: out of memory", "FMM_EHIP: HIP runtime error",
+                                "FMM_EUNSUPPORTED: unsupported request"};
+
+// Shell stencil 5 <= |d|^2 <= 36, dz slowest, then dy, then dx.
+std::vector<int> make_stencil() {
+  std::vector<int> s;
+  for (int dz = -kRad; dz <= kRad; ++dz)
+    for (int dy = -kRad; dy <= kRad; ++dy)
+      for (int dx = -kRad; dx <= kRad; ++dx) {
+        int q = dx * dx + dy * dy + dz * dz;
+        if (q >= 5 && q <= 36) {
+          s.push_back(dx);
+          s.push_back(dy);
+          s.push_back(dz);
+        }
+      }
+  return s;
+}
+
+const std::vector<int>& stencil_host() {
+  static const std::vector<int> s = make_stencil();
+  return s;
+}
+
+// pairs (target cell, offset) whose source lies in each of the 27 blocks
+const std::vector<int64_t>& block_pairs() {
+  static const std::vector<int64_t> bp = [] {
+    std::vector<int64_t> v(27, 0);
+    const auto& s = stencil_host();
+    for (int t = 0; t < kNTarget; ++t) {
+      int jx = t % 8 + 8, jy = (t / 8) % 8 + 8, jz = t / 64 + 8;
+      for (size_t i = 0; i < s.size(); i += 3) {
+        int sx = jx + s[i], sy = jy + s[i + 1], sz = jz + s[i + 2];
+        v[(sx / 8) + 3 * (sy / 8) + 9 * (sz / 8)]++;
+      }
+    }
+    return v;
+  }();
+  return bp;
+}
+
+int64_t pairs_of_mask(uint32_t mask) {
+  const auto& bp = block_pairs();
+  int64_t n = 0;
+  for (int b = 0; b < 27; ++b)
+    if ((mask >> b) & 1u) n += bp[b];
+  return n;
+}
+
+uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* p = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+}  // namespace
+
+// Descriptor set uploaded to the device, plus everything derived from it.
+struct DescEntry {
+  std::vector<fmm_subgrid> host;
+  uint64_t hash = 0;
+  uint64_t last_use = 0;
+  void* dev = nullptr;            // one device allocation: descriptors, id lists, work list
+  void* pinned = nullptr;         // pinned host copy of the same bytes
+  size_t bytes = 0;
+  DevDesc* d_desc = nullptr;
+  int* d_ids[kMaxP + 1] = {};     // reference kernels: sub-grids per order
+  int count[kMaxP + 1] = {};
+  WorkList work;                  // matrix-core kernels
+  hipEvent_t ready = nullptr;     // upload finished
+  hipEvent_t last_launch = nullptr;
+};
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;
+};
+
+struct fmm_ctx {
+  int device = -1;
+  bool host_only = true;
+  std::string last_error;
+  hipStream_t internal = nullptr;
+  int* d_stencil = nullptr;
+  double* d_D = nullptr;                      // [892][165] derivatives up to order 8
+  double* d_T[kMaxP + 1] = {};                // canonical [892][C][C] per order
+  MfmaTables mfma;                            // packed tables for the matrix-core kernels
+  std::vector<std::unique_ptr<DescEntry>> descs;
+  std::unordered_map<uint64_t, GraphEntry> graphs;
+  uint64_t clock = 0;
+  int m2l_kernel = 0;                         // 0 auto, 1 reference, 2 matrix core
+  int use_graph = 1;
+  int tile_config = -1;
+  int tuned[2] = {-1, -1};                    // per precision
+};
+
+namespace {
+
+fmm_status set_err(fmm_ctx* ctx, fmm_status st, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  else g_create_error = msg;
+  return st;
+}
+
+fmm_status hip_err(fmm_ctx* ctx, hipError_t e, const char* what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return set_err(ctx, e == hipErrorOutOfMemory ? FMM_ENOMEM : FMM_EHIP, msg);
+}
+
+#define HIP_TRY(ctx, call)                                   \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return hip_err((ctx), e_, #call);  \
+  } while (0)
+
+bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+fmm_status check_ctx(fmm_ctx* ctx) {
+  if (!ctx) return set_err(nullptr, FMM_EINVAL, "context is NULL");
+  return FMM_OK;
+}
+
+fmm_status check_desc(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub) {
+  if (nsub < 0) return set_err(ctx, FMM_EINVAL, "nsub < 0");
+  if (nsub > 0x7fffffff) return set_err(ctx, FMM_EINVAL, "nsub exceeds 2^31 - 1");
+  if (nsub > 0 && !desc) return set_err(ctx, FMM_EINVAL, "desc is NULL");
+  for (int64_t b = 0; b < nsub; ++b) {
+    const fmm_subgrid& d = desc[b];
+    char buf[160];
+    if (d.p < 2 || d.p > kMaxP) {
+      snprintf(buf, sizeof buf, "desc[%lld].p = %d not in {2,3,4}", (long long)b, d.p);
+      return set_err(ctx, FMM_EINVAL, buf);
+    }
+    if (d.log2_inv_h < 0 || d.log2_inv_h > 2) {
+      snprintf(buf, sizeof buf, "desc[%lld].log2_inv_h = %d not in [0,2]", (long long)b, d.log2_inv_h);
+      return set_err(ctx, FMM_EINVAL, buf);
+    }
+    if (d.mask > kFullMask || !((d.mask >> kCentreBit) & 1u)) {
+      snprintf(buf, sizeof buf, "desc[%lld].mask = 0x%x: needs bit 13 and no bit above 26", (long long)b, d.mask);
+      return set_err(ctx, FMM_EINVAL, buf);
+    }
+    if (d.reserved != 0) {
+      snprintf(buf, sizeof buf, "desc[%lld].reserved must be 0", (long long)b);
+      return set_err(ctx, FMM_EINVAL, buf);
+    }
+    if (d.m_off < 0 || d.l_off < 0 || d.part_off < 0) {
+      snprintf(buf, sizeof buf, "desc[%lld] has a negative offset", (long long)b);
+      return set_err(ctx, FMM_EINVAL, buf);
+    }
+  }
+  return FMM_OK;
+}
+
+fmm_status check_ptr(fmm_ctx* ctx, const void* p, const char* name, int64_t nsub) {
+  if (nsub == 0) return FMM_OK;
+  if (!p) return set_err(ctx, FMM_EINVAL, std::string(name) + " is NULL");
+  if (!aligned8(p)) return set_err(ctx, FMM_EINVAL, std::string(name) + " is not 8-byte aligned");
+  return FMM_OK;
+}
+
+fmm_status check_ppc(fmm_ctx* ctx, int32_t ppc) {
+  if (ppc < 1 || ppc > 64) return set_err(ctx, FMM_EINVAL, "ppc not in [1, 64]");
+  return FMM_OK;
+}
+
+#define CHECK_OK(expr)                    \
+  do {                                    \
+    fmm_status s_ = (expr);               \
+    if (s_ != FMM_OK) return s_;          \
+  } while (0)
+
+// Set the context's device for the duration of a call, restore on exit.
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != dev) {
+      err = hipSetDevice(dev);
+      changed = err == hipSuccess;
+    }
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+void free_entry(DescEntry* e) {
+  if (e->last_launch) (void)hipEventSynchronize(e->last_launch);
+  if (e->ready) (void)hipEventSynchronize(e->ready);
+  if (e->dev) (void)hipFree(e->dev);
+  if (e->pinned) (void)hipHostFree(e->pinned);
+  if (e->ready) (void)hipEventDestroy(e->ready);
+  if (e->last_launch) (void)hipEventDestroy(e->last_launch);
+}
+
+constexpr size_t kMaxDescEntries = 8;
+constexpr size_t kMaxGraphs = 16;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Find or upload the descriptor set; builds the id lists and the work list.
+fmm_status get_desc(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, hipStream_t stream,
+                    DescEntry** out) {
+  const size_t nbytes = sizeof(fmm_subgrid) * (size_t)nsub;
+  const uint64_t h = fnv1a(desc, nbytes, fnv1a(&nsub, sizeof nsub));
+  for (auto& e : ctx->descs) {
+    if (e->hash == h && e->host.size() == (size_t)nsub &&
+        std::memcmp(e->host.data(), desc, nbytes) == 0) {
+      e->last_use = ++ctx->clock;
+      HIP_TRY(ctx, hipStreamWaitEvent(stream, e->ready, 0));
+      *out = e.get();
+      return FMM_OK;
+    }
+  }
+  if (ctx->descs.size() >= kMaxDescEntries) {
+    auto it = std::min_element(ctx->descs.begin(), ctx->descs.end(),
+                               [](const auto& a, const auto& b) { return a->last_use < b->last_use; });
+    // graphs refer to this entry's work list: drop them all (re-captured on demand)
+    for (auto& g : ctx->graphs) {
+      if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+      if (g.second.graph) (void)hipGraphDestroy(g.second.graph);
+    }
+    ctx->graphs.clear();
+    free_entry(it->get());
+    ctx->descs.erase(it);
+  }
+  auto e = std::make_unique<DescEntry>();
+  e->host.assign(desc, desc + nsub);
+  e->hash = h;
+  e->last_use = ++ctx->clock;
+  // layout: descriptors | ids per order | work list
+  std::vector<int> ids[kMaxP + 1];
+  for (int64_t b = 0; b < nsub; ++b) ids[desc[b].p].push_back((int)b);
+  std::vector<WorkItem> items = build_work_list(desc, nsub);
+  size_t off_desc = 0;
+  size_t off = align_up(nbytes, 256);
+  size_t off_ids[kMaxP + 1] = {};
+  for (int p = 2; p <= kMaxP; ++p) {
+    off_ids[p] = off;
+    off = align_up(off + sizeof(int) * ids[p].size(), 256);
+  }
+  size_t off_work = off;
+  off = align_up(off + sizeof(WorkItem) * items.size(), 256);
+  size_t off_counter = off;
+  off = align_up(off + 256, 256);
+  e->bytes = off;
+  HIP_TRY(ctx, hipMalloc(&e->dev, e->bytes));
+  HIP_TRY(ctx, hipHostMalloc(&e->pinned, e->bytes, hipHostMallocDefault));
+  char* hp = static_cast<char*>(e->pinned);
+  std::memset(hp, 0, e->bytes);
+  std::memcpy(hp + off_desc, desc, nbytes);
+  for (int p = 2; p <= kMaxP; ++p) std::memcpy(hp + off_ids[p], ids[p].data(), sizeof(int) * ids[p].size());
+  std::memcpy(hp + off_work, items.data(), sizeof(WorkItem) * items.size());
+  char* dp = static_cast<char*>(e->dev);
+  e->d_desc = reinterpret_cast<DevDesc*>(dp + off_desc);
+  for (int p = 2; p <= kMaxP; ++p) {
+    e->d_ids[p] = reinterpret_cast<int*>(dp + off_ids[p]);
+    e->count[p] = (int)ids[p].size();
+  }
+  e->work.items = reinterpret_cast<const WorkItem*>(dp + off_work);
+  e->work.count = (int)items.size();
+  e->work.counter = reinterpret_cast<unsigned*>(dp + off_counter);
+  e->work.cost = 0;
+  for (const auto& it : items) e->work.cost += it.cost;
+  HIP_TRY(ctx, hipEventCreateWithFlags(&e->ready, hipEventDisableTiming));
+  HIP_TRY(ctx, hipEventCreateWithFlags(&e->last_launch, hipEventDisableTiming));
+  HIP_TRY(ctx, hipMemcpyAsync(e->dev, e->pinned, e->bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(ctx, hipEventRecord(e->ready, stream));
+  *out = e.get();
+  ctx->descs.push_back(std::move(e));
+  return FMM_OK;
+}
+
+fmm_status mark_used(fmm_ctx* ctx, DescEntry* e, hipStream_t stream) {
+  HIP_TRY(ctx, hipEventRecord(e->last_launch, stream));
+  return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fmm_status_string(fmm_status s) {
+  if (s <= 0 && s >= -4) return kStatusStrings[-s];
+  return "unknown fmm_status";
+}
+
+const char* fmm_last_error(const fmm_ctx* ctx) {
+  return ctx ? ctx->last_error.c_str() : g_create_error.c_str();
+}
+
+fmm_status fmm_stencil(int32_t* count, int32_t* offsets) {
+  if (!count) return set_err(nullptr, FMM_EINVAL, "count is NULL");
+  const auto& s = stencil_host();
+  *count = (int32_t)(s.size() / 3);
+  if (offsets) std::memcpy(offsets, s.data(), s.size() * sizeof(int32_t));
+  return FMM_OK;
+}
+
+fmm_status fmm_pair_count(const fmm_subgrid* desc, int64_t nsub, int64_t* pairs) {
+  if (!pairs) return set_err(nullptr, FMM_EINVAL, "pairs is NULL");
+  CHECK_OK(check_desc(nullptr, desc, nsub));
+  int64_t n = 0;
+  for (int64_t b = 0; b < nsub; ++b) n += pairs_of_mask(desc[b].mask);
+  *pairs = n;
+  return FMM_OK;
+}
+
+fmm_status fmm_create(fmm_ctx** out, int32_t device) {
+  if (!out) return set_err(nullptr, FMM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (device < -1) return set_err(nullptr, FMM_EINVAL, "device < -1");
+  auto ctx = std::make_unique<fmm_ctx>();
+  if (device == -1) {
+    *out = ctx.release();
+    return FMM_OK;
+  }
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_err(nullptr, e, "hipGetDeviceCount");
+  if (device >= ndev) return set_err(nullptr, FMM_EINVAL, "device index out of range");
+  ctx->device = device;
+  ctx->host_only = false;
+  DeviceGuard guard(device);
+  if (guard.err != hipSuccess) return hip_err(nullptr, guard.err, "hipSetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return hip_err(nullptr, e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return set_err(nullptr, FMM_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName + ", library is built for gfx950");
+  fmm_ctx* c = ctx.get();
+  auto fail = [&](hipError_t err, const char* what) {
+    fmm_status st = hip_err(c, err, what);
+    g_create_error = c->last_error;
+    fmm_destroy(ctx.release());
+    return st;
+  };
+#define CREATE_TRY(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) return fail(e_, #call); } while (0)
+  CREATE_TRY(hipStreamCreateWithFlags(&c->internal, hipStreamNonBlocking));
+  const auto& st = stencil_host();
+  CREATE_TRY(hipMalloc(&c->d_stencil, st.size() * sizeof(int)));
+  CREATE_TRY(hipMemcpyAsync(c->d_stencil, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice, c->internal));
+  CREATE_TRY(hipMalloc(&c->d_D, sizeof(double) * kNStencil * ncomp(kMaxOrderD)));
+  CREATE_TRY(launch_gen_tables(c->d_stencil, kMaxOrderD, c->d_D, c->internal));
+  for (int p = 2; p <= kMaxP; ++p) {
+    const int C = ncomp(p);
+    CREATE_TRY(hipMalloc(&c->d_T[p], sizeof(double) * kNStencil * C * C));
+    CREATE_TRY(launch_build_tensors(c->d_D, kMaxOrderD, p, c->d_T[p], c->internal));
+  }
+  CREATE_TRY(mfma_tables_create(&c->mfma, c->d_T, c->d_stencil, c->internal));
+  CREATE_TRY(hipStreamSynchronize(c->internal));
+#undef CREATE_TRY
+  *out = ctx.release();
+  return FMM_OK;
+}
+
+fmm_status fmm_destroy(fmm_ctx* ctx) {
+  if (!ctx) return FMM_OK;
+  if (!ctx->host_only) {
+    DeviceGuard guard(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& g : ctx->graphs) {
+      if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+      if (g.second.graph) (void)hipGraphDestroy(g.second.graph);
+    }
+    for (auto& e : ctx->descs) free_entry(e.get());
+    mfma_tables_destroy(&ctx->mfma);
+    for (int p = 0; p <= kMaxP; ++p)
+      if (ctx->d_T[p]) (void)hipFree(ctx->d_T[p]);
+    if (ctx->d_D) (void)hipFree(ctx->d_D);
+    if (ctx->d_stencil) (void)hipFree(ctx->d_stencil);
+    if (ctx->internal) (void)hipStreamDestroy(ctx->internal);
+  }
+  delete ctx;
+  return FMM_OK;
+}
+
+fmm_status fmm_set_option(fmm_ctx* ctx, int32_t option, int64_t value) {
+  CHECK_OK(check_ctx(ctx));
+  switch (option) {
+    case FMM_OPT_M2L_KERNEL:
+      if (value < 0 || value > 2) return set_err(ctx, FMM_EINVAL, "FMM_OPT_M2L_KERNEL value not in [0,2]");
+      ctx->m2l_kernel = (int)value;
+      return FMM_OK;
+    case FMM_OPT_USE_GRAPH:
+      if (value != 0 && value != 1) return set_err(ctx, FMM_EINVAL, "FMM_OPT_USE_GRAPH value not 0/1");
+      ctx->use_graph = (int)value;
+      return FMM_OK;
+    case FMM_OPT_TILE_CONFIG:
+      if (value < -1 || value >= mfma_num_configs()) return set_err(ctx, FMM_EINVAL, "FMM_OPT_TILE_CONFIG out of range");
+      ctx->tile_config = (int)value;
+      return FMM_OK;
+    default:
+      return set_err(ctx, FMM_EINVAL, "unknown option");
+  }
+}
+
+fmm_status fmm_p2m(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const double* pos,
+                   const double* mass, int32_t ppc, double* M, void* stream) {
+  CHECK_OK(check_ctx(ctx));
+  CHECK_OK(check_desc(ctx, desc, nsub));
+  CHECK_OK(check_ppc(ctx, ppc));
+  CHECK_OK(check_ptr(ctx, pos, "pos", nsub));
+  CHECK_OK(check_ptr(ctx, mass, "mass", nsub));
+  CHECK_OK(check_ptr(ctx, M, "M", nsub));
+  if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
+  if (nsub == 0) return FMM_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  DescEntry* e = nullptr;
+  CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
+  HIP_TRY(ctx, launch_p2m(e->d_desc, nsub, pos, mass, ppc, M, s));
+  return mark_used(ctx, e, s);
+}
+
+fmm_status fmm_p2m_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const double* pos,
+                            int32_t ppc, const double* dM, double* dmass, void* stream) {
+  CHECK_OK(check_ctx(ctx));
+  CHECK_OK(check_desc(ctx, desc, nsub));
+  CHECK_OK(check_ppc(ctx, ppc));
+  CHECK_OK(check_ptr(ctx, pos, "pos", nsub));
+  CHECK_OK(check_ptr(ctx, dM, "dM", nsub));
+  CHECK_OK(check_ptr(ctx, dmass, "dmass", nsub));
+  if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
+  if (nsub == 0) return FMM_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  DescEntry* e = nullptr;
+  CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
+  HIP_TRY(ctx, launch_p2m_backward(e->d_desc, nsub, pos, ppc, dM, dmass, s));
+  return mark_used(ctx, e, s);
+}
+
+static fmm_status run_ref(fmm_ctx* ctx, DescEntry* e, bool backward, const double* src, double* out,
+                          hipStream_t s) {
+  for (int p = 2; p <= kMaxP; ++p)
+    HIP_TRY(ctx, launch_m2l_ref(p, backward, e->d_desc, e->d_ids[p], e->count[p], ctx->d_stencil,
+                                ctx->d_T[p], src, out, s));
+  return FMM_OK;
+}
+
+// Launch the persistent matrix-core kernel, through a cached graph if enabled.
+static fmm_status run_mfma(fmm_ctx* ctx, DescEntry* e, const double* M, double* L,
+                           fmm_precision prec, int cfg, hipStream_t s) {
+  if (!ctx->use_graph) {
+    HIP_TRY(ctx, launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, s));
+    return FMM_OK;
+  }
+  uint64_t key = fnv1a(&e->hash, sizeof e->hash);
+  key = fnv1a(&M, sizeof M, key);
+  key = fnv1a(&L, sizeof L, key);
+  key = fnv1a(&prec, sizeof prec, key);
+  key = fnv1a(&cfg, sizeof cfg, key);
+  auto it = ctx->graphs.find(key);
+  if (it == ctx->graphs.end()) {
+    if (ctx->graphs.size() >= kMaxGraphs) {
+      auto victim = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                     [](const auto& a, const auto& b) { return a.second.last_use < b.second.last_use; });
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      (void)hipGraphExecDestroy(victim->second.exec);
+      (void)hipGraphDestroy(victim->second.graph);
+      ctx->graphs.erase(victim);
+    }
+    GraphEntry g;
+    HIP_TRY(ctx, hipStreamBeginCapture(ctx->internal, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, ctx->internal);
+    hipError_t ce = hipStreamEndCapture(ctx->internal, &g.graph);
+    if (le != hipSuccess) return hip_err(ctx, le, "launch_m2l_mfma (capture)");
+    if (ce != hipSuccess) return hip_err(ctx, ce, "hipStreamEndCapture");
+    HIP_TRY(ctx, hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+    it = ctx->graphs.emplace(key, g).first;
+  }
+  it->second.last_use = ++ctx->clock;
+  HIP_TRY(ctx, hipGraphLaunch(it->second.exec, s));
+  return FMM_OK;
+}
+
+static int pick_config(fmm_ctx* ctx, fmm_precision prec) {
+  if (ctx->tile_config >= 0) return ctx->tile_config;
+  if (ctx->tuned[prec] >= 0) return ctx->tuned[prec];
+  return mfma_default_config(prec);
+}
+
+fmm_status fmm_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const double* M, double* L,
+                   fmm_precision prec, void* stream) {
+  CHECK_OK(check_ctx(ctx));
+  CHECK_OK(check_desc(ctx, desc, nsub));
+  CHECK_OK(check_ptr(ctx, M, "M", nsub));
+  CHECK_OK(check_ptr(ctx, L, "L", nsub));
+  if (prec != FMM_FP64 && prec != FMM_SPLIT_FP32) return set_err(ctx, FMM_EINVAL, "unknown precision");
+  if (prec == FMM_SPLIT_FP32 && ctx->m2l_kernel == 1)
+    return set_err(ctx, FMM_EINVAL, "the reference kernel computes FMM_FP64 only");
+  if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
+  if (nsub == 0) return FMM_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  DescEntry* e = nullptr;
+  CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
+  if (ctx->m2l_kernel == 1) {
+    CHECK_OK(run_ref(ctx, e, false, M, L, s));
+  } else {
+    CHECK_OK(run_mfma(ctx, e, M, L, prec, pick_config(ctx, prec), s));
+  }
+  return mark_used(ctx, e, s);
+}
+
+fmm_status fmm_m2l_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const double* dL,
+                            double* dM, void* stream) {
+  CHECK_OK(check_ctx(ctx));
+  CHECK_OK(check_desc(ctx, desc, nsub));
+  CHECK_OK(check_ptr(ctx, dL, "dL", nsub));
+  CHECK_OK(check_ptr(ctx, dM, "dM", nsub));
+  if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
+  if (nsub == 0) return FMM_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  DescEntry* e = nullptr;
+  CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
+  if (ctx->m2l_kernel == 1) {
+    CHECK_OK(run_ref(ctx, e, true, dL, dM, s));
+  } else {
+    HIP_TRY(ctx, launch_m2l_mfma_backward(ctx->mfma, e->work, e->d_desc, dL, dM, s));
+  }
+  return mark_used(ctx, e, s);
+}
+
+fmm_status fmm_stencil_tables(fmm_ctx* ctx, int32_t p, double* out, void* stream) {
+  CHECK_OK(check_ctx(ctx));
+  if (p < 2 || p > kMaxP) return set_err(ctx, FMM_EINVAL, "p not in {2,3,4}");
+  CHECK_OK(check_ptr(ctx, out, "out", 1));
+  if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  const int C = ncomp(p);
+  HIP_TRY(ctx, hipMemcpyAsync(out, ctx->d_T[p], sizeof(double) * kNStencil * C * C,
+                              hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+  return FMM_OK;
+}
+
+fmm_status fmm_autotune(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const double* M,
+                        double* L, fmm_precision prec, void* stream, int32_t* chosen) {
+  CHECK_OK(check_ctx(ctx));
+  CHECK_OK(check_desc(ctx, desc, nsub));
+  CHECK_OK(check_ptr(ctx, M, "M", nsub));
+  CHECK_OK(check_ptr(ctx, L, "L", nsub));
+  if (prec != FMM_FP64 && prec != FMM_SPLIT_FP32) return set_err(ctx, FMM_EINVAL, "unknown precision");
+  if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
+  if (nsub == 0) {
+    if (chosen) *chosen = pick_config(ctx, prec);
+    return FMM_OK;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  DescEntry* e = nullptr;
+  CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
+  hipEvent_t t0, t1;
+  HIP_TRY(ctx, hipEventCreate(&t0));
+  HIP_TRY(ctx, hipEventCreate(&t1));
+  int best = -1;
+  float best_ms = 0.f;
+  for (int cfg = 0; cfg < mfma_num_configs(); ++cfg) {
+    if (!mfma_config_supports(cfg, prec)) continue;
+    // one warm-up launch, then the best of three
+    HIP_TRY(ctx, launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, s));
+    float cfg_ms = 1e30f;
+    for (int r = 0; r < 3; ++r) {
+      HIP_TRY(ctx, hipEventRecord(t0, s));
+      HIP_TRY(ctx, launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, s));
+      HIP_TRY(ctx, hipEventRecord(t1, s));
+      HIP_TRY(ctx, hipEventSynchronize(t1));
+      float ms = 0.f;
+      HIP_TRY(ctx, hipEventElapsedTime(&ms, t0, t1));
+      cfg_ms = std::min(cfg_ms, ms);
+    }
+    if (best < 0 || cfg_ms < best_ms) {
+      best = cfg;
+      best_ms = cfg_ms;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  ctx->tuned[prec] = best;
+  if (chosen) *chosen = best;
+  return mark_used(ctx, e, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,58 @@
+// Matrix-core M2L kernels (persistent, work-list driven) and their tables.
+#pragma once
+
+#include <vector>
+
+#include "fmm_common.h"
+
+namespace fmm {
+
+// One work item: a sub-grid (forward and adjoint kernels both own whole
+// sub-grids, so every output element has exactly one writer).
+struct WorkItem {
+  int32_t sub;    // descriptor index
+  int32_t cost;   // relative cost used for the longest-first order
+};
+
+struct WorkList {
+  const WorkItem* items = nullptr;   // device, longest first
+  int count = 0;
+  unsigned* counter = nullptr;       // device work counter, reset by every launch
+  int64_t cost = 0;
+};
+
+// Host: items for the descriptors, longest first (cost ~ C^2 x present pairs).
+std::vector<WorkItem> build_work_list(const fmm_subgrid* desc, int64_t nsub);
+
+constexpr int kQuads = kNStencil / 4;   // offsets are consumed four at a time
+static_assert(kNStencil % 4 == 0, "offset quads");
+
+struct MfmaTables {
+  // forward, per order p: [rounds][quad][comp of pair][n-group][kk*4 + j] float64
+  double* fwd[kMaxP + 1] = {};
+  // split precision, per order p: the same layout, float32 hi and lo parts
+  float* fwd_hi[kMaxP + 1] = {};
+  float* fwd_lo[kMaxP + 1] = {};
+  // adjoint, per order p: [offset][k-chunk][n-group][kk*4 + j] float64
+  double* bwd[kMaxP + 1] = {};
+  const int* stencil = nullptr;   // [892][3] offsets (owned by the context)
+  int* lds_off = nullptr;     // [892] dx + 20 dy + 400 dz
+  uint32_t* touch = nullptr;  // [8][quads] blocks touched by an 8x8 target plane per quad
+  int num_cu = 0;
+};
+
+hipError_t mfma_tables_create(MfmaTables* t, double* const* d_T, const int* d_stencil,
+                              hipStream_t s);
+void mfma_tables_destroy(MfmaTables* t);
+
+int mfma_num_configs();
+bool mfma_config_supports(int cfg, fmm_precision prec);
+int mfma_default_config(fmm_precision prec);
+
+hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc* d_desc,
+                           const double* M, double* L, fmm_precision prec, int cfg,
+                           hipStream_t s);
+hipError_t launch_m2l_mfma_backward(const MfmaTables& t, const WorkList& w, const DevDesc* d_desc,
+                                    const double* dL, double* dM, hipStream_t s);
+
+}  // namespace fmm

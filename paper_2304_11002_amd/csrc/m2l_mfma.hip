@@ -1,0 +1,509 @@
+// Matrix-core M2L on gfx950: v_mfma_f64_4x4x4_4b (four independent 4x4x4
+// products per instruction), persistent workgroups over a longest-first list
+// of sub-grids.
+//
+// Forward (one workgroup owns one sub-grid's 512 targets for the whole sum):
+//   L[t][n] = h^(-1-|n|) sum_d sum_k [h^-|k| M_k(t + d)] T_d[k][n]
+// is a sum over (d, k) of rank-1 updates of the [512 x C] output. The
+// reduction is taken four stencil offsets at a time for one moment
+// component: one instruction multiplies a [16 cells x 4 offsets] slice of the
+// shifted source window (A) by [4 offsets x 4 components] of the tables (B),
+// for four groups of 4 cells at once. C = 20 splits into five column groups
+// of 4, so no column padding is computed at p = 3.
+//
+// Data movement: the 20^3 reachable window of two moment components at a
+// time ("round") is staged in LDS as double2 (128,000 bytes), zero on absent
+// blocks and pre-scaled by h^-|k| (exact powers of two); every cell of it is
+// then reused by all 892 offsets. Table operands stream from L2 (the packed
+// tables are laid out in consumption order). The only HBM traffic is the
+// window (read once) and L.
+//
+// Operand lane layouts of v_mfma_f64_4x4x4_4b (checked on gfx950):
+//   A: lane l -> block (l%16)/4, row l%4, k l/16   (so: cell l%16 of a 16-cell tile)
+//   B: lane l -> block (l%16)/4, col l%4, k l/16
+//   D: lane l -> block (l%16)/4, col l%4, row l/16 (so: cell 4*((l%16)/4) + l/16)
+#include <algorithm>
+
+#include "kernels.h"
+#include "m2l_mfma.h"
+
+namespace fmm {
+
+namespace {
+
+constexpr int kWinCells = kWin * kWin * kWin;   // 8000
+
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+__global__ void reset_counter_kernel(unsigned* counter) { *counter = 0u; }
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+
+template <int P, int WAVES>
+__device__ __forceinline__ void fwd_subgrid(const DevDesc& d, const double* __restrict__ M,
+                                            double* __restrict__ L, const double* __restrict__ Bp,
+                                            const int* __restrict__ lds_off,
+                                            const uint32_t* __restrict__ touch, double2* smem) {
+  constexpr int C = ncomp(P);
+  constexpr int NG = (C + 3) / 4;        // output column groups of 4
+  constexpr int ROUNDS = (C + 1) / 2;    // moment components staged two at a time
+  constexpr int TPW = 32 / WAVES;        // 16-cell tiles per wave
+  constexpr int NT = WAVES * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kk = lane >> 4;              // offset of the quad this lane feeds
+  const int ci = lane & 15;              // cell of the tile this lane feeds
+
+  // tile gt = wave*TPW + t: target plane gt/4, 4x4 patch ((gt&1)*4, ((gt>>1)&1)*4)
+  int abase[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int gt = wave * TPW + t;
+    const int z = gt >> 2, x = (gt & 1) * 4 + (ci & 3), y = ((gt >> 1) & 1) * 4 + (ci >> 2);
+    // window coordinates of the target cell: frame (x+8, y+8, z+8) minus 2
+    abase[t] = (x + 6) + kWin * (y + 6) + kWin * kWin * (z + 6);
+  }
+  const int zlo = (wave * TPW) >> 2, zhi = (wave * TPW + TPW - 1) >> 2;
+
+  double acc[TPW][NG];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) acc[t][g] = 0.0;
+
+  const int l2 = d.log2_inv_h;
+  const double* src = M + d.m_off;
+  for (int r = 0; r < ROUNDS; ++r) {
+    const int k0 = 2 * r, k1 = 2 * r + 1;
+    const double s0 = ldexp(1.0, l2 * order_of(k0));
+    const double s1 = k1 < C ? ldexp(1.0, l2 * order_of(k1)) : 0.0;
+    const double* src0 = src + (size_t)k0 * kNCell;
+    const double* src1 = src + (size_t)(k1 < C ? k1 : k0) * kNCell;
+    __syncthreads();   // previous round's reads of smem are done
+    for (int c = tid; c < kWinCells; c += NT) {
+      const int wx = c % kWin, wy = (c / kWin) % kWin, wz = c / (kWin * kWin);
+      const int jx = wx + kWin0, jy = wy + kWin0, jz = wz + kWin0;
+      const int cell = jx + kFrame * jy + kFrame * kFrame * jz;
+      double2 v = make_double2(0.0, 0.0);
+      if (block_present(d.mask, jx, jy, jz)) {
+        v.x = src0[cell] * s0;
+        v.y = src1[cell] * s1;
+      }
+      smem[c] = v;
+    }
+    __syncthreads();
+    const double* Br = Bp + (size_t)r * kQuads * 2 * NG * 16 + kk * 4 + (lane & 3);
+    for (int q = 0; q < kQuads; ++q) {
+      uint32_t tm = 0;
+      for (int z = zlo; z <= zhi; ++z) tm |= touch[z * kQuads + q];
+      if ((tm & d.mask) == 0) continue;   // every source of this quad is absent for this wave
+      const int doff = lds_off[4 * q + kk];
+      const double* Bq = Br + (size_t)q * 2 * NG * 16;
+      double b0[NG], b1[NG];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        b0[g] = Bq[g * 16];
+        b1[g] = Bq[(NG + g) * 16];
+      }
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const double2 a = smem[abase[t] + doff];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a.x, b0[g], acc[t][g]);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a.y, b1[g], acc[t][g]);
+      }
+    }
+  }
+
+  // D layout: this lane holds cell (x = lane/16, y = (lane%16)/4) of each tile, column lane%4
+  double* out = L + d.l_off;
+  const int xi = lane >> 4, yi = (lane & 15) >> 2, j = lane & 3;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int gt = wave * TPW + t;
+    const int z = gt >> 2, x = (gt & 1) * 4 + xi, y = ((gt >> 1) & 1) * 4 + yi;
+    const int tcell = x + kBlock * y + kBlock * kBlock * z;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int n = 4 * g + j;
+      if (n < C) out[(size_t)n * kNTarget + tcell] = ldexp(acc[t][g], l2 * (1 + order_of(n)));
+    }
+  }
+}
+
+template <int WAVES>
+__global__ void __launch_bounds__(WAVES * 64) m2l_fwd_kernel(
+    const WorkItem* __restrict__ items, int count, unsigned* __restrict__ counter,
+    const DevDesc* __restrict__ desc, const double* __restrict__ M, double* __restrict__ L,
+    const double* __restrict__ B2, const double* __restrict__ B3, const double* __restrict__ B4,
+    const int* __restrict__ lds_off, const uint32_t* __restrict__ touch) {
+  __shared__ double2 smem[kWinCells];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= count) break;
+    const DevDesc d = desc[items[item].sub];
+    switch (d.p) {
+      case 2: fwd_subgrid<2, WAVES>(d, M, L, B2, lds_off, touch, smem); break;
+      case 3: fwd_subgrid<3, WAVES>(d, M, L, B3, lds_off, touch, smem); break;
+      case 4: fwd_subgrid<4, WAVES>(d, M, L, B4, lds_off, touch, smem); break;
+      default: break;
+    }
+    __syncthreads();   // s_item and smem are free for the next item
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint: dM_k(s) = h^-|k| sum_e sum_n [h^(-1-|n|) dL_n(s + e)] T_e[n][k]
+// ---------------------------------------------------------------------------
+//
+// Targets are the 20^3 reachable window in 4x4x1 tiles (5 x 5 x 20 = 500
+// per sub-grid); sources are dL, staged whole in LDS ([C rounded to 4][512],
+// zero-padded components). The reduction is taken four source components at
+// a time for one offset; an offset is skipped for a tile when the shifted
+// tile misses the 8^3 block, and lanes whose shifted cell misses it read 0.
+
+constexpr int kBwdWaves = 8;
+constexpr int kBwdThreads = kBwdWaves * 64;
+constexpr int kBwdTilesPerGroup = 5;   // one row of 4x4 patches across the window
+constexpr int kBwdGroups = 5 * 20;     // rows x planes
+
+template <int P>
+__device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __restrict__ dL,
+                                            double* __restrict__ dM, const double* __restrict__ Bp,
+                                            const int* __restrict__ stencil, double* smem) {
+  constexpr int C = ncomp(P);
+  constexpr int KC = (C + 3) / 4;     // source component chunks of 4
+  constexpr int NG = (C + 3) / 4;     // output column groups of 4
+  constexpr int TPG = kBwdTilesPerGroup;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kk = lane >> 4, ci = lane & 15;
+  const int l2 = d.log2_inv_h;
+  double* out = dM + d.m_off;
+
+  // zero every cell this sub-grid does not compute: outside the window, absent blocks
+  for (int i = tid; i < KC * 4 * kNCell; i += kBwdThreads) {
+    const int k = i / kNCell, cell = i % kNCell;
+    if (k >= C) break;
+    const int jx = cell % kFrame, jy = (cell / kFrame) % kFrame, jz = cell / (kFrame * kFrame);
+    const bool win = jx >= kWin0 && jx < kWin0 + kWin && jy >= kWin0 && jy < kWin0 + kWin &&
+                     jz >= kWin0 && jz < kWin0 + kWin;
+    if (!win || !block_present(d.mask, jx, jy, jz)) out[(size_t)k * kNCell + cell] = 0.0;
+  }
+  // stage dL scaled by h^(-1-|n|); components beyond C are zero
+  const double* src = dL + d.l_off;
+  for (int i = tid; i < KC * 4 * kNTarget; i += kBwdThreads) {
+    const int n = i / kNTarget;
+    smem[i] = n < C ? ldexp(src[i], l2 * (1 + order_of(n))) : 0.0;
+  }
+  __syncthreads();
+
+  for (int grp = wave; grp < kBwdGroups; grp += kBwdWaves) {
+    const int z = grp / 5 + kWin0;         // frame plane
+    const int y0 = (grp % 5) * 4 + kWin0;  // frame row of the 4x4 patches
+    // skip groups whose cells all lie in absent blocks
+    bool any = false;
+#pragma unroll
+    for (int t = 0; t < TPG; ++t) {
+      const int x0 = t * 4 + kWin0;
+      for (int c = 0; c < 16; ++c) any |= block_present(d.mask, x0 + (c & 3), y0 + (c >> 2), z);
+    }
+    if (!any) continue;
+    double acc[TPG][NG];
+#pragma unroll
+    for (int t = 0; t < TPG; ++t)
+#pragma unroll
+      for (int g = 0; g < NG; ++g) acc[t][g] = 0.0;
+    for (int e = 0; e < kNStencil; ++e) {
+      const int ex = stencil[3 * e], ey = stencil[3 * e + 1], ez = stencil[3 * e + 2];
+      const int tz = z + ez - kBlock;
+      if ((unsigned)tz >= (unsigned)kBlock) continue;
+      const int ylo = y0 + ey - kBlock;   // target-block y of the patch's first row
+      if (ylo > kBlock - 1 || ylo + 3 < 0) continue;
+      const int ty = ylo + (ci >> 2);
+      const bool yok = (unsigned)ty < (unsigned)kBlock;
+      bool active[TPG];
+      int tcell[TPG];
+      bool ok[TPG];
+      bool any_active = false;
+#pragma unroll
+      for (int t = 0; t < TPG; ++t) {
+        const int xlo = t * 4 + kWin0 + ex - kBlock;
+        active[t] = !(xlo > kBlock - 1 || xlo + 3 < 0);
+        any_active |= active[t];
+        const int tx = xlo + (ci & 3);
+        ok[t] = active[t] && yok && (unsigned)tx < (unsigned)kBlock;
+        tcell[t] = ok[t] ? tx + kBlock * ty + kBlock * kBlock * tz : 0;
+      }
+      if (!any_active) continue;
+      const double* Be = Bp + (size_t)e * KC * NG * 16 + kk * 4 + (lane & 3);
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        double b[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) b[g] = Be[(kc * NG + g) * 16];
+        const double* sm = smem + (4 * kc + kk) * kNTarget;
+#pragma unroll
+        for (int t = 0; t < TPG; ++t) {
+          if (!active[t]) continue;
+          const double v = sm[tcell[t]];
+          const double a = ok[t] ? v : 0.0;
+#pragma unroll
+          for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a, b[g], acc[t][g]);
+        }
+      }
+    }
+    const int xi = lane >> 4, yi = (lane & 15) >> 2, j = lane & 3;
+#pragma unroll
+    for (int t = 0; t < TPG; ++t) {
+      const int x = t * 4 + kWin0 + xi, y = y0 + yi;
+      const bool pres = block_present(d.mask, x, y, z);
+      const int cell = x + kFrame * y + kFrame * kFrame * z;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const int k = 4 * g + j;
+        if (k < C) out[(size_t)k * kNCell + cell] = pres ? ldexp(acc[t][g], l2 * order_of(k)) : 0.0;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBwdThreads) m2l_bwd_kernel(
+    const WorkItem* __restrict__ items, int count, unsigned* __restrict__ counter,
+    const DevDesc* __restrict__ desc, const double* __restrict__ dL, double* __restrict__ dM,
+    const double* __restrict__ B2, const double* __restrict__ B3, const double* __restrict__ B4,
+    const int* __restrict__ stencil) {
+  __shared__ double smem[36 * kNTarget];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= count) break;
+    const DevDesc d = desc[items[item].sub];
+    switch (d.p) {
+      case 2: bwd_subgrid<2>(d, dL, dM, B2, stencil, smem); break;
+      case 3: bwd_subgrid<3>(d, dL, dM, B3, stencil, smem); break;
+      case 4: bwd_subgrid<4>(d, dL, dM, B4, stencil, smem); break;
+      default: break;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// table packing
+// ---------------------------------------------------------------------------
+
+// forward: [r][q][c][g][kk*4 + j] = T_{4q+kk}[2r+c][4g+j]
+__global__ void pack_fwd_kernel(const double* __restrict__ T, int p, double* __restrict__ out,
+                                float* __restrict__ hi, float* __restrict__ lo) {
+  const int C = ncomp(p), NG = (C + 3) / 4, ROUNDS = (C + 1) / 2;
+  const int total = ROUNDS * kQuads * 2 * NG * 16;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int j = i & 3, kk = (i >> 2) & 3;
+  int rest = i >> 4;
+  const int g = rest % NG; rest /= NG;
+  const int c = rest % 2; rest /= 2;
+  const int q = rest % kQuads;
+  const int r = rest / kQuads;
+  const int k = 2 * r + c, n = 4 * g + j, s = 4 * q + kk;
+  const double v = (k < C && n < C) ? T[((size_t)s * C + k) * C + n] : 0.0;
+  out[i] = v;
+  const float h = (float)v;
+  hi[i] = h;
+  lo[i] = (float)(v - (double)h);
+}
+
+// adjoint: [e][kc][g][kk*4 + j] = T_e[4kc+kk][4g+j]
+__global__ void pack_bwd_kernel(const double* __restrict__ T, int p, double* __restrict__ out) {
+  const int C = ncomp(p), NG = (C + 3) / 4, KC = NG;
+  const int total = kNStencil * KC * NG * 16;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int j = i & 3, kk = (i >> 2) & 3;
+  int rest = i >> 4;
+  const int g = rest % NG; rest /= NG;
+  const int kc = rest % KC;
+  const int e = rest / KC;
+  const int n = 4 * kc + kk, k = 4 * g + j;
+  out[i] = (n < C && k < C) ? T[((size_t)e * C + n) * C + k] : 0.0;
+}
+
+size_t fwd_pack_elems(int p) {
+  const int C = ncomp(p), NG = (C + 3) / 4, ROUNDS = (C + 1) / 2;
+  return (size_t)ROUNDS * kQuads * 2 * NG * 16;
+}
+
+size_t bwd_pack_elems(int p) {
+  const int C = ncomp(p), NG = (C + 3) / 4;
+  return (size_t)kNStencil * NG * NG * 16;
+}
+
+int64_t block_pair_count(uint32_t mask, const std::vector<int>& st) {
+  static int64_t per_block[27] = {-1};
+  if (per_block[0] < 0) {
+    int64_t v[27] = {};
+    for (int t = 0; t < kNTarget; ++t) {
+      const int jx = t % 8 + 8, jy = (t / 8) % 8 + 8, jz = t / 64 + 8;
+      for (size_t i = 0; i < st.size(); i += 3)
+        v[(jx + st[i]) / 8 + 3 * ((jy + st[i + 1]) / 8) + 9 * ((jz + st[i + 2]) / 8)]++;
+    }
+    for (int b = 0; b < 27; ++b) per_block[b] = v[b];
+  }
+  int64_t n = 0;
+  for (int b = 0; b < 27; ++b)
+    if ((mask >> b) & 1u) n += per_block[b];
+  return n;
+}
+
+std::vector<int> host_stencil() {
+  std::vector<int> s;
+  for (int dz = -kRad; dz <= kRad; ++dz)
+    for (int dy = -kRad; dy <= kRad; ++dy)
+      for (int dx = -kRad; dx <= kRad; ++dx) {
+        const int q = dx * dx + dy * dy + dz * dz;
+        if (q >= 5 && q <= 36) {
+          s.push_back(dx);
+          s.push_back(dy);
+          s.push_back(dz);
+        }
+      }
+  return s;
+}
+
+// Configurations: forward waves per workgroup (tiles per wave = 32 / waves).
+struct Config {
+  int waves;
+  fmm_precision prec;
+};
+constexpr Config kConfigs[] = {{8, FMM_FP64}, {4, FMM_FP64}};
+constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
+
+}  // namespace
+
+std::vector<WorkItem> build_work_list(const fmm_subgrid* desc, int64_t nsub) {
+  static const std::vector<int> st = host_stencil();
+  std::vector<WorkItem> items((size_t)nsub);
+  for (int64_t b = 0; b < nsub; ++b) {
+    const int C = ncomp(desc[b].p);
+    const int64_t pairs = block_pair_count(desc[b].mask, st);
+    items[b].sub = (int32_t)b;
+    items[b].cost = (int32_t)((int64_t)C * C * pairs / 4096);
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [](const WorkItem& a, const WorkItem& b) { return a.cost > b.cost; });
+  return items;
+}
+
+hipError_t mfma_tables_create(MfmaTables* t, double* const* d_T, const int* d_stencil,
+                              hipStream_t s) {
+  hipError_t e;
+  t->stencil = d_stencil;
+  int dev = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&t->num_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  for (int p = 2; p <= kMaxP; ++p) {
+    const size_t nf = fwd_pack_elems(p), nb = bwd_pack_elems(p);
+    if ((e = hipMalloc(&t->fwd[p], nf * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc(&t->fwd_hi[p], nf * sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMalloc(&t->fwd_lo[p], nf * sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMalloc(&t->bwd[p], nb * sizeof(double))) != hipSuccess) return e;
+    hipLaunchKernelGGL(pack_fwd_kernel, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s, d_T[p], p,
+                       t->fwd[p], t->fwd_hi[p], t->fwd_lo[p]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(pack_bwd_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, d_T[p], p,
+                       t->bwd[p]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // LDS offsets of the offsets and the blocks each quad touches per target plane
+  const std::vector<int> st = host_stencil();
+  std::vector<int> off(kNStencil);
+  for (int i = 0; i < kNStencil; ++i) off[i] = st[3 * i] + kWin * st[3 * i + 1] + kWin * kWin * st[3 * i + 2];
+  std::vector<uint32_t> touch(8 * kQuads, 0u);
+  for (int z = 0; z < 8; ++z)
+    for (int q = 0; q < kQuads; ++q) {
+      uint32_t m = 0;
+      for (int o = 4 * q; o < 4 * q + 4; ++o) {
+        const int dx = st[3 * o], dy = st[3 * o + 1], dz = st[3 * o + 2];
+        const int bz = (8 + z + dz) / 8;
+        for (int bx = (8 + dx) / 8; bx <= (15 + dx) / 8; ++bx)
+          for (int by = (8 + dy) / 8; by <= (15 + dy) / 8; ++by) m |= 1u << (bx + 3 * by + 9 * bz);
+      }
+      touch[z * kQuads + q] = m;
+    }
+  if ((e = hipMalloc(&t->lds_off, off.size() * sizeof(int))) != hipSuccess) return e;
+  if ((e = hipMalloc(&t->touch, touch.size() * sizeof(uint32_t))) != hipSuccess) return e;
+  // synchronous copies: the host vectors die at return
+  if ((e = hipMemcpy(t->lds_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMemcpy(t->touch, touch.data(), touch.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+void mfma_tables_destroy(MfmaTables* t) {
+  for (int p = 0; p <= kMaxP; ++p) {
+    if (t->fwd[p]) (void)hipFree(t->fwd[p]);
+    if (t->fwd_hi[p]) (void)hipFree(t->fwd_hi[p]);
+    if (t->fwd_lo[p]) (void)hipFree(t->fwd_lo[p]);
+    if (t->bwd[p]) (void)hipFree(t->bwd[p]);
+    t->fwd[p] = t->bwd[p] = nullptr;
+    t->fwd_hi[p] = t->fwd_lo[p] = nullptr;
+  }
+  if (t->lds_off) (void)hipFree(t->lds_off);
+  if (t->touch) (void)hipFree(t->touch);
+  t->lds_off = nullptr;
+  t->touch = nullptr;
+}
+
+int mfma_num_configs() { return kNumConfigs; }
+
+bool mfma_config_supports(int cfg, fmm_precision prec) {
+  return cfg >= 0 && cfg < kNumConfigs && kConfigs[cfg].prec == prec;
+}
+
+int mfma_default_config(fmm_precision prec) {
+  for (int c = 0; c < kNumConfigs; ++c)
+    if (kConfigs[c].prec == prec) return c;
+  return 0;
+}
+
+hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc* d_desc,
+                           const double* M, double* L, fmm_precision prec, int cfg,
+                           hipStream_t s) {
+  if (w.count == 0) return hipSuccess;
+  if (!mfma_config_supports(cfg, prec)) return hipErrorInvalidValue;
+  const int grid = std::min(t.num_cu, w.count);
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, w.counter);
+  switch (kConfigs[cfg].waves) {
+    case 8:
+      hipLaunchKernelGGL(m2l_fwd_kernel<8>, dim3(grid), dim3(512), 0, s, w.items, w.count, w.counter,
+                         d_desc, M, L, t.fwd[2], t.fwd[3], t.fwd[4], t.lds_off, t.touch);
+      break;
+    case 4:
+      hipLaunchKernelGGL(m2l_fwd_kernel<4>, dim3(grid), dim3(256), 0, s, w.items, w.count, w.counter,
+                         d_desc, M, L, t.fwd[2], t.fwd[3], t.fwd[4], t.lds_off, t.touch);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_m2l_mfma_backward(const MfmaTables& t, const WorkList& w, const DevDesc* d_desc,
+                                    const double* dL, double* dM, hipStream_t s) {
+  if (w.count == 0) return hipSuccess;
+  const int grid = std::min(t.num_cu, w.count);
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, w.counter);
+  hipLaunchKernelGGL(m2l_bwd_kernel, dim3(grid), dim3(kBwdThreads), 0, s, w.items, w.count, w.counter,
+                     d_desc, dL, dM, t.bwd[2], t.bwd[3], t.bwd[4], t.stencil);
+  return hipGetLastError();
+}
+
+}  // namespace fmm

@@ -1,0 +1,224 @@
+"""Thin Python binding of libfmm.so (ctypes): argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels; torch is
+used for device memory and streams. There is no CPU fallback: if the shared
+library is missing, loading it raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfmm.so")
+
+FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_EUNSUPPORTED = 0, -1, -2, -3, -4
+FMM_FP64, FMM_SPLIT_FP32 = 0, 1
+FMM_OPT_M2L_KERNEL, FMM_OPT_USE_GRAPH, FMM_OPT_TILE_CONFIG = 1, 2, 3
+
+FRAME, NCELL, NTARGET = 24, 24 ** 3, 512
+FULL_MASK = (1 << 27) - 1
+
+EXPORTS = [
+    "fmm_create", "fmm_destroy", "fmm_status_string", "fmm_last_error", "fmm_set_option",
+    "fmm_stencil", "fmm_pair_count", "fmm_p2m", "fmm_m2l", "fmm_m2l_backward",
+    "fmm_p2m_backward", "fmm_stencil_tables", "fmm_autotune",
+]
+
+DESC_DTYPE = np.dtype([("p", "<i4"), ("log2_inv_h", "<i4"), ("mask", "<u4"), ("reserved", "<i4"),
+                       ("m_off", "<i8"), ("l_off", "<i8"), ("part_off", "<i8")])
+assert DESC_DTYPE.itemsize == 40
+
+
+class FMMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (status_string(status), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libfmm.so once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libfmm.so not found at %s: build it with "
+                          "`python -m paper_2304_11002_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "fmm_create": ([ctypes.POINTER(vp), i32], i32),
+        "fmm_destroy": ([vp], i32),
+        "fmm_status_string": ([i32], ctypes.c_char_p),
+        "fmm_last_error": ([vp], ctypes.c_char_p),
+        "fmm_set_option": ([vp, i32, i64], i32),
+        "fmm_stencil": ([ctypes.POINTER(i32), vp], i32),
+        "fmm_pair_count": ([vp, i64, ctypes.POINTER(i64)], i32),
+        "fmm_p2m": ([vp, vp, i64, vp, vp, i32, vp, vp], i32),
+        "fmm_m2l": ([vp, vp, i64, vp, vp, i32, vp], i32),
+        "fmm_m2l_backward": ([vp, vp, i64, vp, vp, vp], i32),
+        "fmm_p2m_backward": ([vp, vp, i64, vp, i32, vp, vp, vp], i32),
+        "fmm_stencil_tables": ([vp, i32, vp, vp], i32),
+        "fmm_autotune": ([vp, vp, i64, vp, vp, i32, vp, ctypes.POINTER(i32)], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def status_string(status):
+    return load_library().fmm_status_string(status).decode()
+
+
+def _desc_ptr(desc):
+    if desc is None or len(desc) == 0:
+        return None, 0
+    if not isinstance(desc, np.ndarray) or desc.dtype != DESC_DTYPE or not desc.flags.c_contiguous:
+        raise TypeError("descriptors must be a C-contiguous numpy array of DESC_DTYPE")
+    return desc.ctypes.data, len(desc)
+
+
+def _ptr(t):
+    """Device (or host) address of a tensor, or of None."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def stencil():
+    """The 892 stencil offsets (dx, dy, dz) in the library's order."""
+    lib = load_library()
+    n = ctypes.c_int32()
+    _check(lib.fmm_stencil(ctypes.byref(n), None), None)
+    out = np.zeros((n.value, 3), np.int32)
+    _check(lib.fmm_stencil(ctypes.byref(n), out.ctypes.data), None)
+    return out
+
+
+def pair_count(desc):
+    lib = load_library()
+    pd, n = _desc_ptr(desc)
+    out = ctypes.c_int64()
+    _check(lib.fmm_pair_count(pd, n, ctypes.byref(out)), None)
+    return out.value
+
+
+def _check(status, ctx_handle):
+    if status != FMM_OK:
+        msg = load_library().fmm_last_error(ctx_handle).decode()
+        raise FMMError(status, msg)
+
+
+def ncomp(p):
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def make_descriptors(p, log2_inv_h, mask, ppc=8):
+    """Descriptors with packed, ragged M/L offsets and particle offsets.
+
+    Returns (desc, m_elems, l_elems): total float64 elements of M and L.
+    """
+    p = np.asarray(p, np.int32)
+    B = len(p)
+    desc = np.zeros(B, DESC_DTYPE)
+    desc["p"] = p
+    desc["log2_inv_h"] = np.asarray(log2_inv_h, np.int32)
+    desc["mask"] = np.asarray(mask, np.uint32)
+    C = (p.astype(np.int64) + 1) * (p + 2) * (p + 3) // 6
+    m_sz, l_sz = C * NCELL, C * NTARGET
+    desc["m_off"] = np.concatenate([[0], np.cumsum(m_sz)[:-1]]) if B else []
+    desc["l_off"] = np.concatenate([[0], np.cumsum(l_sz)[:-1]]) if B else []
+    desc["part_off"] = np.arange(B, dtype=np.int64) * NCELL * ppc
+    return desc, int(m_sz.sum()), int(l_sz.sum())
+
+
+class Context:
+    """One library context on one device (device=-1: host-only, checks only)."""
+
+    def __init__(self, device=0):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        st = self.lib.fmm_create(ctypes.byref(h), int(device))
+        if st != FMM_OK:
+            raise FMMError(st, self.lib.fmm_last_error(None).decode())
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            self.lib.fmm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _s(self, stream, n):
+        # a host-only context never reaches a stream; empty batches need none
+        if self.device < 0 or not n:
+            return None
+        return _stream(stream)
+
+    def last_error(self):
+        return self.lib.fmm_last_error(self.handle).decode()
+
+    def _run(self, status):
+        _check(status, self.handle)
+
+    def set_option(self, option, value):
+        self._run(self.lib.fmm_set_option(self.handle, option, int(value)))
+
+    def p2m(self, desc, pos, mass, ppc, M, stream=None):
+        pd, n = _desc_ptr(desc)
+        self._run(self.lib.fmm_p2m(self.handle, pd, n, _ptr(pos), _ptr(mass), int(ppc), _ptr(M),
+                                   self._s(stream, n)))
+
+    def m2l(self, desc, M, L, precision=FMM_FP64, stream=None):
+        pd, n = _desc_ptr(desc)
+        self._run(self.lib.fmm_m2l(self.handle, pd, n, _ptr(M), _ptr(L), int(precision),
+                                   self._s(stream, n)))
+
+    def m2l_backward(self, desc, dL, dM, stream=None):
+        pd, n = _desc_ptr(desc)
+        self._run(self.lib.fmm_m2l_backward(self.handle, pd, n, _ptr(dL), _ptr(dM),
+                                            self._s(stream, n)))
+
+    def p2m_backward(self, desc, pos, ppc, dM, dmass, stream=None):
+        pd, n = _desc_ptr(desc)
+        self._run(self.lib.fmm_p2m_backward(self.handle, pd, n, _ptr(pos), int(ppc), _ptr(dM),
+                                            _ptr(dmass), self._s(stream, n)))
+
+    def stencil_tables(self, p, out, stream=None):
+        self._run(self.lib.fmm_stencil_tables(self.handle, int(p), _ptr(out), self._s(stream, 1)))
+
+    def autotune(self, desc, M, L, precision=FMM_FP64, stream=None):
+        pd, n = _desc_ptr(desc)
+        chosen = ctypes.c_int32(-1)
+        self._run(self.lib.fmm_autotune(self.handle, pd, n, _ptr(M), _ptr(L), int(precision),
+                                        self._s(stream, n), ctypes.byref(chosen)))
+        return chosen.value

@@ -1,0 +1,129 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments on the host (through a host-only
+context, device = -1) before any HIP call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from paper_2304_11002_amd import fmm
+
+from _gpu_helpers import ensure_library
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "fmm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return ensure_library()
+
+
+@pytest.fixture
+def hctx(lib):
+    c = fmm.Context(device=-1)
+    yield c
+    c.close()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w]+\s*\*?\s*(fmm_\w+)\s*\(", text, re.M)))
+
+
+def test_header_symbols_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(fmm.EXPORTS)
+
+
+def test_status_strings(lib):
+    for s in (0, -1, -2, -3, -4):
+        assert fmm.status_string(s).startswith("FMM_")
+    assert "unknown" in fmm.status_string(7)
+
+
+def test_stencil_matches_oracle(lib):
+    st = fmm.stencil()
+    assert st.shape == (892, 3)
+    assert [tuple(x) for x in st] == O.stencil()
+
+
+def test_pair_count_matches_oracle(lib):
+    rng = np.random.default_rng(5)
+    masks = [synth.FULL_MASK, 1 << 13] + [synth.random_mask(rng) for _ in range(6)]
+    desc, _, _ = fmm.make_descriptors([3] * len(masks), [0] * len(masks), masks)
+    assert fmm.pair_count(desc) == sum(O.pair_count(m) for m in masks)
+    assert fmm.pair_count(desc[:0]) == 0
+
+
+def _bad(desc, field, value):
+    d = desc.copy()
+    d[field][0] = value
+    return d
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("p", 1, "p ="), ("p", 5, "p ="), ("log2_inv_h", 3, "log2_inv_h"), ("log2_inv_h", -1, "log2_inv_h"),
+    ("mask", synth.FULL_MASK & ~(1 << 13), "mask"), ("mask", 1 << 27 | 1 << 13, "mask"),
+    ("reserved", 1, "reserved"), ("m_off", -8, "negative"), ("l_off", -1, "negative"),
+])
+def test_descriptor_validation(hctx, field, value, msg):
+    desc, _, _ = fmm.make_descriptors([3, 3], [0, 0], [synth.FULL_MASK] * 2)
+    bad = _bad(desc, field, value)
+    with pytest.raises(fmm.FMMError) as e:
+        hctx.m2l(bad, 8, 8)
+    assert e.value.status == fmm.FMM_EINVAL
+    assert msg in str(e.value)
+
+
+def test_pointer_and_option_validation(hctx):
+    desc, _, _ = fmm.make_descriptors([3], [0], [synth.FULL_MASK])
+    for call in (lambda: hctx.m2l(desc, 0, 8), lambda: hctx.m2l(desc, 8, 0),
+                 lambda: hctx.m2l(desc, 12, 8),                       # misaligned
+                 lambda: hctx.p2m(desc, 8, 8, 0, 8),                  # ppc = 0
+                 lambda: hctx.p2m(desc, 8, 8, 65, 8),
+                 lambda: hctx.p2m(desc, 0, 8, 8, 8),
+                 lambda: hctx.m2l_backward(desc, 8, 0),
+                 lambda: hctx.p2m_backward(desc, 8, 8, 0, 8),
+                 lambda: hctx.m2l(desc, 8, 8, precision=7),
+                 lambda: hctx.set_option(fmm.FMM_OPT_M2L_KERNEL, 3),
+                 lambda: hctx.set_option(fmm.FMM_OPT_USE_GRAPH, 2),
+                 lambda: hctx.set_option(99, 0),
+                 lambda: hctx.stencil_tables(5, 8)):
+        with pytest.raises(fmm.FMMError) as e:
+            call()
+        assert e.value.status == fmm.FMM_EINVAL
+
+
+def test_host_only_context_reports_unsupported_after_checks(hctx, lib):
+    desc, _, _ = fmm.make_descriptors([2, 3, 4], [0, 1, 2], [synth.FULL_MASK] * 3)
+    with pytest.raises(fmm.FMMError) as e:
+        hctx.m2l(desc, 8, 8)
+    assert e.value.status == fmm.FMM_EUNSUPPORTED
+    # empty batches are valid no-ops only after the host-only check
+    n = ctypes.c_int64(0)
+    assert lib.fmm_m2l(hctx.handle, None, 0, None, None, 0, None) == fmm.FMM_EUNSUPPORTED
+    assert lib.fmm_m2l(hctx.handle, None, -1, None, None, 0, None) == fmm.FMM_EINVAL
+    assert lib.fmm_pair_count(None, 0, ctypes.byref(n)) == 0 and n.value == 0
+
+
+def test_null_context_and_create_errors(lib):
+    assert lib.fmm_m2l(None, None, 0, None, None, 0, None) == fmm.FMM_EINVAL
+    assert lib.fmm_destroy(None) == fmm.FMM_OK
+    h = ctypes.c_void_p()
+    assert lib.fmm_create(ctypes.byref(h), -2) == fmm.FMM_EINVAL
+    assert lib.fmm_create(None, 0) == fmm.FMM_EINVAL
+
+
+def test_descriptor_layout():
+    desc, m_el, l_el = fmm.make_descriptors([2, 3, 4], [0, 1, 2], [synth.FULL_MASK] * 3)
+    assert list(desc["m_off"]) == [0, 10 * 13824, 30 * 13824]
+    assert list(desc["l_off"]) == [0, 10 * 512, 30 * 512]
+    assert m_el == 65 * 13824 and l_el == 65 * 512
+    assert list(desc["part_off"]) == [0, 13824 * 8, 2 * 13824 * 8]

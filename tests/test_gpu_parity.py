@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerance (float64 paths): per entry |x_gpu - x_oracle| <= 1e-12 * x_abs,
+where x_abs is the same sum taken over absolute values (Labs for L, Gabs
+for dM). Relative-to-|L| tolerances would fail correct code, because
+orders >= 1 cancel heavily.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from paper_2304_11002_amd import fmm
+
+from _gpu_helpers import (descriptors, ensure_library, moment_abs_scale, oracle_subgrid,
+                          particles, split_views, to_dev)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+REF, MFMA = 1, 2
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    ensure_library()
+    c = fmm.Context(0)
+    yield c
+    c.close()
+
+
+def forward(ctx, torch, w, idx, kernel, prec=fmm.FMM_FP64, poison=False, graph=1):
+    desc, m_el, l_el = descriptors(w, idx)
+    pos, mass = particles(w, idx)
+    dpos, dmass = to_dev(pos), to_dev(mass)
+    M = torch.empty(m_el, dtype=torch.float64, device="cuda")
+    L = torch.full((l_el,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.p2m(desc, dpos, dmass, w.ppc, M)
+    if poison:
+        Mh = M.cpu().numpy()
+        for d, v in zip(desc, split_views(Mh, desc, "M")):
+            v[:, ~O.present_cells(int(d["mask"]))] = np.nan
+        M = to_dev(Mh)
+    ctx.set_option(fmm.FMM_OPT_M2L_KERNEL, kernel)
+    ctx.set_option(fmm.FMM_OPT_USE_GRAPH, graph)
+    ctx.m2l(desc, M, L, prec)
+    torch.cuda.synchronize()
+    return desc, pos, mass, M, L
+
+
+def assert_close(got, want, scale, tol=TOL, what=""):
+    err = np.abs(got - want)
+    bad = ~(err <= tol * scale)
+    assert not bad.any(), "%s: %d entries off, worst ratio %.3g" % (
+        what, bad.sum(), np.nanmax(err / np.maximum(scale, 1e-300)))
+
+
+# ---------------------------------------------------------------------------
+
+def _order_scale(T, p):
+    ks = O.multi_indices(p)
+    order = np.array([sum(k) for k in ks])
+    tot = order[:, None] + order[None, :]
+    scale = np.zeros_like(T)
+    for m in range(2 * p + 1):
+        sel = tot == m
+        scale[:, sel] = np.abs(T[:, sel]).max(axis=1, keepdims=True)
+    return scale
+
+
+def test_stencil_tables_match_exact_and_oracle(ctx, torch):
+    from oracle.exact import dtensor_exact
+    eps = np.finfo(float).eps
+    S = O.stencil()
+    for p in (2, 3, 4):
+        C = fmm.ncomp(p)
+        out = torch.empty(892 * C * C, dtype=torch.float64, device="cuda")
+        ctx.stencil_tables(p, out)
+        torch.cuda.synchronize()
+        T = out.cpu().numpy().reshape(892, C, C)
+        To = O.stencil_tensors(p, 1.0)
+        # both sides round (alternating sums at order 2p): ~150 ulp of the order scale each
+        assert_close(T, To, _order_scale(To, p), 512 * eps, "T p=%d vs closed form" % p)
+        # transposition symmetry T_{-d} = T_d^T holds exactly on the device tables
+        idx = {d: i for i, d in enumerate(S)}
+        for i in range(0, 892, 37):
+            a, b, c = S[i]
+            assert np.array_equal(T[idx[(-a, -b, -c)]], T[i].T)
+    # p = 4 holds every derivative up to order 8: pin it to exact values at sampled offsets
+    ks = O.multi_indices(4)
+    sample = list(range(0, 892, 11))
+    Te = np.empty((len(sample), 35, 35))
+    for si, s in enumerate(sample):
+        R = tuple(-v for v in S[s])
+        cache = {}
+        for ik, k in enumerate(ks):
+            for jn, n in enumerate(ks):
+                m = (k[0] + n[0], k[1] + n[1], k[2] + n[2])
+                if m not in cache:
+                    cache[m] = dtensor_exact(m, R)
+                Te[si, ik, jn] = (-1) ** sum(k) * cache[m]
+    assert_close(T[sample], Te, _order_scale(Te, 4), 256 * eps, "T p=4 vs exact")
+
+
+def test_p2m_single_subgrid(ctx, torch):
+    w = synth.config(1)
+    desc, pos, mass, M, L = forward(ctx, torch, w, [0], MFMA)
+    Mo = O.p2m(pos[0], mass[0], 3, 1.0)
+    scale = moment_abs_scale(pos[0], mass[0], 3, 1.0, synth.FULL_MASK)
+    assert_close(M.cpu().numpy().reshape(Mo.shape), Mo, scale, 1e-14, "M")
+
+
+@pytest.mark.parametrize("kernel", [REF, MFMA])
+def test_m2l_single_subgrid(ctx, torch, kernel):
+    w = synth.config(1)
+    desc, pos, mass, M, L = forward(ctx, torch, w, [0], kernel)
+    _, Lo, La = oracle_subgrid(w, 0, pos[0], mass[0])
+    Lg = L.cpu().numpy().reshape(Lo.shape)
+    assert_close(Lg, Lo, La, TOL, "L kernel %d" % kernel)
+    assert 2600 < Lg[0].min() and Lg[0].max() < 2800
+
+
+@pytest.mark.parametrize("kernel", [REF, MFMA])
+def test_m2l_uneven_batch_with_poisoned_absent_blocks(ctx, torch, kernel):
+    # mixed p, h and random masks; absent blocks hold NaN and must never be read
+    w = synth.config(3, nsub=9)
+    idx = list(range(9))
+    desc, pos, mass, M, L = forward(ctx, torch, w, idx, kernel, poison=True)
+    Lg = split_views(L.cpu().numpy(), desc, "L")
+    assert sorted(set(w.p.tolist())) == [2, 3, 4] and len(set(w.log2_inv_h.tolist())) > 1
+    for b in idx:
+        _, Lo, La = oracle_subgrid(w, b, pos[b], mass[b])
+        assert_close(Lg[b], Lo, La, TOL, "sub-grid %d (p=%d, h=%g)" % (b, w.p[b], w.h(b)))
+
+
+def test_edge_cases(ctx, torch):
+    # empty batch, centre block only, and the largest order at the smallest spacing
+    ctx.m2l(np.zeros(0, fmm.DESC_DTYPE), None, None)
+    w = synth.Workload("edge", 17, np.array([4, 3, 2], np.int32), np.array([2, 0, 1], np.int32),
+                       np.array([1 << 13, synth.FULL_MASK, (1 << 13) | (1 << 0) | (1 << 26)], np.uint32))
+    for kernel in (REF, MFMA):
+        desc, pos, mass, M, L = forward(ctx, torch, w, [0, 1, 2], kernel, poison=True)
+        Lg = split_views(L.cpu().numpy(), desc, "L")
+        for b in range(3):
+            _, Lo, La = oracle_subgrid(w, b, pos[b], mass[b])
+            assert_close(Lg[b], Lo, La, TOL, "edge %d kernel %d" % (b, kernel))
+
+
+def test_determinism_and_slot_independence(ctx, torch):
+    w = synth.config(3, nsub=6)
+    _, _, _, M, L1 = forward(ctx, torch, w, range(6), MFMA)
+    desc, _, _ = descriptors(w, range(6))
+    L2 = torch.full_like(L1, float("nan"))
+    ctx.m2l(desc, M, L2)
+    torch.cuda.synchronize()
+    assert torch.equal(L1, L2)
+    # the same sub-grid in another slot of a differently ordered batch
+    order = [5, 2, 0, 4, 1, 3]
+    desc_r, m_el, l_el = descriptors(w, order)
+    Mv = split_views(M.cpu().numpy(), desc, "M")
+    Mr = np.concatenate([Mv[b].ravel() for b in order])
+    Lr = torch.full((l_el,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.m2l(desc_r, to_dev(Mr), Lr)
+    torch.cuda.synchronize()
+    a = split_views(L1.cpu().numpy(), desc, "L")
+    bb = split_views(Lr.cpu().numpy(), desc_r, "L")
+    for i, b in enumerate(order):
+        assert np.array_equal(a[b], bb[i])
+
+
+def test_graph_replays_match_plain_launches(ctx, torch):
+    w = synth.config(3, nsub=5)
+    _, _, _, M, L_plain = forward(ctx, torch, w, range(5), MFMA, graph=0)
+    desc, _, _ = descriptors(w, range(5))
+    ctx.set_option(fmm.FMM_OPT_USE_GRAPH, 1)
+    for rep in range(4):
+        L = torch.full_like(L_plain, float("nan"))
+        ctx.m2l(desc, M, L)
+        x = torch.ones(1000, device="cuda").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(L, L_plain), rep
+        assert x.item() == 1000
+
+
+@pytest.mark.parametrize("kernel", [REF, MFMA])
+def test_backward_matches_oracle_adjoint(ctx, torch, kernel):
+    w = synth.config(3, nsub=6)
+    idx = list(range(6))
+    desc, m_el, l_el = descriptors(w, idx)
+    pos, mass = particles(w, idx)
+    rng = np.random.default_rng(77)
+    W = rng.standard_normal(l_el)
+    dM = torch.full((m_el,), float("nan"), dtype=torch.float64, device="cuda")
+    dmass = torch.full((len(idx) * fmm.NCELL * 8,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.set_option(fmm.FMM_OPT_M2L_KERNEL, kernel)
+    ctx.m2l_backward(desc, to_dev(W), dM)
+    ctx.p2m_backward(desc, to_dev(pos), 8, dM, dmass)
+    torch.cuda.synchronize()
+    Gg = split_views(dM.cpu().numpy(), desc, "M")
+    Wv = split_views(W, desc, "L")
+    gm = dmass.cpu().numpy().reshape(len(idx), fmm.NCELL, 8)
+    for b in idx:
+        p, h, mask = int(w.p[b]), w.h(b), int(w.mask[b])
+        Go = O.m2l_adjoint(Wv[b], p, h, mask)
+        Ga = O.m2l_adjoint_abs(Wv[b], p, h, mask)
+        assert_close(Gg[b], Go, Ga, TOL, "dM sub-grid %d kernel %d" % (b, kernel))
+        go = O.p2m_adjoint(pos[b], Go, p, h, mask)
+        c = O.cell_centres(h)[:, None, :]
+        gscale = O.p2m_adjoint(c + np.abs(pos[b] - c), Ga, p, h, mask)
+        assert_close(gm[b], go, gscale, TOL, "dmass sub-grid %d" % b)
+
+
+def test_adjoint_dot_product_on_device(ctx, torch):
+    w = synth.config(3, nsub=4)
+    desc, pos, mass, M, L = forward(ctx, torch, w, range(4), MFMA)
+    rng = np.random.default_rng(3)
+    W = rng.standard_normal(L.numel())
+    dM = torch.empty_like(M)
+    ctx.m2l_backward(desc, to_dev(W), dM)
+    torch.cuda.synchronize()
+    lhs = float(np.dot(W, L.cpu().numpy()))
+    rhs = float(np.dot(dM.cpu().numpy(), M.cpu().numpy()))
+    assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + abs(rhs))
