@@ -1,0 +1,333 @@
+"""Benchmark of the same-level M2L hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: 4096 independent 8^3 sub-grids (24^3 frames, 8 point masses per
+cell, lognormal masses, seeded synthetic inputs), expansion order p = 3
+(C = 20), the 892-offset shell stencil, float64. A step is the forward hot
+path on that batch with inputs resident in HBM: P2M (point masses -> cell
+moments) then M2L (moments -> local coefficients of the 512 targets of every
+sub-grid). `value` is cell-pair interactions per second over the whole step.
+
+The same run also measures, each on its own batch: the split-precision M2L
+(float32 matrix cores, hi/lo products) on the step's moments, with its error
+against the oracle; forward + backward (P2M, M2L, adjoint M2L, adjoint P2M)
+on 2048 sub-grids; the uneven batch (6000 sub-grids, p in {2,3,4} as 1:2:1,
+h in {1,1/2,1/4}, random boundary masks) in one persistent launch; and the
+CPU oracle on a bounded sample of the step's workload on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import synth  # noqa: E402
+
+METRIC = "M2L cell-pair interactions/s FP64 vs split-FP32 (<=1e-10 rel); fwd+bwd ms/batch"
+FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
+FP32_PEAK_TFLOPS = 157.3    # MI355X dense FP32 matrix peak
+HBM_PEAK_GBS = 8000.0
+M2L_SRC = os.path.join(ROOT, "paper_2304_11002_amd", "csrc", "m2l_mfma.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_fwd_uniform4096_p3_traffic.txt")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def flops_per_pair(p):
+    C = (p + 1) * (p + 2) * (p + 3) // 6
+    return 2 * C * C
+
+
+# ---------------------------------------------------------------------------
+# device helpers
+# ---------------------------------------------------------------------------
+
+def upload_batch(torch, w):
+    t0 = time.time()
+    with synth.SharedBatch(w) as sb:
+        pos = torch.from_numpy(sb.pos).to("cuda")
+        mass = torch.from_numpy(sb.mass).to("cuda")
+        torch.cuda.synchronize()
+    log("generated + uploaded %s (%d sub-grids) in %.1f s" % (w.name, w.nsub, time.time() - t0))
+    return pos, mass
+
+
+def timed(torch, fn, steps, warmup, marks=1):
+    """Run fn(events, i) warmup+steps times; fn records `marks`+1 events per step.
+    Returns (wall seconds of the timed steps, per-segment event ms arrays)."""
+    for i in range(warmup):
+        fn(None, i)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(marks + 1)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        fn(evs[i], i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    seg = np.array([[evs[i][j].elapsed_time(evs[i][j + 1]) for j in range(marks)] for i in range(steps)])
+    return wall, seg
+
+
+def sampled_parity(fmm, w, desc, L_dev, sample, pos_fn):
+    """max |dL|/Labs and |dL|/|L| over sampled sub-grids (oracle on the host)."""
+    import oracle as O
+    Lh = L_dev
+    worst_labs, rel_labs, rel_l = 0.0, [], []
+    for b in sample:
+        p, h, mask = int(w.p[b]), w.h(b), int(w.mask[b])
+        C = fmm.ncomp(p)
+        o = int(desc["l_off"][b])
+        Lg = Lh[o:o + C * 512].cpu().numpy().reshape(C, 8, 8, 8)
+        pos, mass = pos_fn(b)
+        M = O.p2m(pos, mass, p, h, mask)
+        Lo = O.m2l(M, p, h, mask)
+        La = O.m2l_abs(M, p, h, mask)
+        e = np.abs(Lg - Lo)
+        worst_labs = max(worst_labs, float(np.max(e / La)))
+        rel_labs.append((e / La).ravel())
+        rel_l.append((e / np.maximum(np.abs(Lo), 1e-300)).ravel())
+    rl, rL = np.concatenate(rel_labs), np.concatenate(rel_l)
+    return {"max_rel_labs": float(rl.max()), "median_rel_labs": float(np.median(rl)),
+            "max_rel_abs_L": float(rL.max()), "median_rel_abs_L": float(np.median(rL)),
+            "sampled_subgrids": len(sample)}
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle itself on a bounded sample, one process per core
+# ---------------------------------------------------------------------------
+
+def _oracle_job(args):
+    seed, b = args
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    with threadpool_limits(1):
+        pos, mass = synth.subgrid_particles(seed, b)
+        M = O.p2m(pos, mass, 3, 1.0)
+        O.m2l(M, 3, 1.0)
+    return b
+
+
+def cpu_baseline(nsample, seed=2):
+    from multiprocessing import get_context
+    cores = min(16, len(os.sched_getaffinity(0)))
+    jobs = [(seed, b) for b in range(nsample)]
+    with get_context("fork").Pool(cores) as pool:
+        pool.map(_oracle_job, jobs[:cores])          # warm the workers (imports)
+        t0 = time.perf_counter()
+        pool.map(_oracle_job, jobs, chunksize=1)
+        wall = time.perf_counter() - t0
+    pairs = nsample * 512 * 892
+    return {"value": pairs / wall, "unit": "pairs/s", "cores": cores, "kind": "oracle",
+            "sample": "%d sub-grids of the step's workload (seed 2, p=3), P2M + M2L each, "
+                      "NumPy float64, one process per core with 1 BLAS thread; %.1f s wall" % (nsample, wall)}
+
+
+# ---------------------------------------------------------------------------
+
+def read_traffic(launch_pairs):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(M2L_SRC, "rb").read()).hexdigest()[:16]
+    if kv.get("kernel_source_sha256_16") != sha:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=192, help="oracle sub-grids for cpu_baseline")
+    ap.add_argument("--no-extras", action="store_true", help="only the step (for profiling)")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device copy of this many GiB three times (counter calibration)")
+    args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+        n = int(args.copy_calibration * 2 ** 30) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "repeats": 3}))
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs its hot path on a single MI355X "
+              "(sub-grids are independent; see DESIGN.md for how the batch would shard). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2304_11002_amd import fmm
+    fmm.load_library()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ctx = fmm.Context(0)
+    K, W = args.steps, args.warmup
+    out = {"metric": METRIC, "unit": "pairs/s", "n_gpus": 1, "steps": K, "warmup": W,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic"}
+
+    # ---------------- the step: P2M + FP64 M2L on 4096 uniform p=3 sub-grids
+    w = synth.config(2)
+    desc, m_el, l_el = fmm.make_descriptors(w.p, w.log2_inv_h, w.mask)
+    pairs = fmm.pair_count(desc)
+    pos, mass = upload_batch(torch, w)
+    M = torch.empty(m_el, dtype=torch.float64, device="cuda")
+    L = torch.empty(l_el, dtype=torch.float64, device="cuda")
+    ctx.p2m(desc, pos, mass, 8, M)
+    tuned = ctx.autotune(desc, M, L, fmm.FMM_FP64)    # tile configuration for this batch
+
+    def step(ev, i):
+        if ev: ev[0].record()
+        ctx.p2m(desc, pos, mass, 8, M)
+        if ev: ev[1].record()
+        ctx.m2l(desc, M, L, fmm.FMM_FP64)
+        if ev: ev[2].record()
+
+    wall, seg = timed(torch, step, K, W, marks=2)
+    ms_step = wall / K * 1e3
+    p2m_ms, m2l_ms = seg[:, 0].mean(), seg[:, 1].mean()
+    out["value"] = pairs / (wall / K)
+    out["ms_per_step"] = ms_step
+    out["config"] = {"workload": "uniform_4096_p3", "subgrids": w.nsub, "p": 3, "components": 20,
+                     "h": 1.0, "particles_per_cell": 8, "stencil_offsets": 892,
+                     "pairs_per_step": pairs, "step": "P2M + M2L (float64)",
+                     "p2m_ms": float(p2m_ms), "m2l_ms": float(m2l_ms),
+                     "m2l_ms_min": float(seg[:, 1].min()), "autotune_choice": tuned}
+    log("step %.3f ms (P2M %.3f, M2L %.3f): %.4g pairs/s" % (ms_step, p2m_ms, m2l_ms, out["value"]))
+    fl = pairs * flops_per_pair(3)
+    achieved = fl / (m2l_ms * 1e-3) / 1e12
+    traffic = read_traffic(pairs)
+    out["roofline"] = {"bound": "mfma", "kernel": "m2l_fwd_kernel (v_mfma_f64_4x4x4)",
+                       "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                       "flops_per_launch": fl, "flops_per_pair": flops_per_pair(3)}
+    log("M2L FP64: %.2f TFLOP/s (%.1f%% of %.1f)" % (achieved, 100 * achieved / FP64_PEAK_TFLOPS, FP64_PEAK_TFLOPS))
+
+    def pos_fn2(b):
+        return synth.subgrid_particles(w.seed, b)
+
+    sample = [0, 1234, 4095]
+    par = sampled_parity(fmm, w, desc, L, sample, pos_fn2)
+    out["parity_fp64"] = par
+    assert par["max_rel_labs"] <= 1e-12, par
+    log("FP64 parity on sampled sub-grids: max |dL|/Labs %.3g" % par["max_rel_labs"])
+
+    if not args.no_extras:
+        # ---------------- split precision on the same moments
+        try:
+            Ls = torch.empty_like(L)
+
+            def step_split(ev, i):
+                if ev: ev[0].record()
+                ctx.m2l(desc, M, Ls, fmm.FMM_SPLIT_FP32)
+                if ev: ev[1].record()
+
+            wall_s, seg_s = timed(torch, step_split, K, W, marks=1)
+            ms_s = seg_s[:, 0].mean()
+            err = sampled_parity(fmm, w, desc, Ls, sample, pos_fn2)
+            out["split_fp32"] = {"pairs_per_s": pairs / (ms_s * 1e-3), "m2l_ms": float(ms_s),
+                                 "speedup_vs_fp64_m2l": float(m2l_ms / ms_s),
+                                 "executed_fp32_tflops": 3 * fl / (ms_s * 1e-3) / 1e12,
+                                 "peak_fp32_tflops": FP32_PEAK_TFLOPS, "error_vs_oracle": err}
+            log("split-FP32 M2L %.3f ms (x%.2f vs FP64), max err/Labs %.3g" % (ms_s, m2l_ms / ms_s, err["max_rel_labs"]))
+            del Ls
+        except fmm.FMMError as e:
+            out["split_fp32"] = {"error": str(e)}
+        del pos, mass, M, L
+        torch.cuda.empty_cache()
+
+        # ---------------- forward + backward on 2048 sub-grids
+        w5 = synth.config(5)
+        d5, m5, l5 = fmm.make_descriptors(w5.p, w5.log2_inv_h, w5.mask)
+        pairs5 = fmm.pair_count(d5)
+        pos5, mass5 = upload_batch(torch, w5)
+        wt = torch.from_numpy(synth.loss_weights(w5.seed, w5.nsub)).to("cuda").reshape(-1)
+        M5 = torch.empty(m5, dtype=torch.float64, device="cuda")
+        L5 = torch.empty(l5, dtype=torch.float64, device="cuda")
+        dM5 = torch.empty_like(M5)
+        dm5 = torch.empty_like(mass5)
+
+        def step_fb(ev, i):
+            if ev: ev[0].record()
+            ctx.p2m(desc=d5, pos=pos5, mass=mass5, ppc=8, M=M5)
+            ctx.m2l(d5, M5, L5)
+            if ev: ev[1].record()
+            ctx.m2l_backward(d5, wt, dM5)      # dLoss/dL = w for loss = sum w . L
+            ctx.p2m_backward(d5, pos5, 8, dM5, dm5)
+            if ev: ev[2].record()
+
+        wall_fb, seg_fb = timed(torch, step_fb, max(3, K // 2), W, marks=2)
+        fwd_ms, bwd_ms = seg_fb[:, 0].mean(), seg_fb[:, 1].mean()
+        out["fwd_bwd"] = {"workload": "grad_2048_p3", "subgrids": w5.nsub, "pairs": pairs5,
+                          "fwd_ms": float(fwd_ms), "bwd_ms": float(bwd_ms),
+                          "fwd_bwd_ms_per_batch": float(fwd_ms + bwd_ms),
+                          "bwd_over_fwd": float(bwd_ms / fwd_ms)}
+        log("fwd+bwd 2048: fwd %.3f ms, bwd %.3f ms" % (fwd_ms, bwd_ms))
+        del pos5, mass5, wt, M5, L5, dM5, dm5
+        torch.cuda.empty_cache()
+
+        # ---------------- uneven batch in one persistent launch
+        w3 = synth.config(3)
+        d3, m3, l3 = fmm.make_descriptors(w3.p, w3.log2_inv_h, w3.mask)
+        pairs3 = fmm.pair_count(d3)
+        fl3 = float(sum(fmm.pair_count(d3[i:i + 1]) * flops_per_pair(int(w3.p[i])) for i in range(w3.nsub)))
+        pos3, mass3 = upload_batch(torch, w3)
+        M3 = torch.empty(m3, dtype=torch.float64, device="cuda")
+        L3 = torch.empty(l3, dtype=torch.float64, device="cuda")
+        ctx.p2m(d3, pos3, mass3, 8, M3)
+        chosen = ctx.autotune(d3, M3, L3, fmm.FMM_FP64)
+
+        def step_u(ev, i):
+            if ev: ev[0].record()
+            ctx.m2l(d3, M3, L3)
+            if ev: ev[1].record()
+
+        wall_u, seg_u = timed(torch, step_u, K, W, marks=1)
+        ms_u = seg_u[:, 0].mean()
+
+        def pos_fn3(b):
+            return synth.subgrid_particles(w3.seed, b, w3.h(b))
+
+        par3 = sampled_parity(fmm, w3, d3, L3, [0, 2999, 5999], pos_fn3)
+        assert par3["max_rel_labs"] <= 1e-12, par3
+        out["uneven"] = {"workload": "uneven_6000_mixed_p", "subgrids": w3.nsub, "pairs": pairs3,
+                         "m2l_ms": float(ms_u), "pairs_per_s": pairs3 / (ms_u * 1e-3),
+                         "useful_tflops": fl3 / (ms_u * 1e-3) / 1e12, "autotune_choice": chosen,
+                         "parity": par3}
+        log("uneven 6000: %.3f ms, %.4g pairs/s, %.2f TFLOP/s useful" % (ms_u, pairs3 / (ms_u * 1e-3), fl3 / (ms_u * 1e-3) / 1e12))
+        del pos3, mass3, M3, L3
+        torch.cuda.empty_cache()
+
+        # ---------------- CPU baseline (the oracle on the host cores)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        log("cpu_baseline %.4g pairs/s on %d cores" % (out["cpu_baseline"]["value"], out["cpu_baseline"]["cores"]))
+
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -140,10 +140,11 @@ fmm_status fmm_p2m_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
  * device memory `out` ([892][C][C], offsets in fmm_stencil order). */
 fmm_status fmm_stencil_tables(fmm_ctx* ctx, int32_t p, double* out, void* stream);
 
-/* Time the candidate M2L tile configurations on these descriptors and
- * buffers (M read, L overwritten) and keep the fastest for later calls
- * with the same precision; `chosen` (may be NULL) receives its index.
- * Synchronises the stream. */
+/* Autotuner: time every candidate M2L configuration (waves per workgroup,
+ * operand prefetch) on these descriptors and buffers (M read, L
+ * overwritten) and keep the fastest for later calls with the same
+ * descriptor set and precision; `chosen` (may be NULL) receives its index.
+ * Synchronises the stream. FMM_OPT_TILE_CONFIG >= 0 overrides the choice. */
 fmm_status fmm_autotune(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
                         const double* M, double* L, fmm_precision prec,
                         void* stream, int32_t* chosen);

@@ -91,6 +91,7 @@ struct DescEntry {
   int* d_ids[kMaxP + 1] = {};     // reference kernels: sub-grids per order
   int count[kMaxP + 1] = {};
   WorkList work;                  // matrix-core kernels
+  int tuned[2] = {-1, -1};        // autotuned configuration per precision
   hipEvent_t ready = nullptr;     // upload finished
   hipEvent_t last_launch = nullptr;
 };
@@ -116,7 +117,6 @@ struct fmm_ctx {
   int m2l_kernel = 0;                         // 0 auto, 1 reference, 2 matrix core
   int use_graph = 1;
   int tile_config = -1;
-  int tuned[2] = {-1, -1};                    // per precision
 };
 
 namespace {
@@ -504,9 +504,9 @@ static fmm_status run_mfma(fmm_ctx* ctx, DescEntry* e, const double* M, double* 
   return FMM_OK;
 }
 
-static int pick_config(fmm_ctx* ctx, fmm_precision prec) {
+static int pick_config(const fmm_ctx* ctx, const DescEntry* e, fmm_precision prec) {
   if (ctx->tile_config >= 0) return ctx->tile_config;
-  if (ctx->tuned[prec] >= 0) return ctx->tuned[prec];
+  if (e && e->tuned[prec] >= 0) return e->tuned[prec];
   return mfma_default_config(prec);
 }
 
@@ -529,7 +529,7 @@ fmm_status fmm_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const do
   if (ctx->m2l_kernel == 1) {
     CHECK_OK(run_ref(ctx, e, false, M, L, s));
   } else {
-    CHECK_OK(run_mfma(ctx, e, M, L, prec, pick_config(ctx, prec), s));
+    CHECK_OK(run_mfma(ctx, e, M, L, prec, pick_config(ctx, e, prec), s));
   }
   return mark_used(ctx, e, s);
 }
@@ -577,7 +577,7 @@ fmm_status fmm_autotune(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, con
   if (prec != FMM_FP64 && prec != FMM_SPLIT_FP32) return set_err(ctx, FMM_EINVAL, "unknown precision");
   if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
   if (nsub == 0) {
-    if (chosen) *chosen = pick_config(ctx, prec);
+    if (chosen) *chosen = pick_config(ctx, nullptr, prec);
     return FMM_OK;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -611,7 +611,7 @@ fmm_status fmm_autotune(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, con
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
-  ctx->tuned[prec] = best;
+  e->tuned[prec] = best;
   if (chosen) *chosen = best;
   return mark_used(ctx, e, s);
 }

@@ -43,7 +43,7 @@ __global__ void reset_counter_kernel(unsigned* counter) { *counter = 0u; }
 // forward
 // ---------------------------------------------------------------------------
 
-template <int P, int WAVES>
+template <int P, int WAVES, bool PF>
 __device__ __forceinline__ void fwd_subgrid(const DevDesc& d, const double* __restrict__ M,
                                             double* __restrict__ L, const double* __restrict__ Bp,
                                             const int* __restrict__ lds_off,
@@ -53,7 +53,9 @@ __device__ __forceinline__ void fwd_subgrid(const DevDesc& d, const double* __re
   constexpr int ROUNDS = (C + 1) / 2;    // moment components staged two at a time
   constexpr int TPW = 32 / WAVES;        // 16-cell tiles per wave
   constexpr int NT = WAVES * 64;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // wave index as a scalar: keeps the per-quad table lookups on the scalar unit
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int kk = lane >> 4;              // offset of the quad this lane feeds
   const int ci = lane & 15;              // cell of the tile this lane feeds
 
@@ -82,39 +84,93 @@ __device__ __forceinline__ void fwd_subgrid(const DevDesc& d, const double* __re
     const double s1 = k1 < C ? ldexp(1.0, l2 * order_of(k1)) : 0.0;
     const double* src0 = src + (size_t)k0 * kNCell;
     const double* src1 = src + (size_t)(k1 < C ? k1 : k0) * kNCell;
-    __syncthreads();   // previous round's reads of smem are done
-    for (int c = tid; c < kWinCells; c += NT) {
-      const int wx = c % kWin, wy = (c / kWin) % kWin, wz = c / (kWin * kWin);
-      const int jx = wx + kWin0, jy = wy + kWin0, jz = wz + kWin0;
-      const int cell = jx + kFrame * jy + kFrame * kFrame * jz;
-      double2 v = make_double2(0.0, 0.0);
-      if (block_present(d.mask, jx, jy, jz)) {
-        v.x = src0[cell] * s0;
-        v.y = src1[cell] * s1;
+    // issue every load of this thread's share of the window before any LDS store,
+    // so the HBM latency is paid once per round rather than once per cell
+    constexpr int kStage = (kWinCells + NT - 1) / NT;
+    double2 v[kStage];
+#pragma unroll
+    for (int i = 0; i < kStage; ++i) {
+      const int c = tid + i * NT;
+      v[i] = make_double2(0.0, 0.0);
+      if (c < kWinCells) {
+        const int wx = c % kWin, wy = (c / kWin) % kWin, wz = c / (kWin * kWin);
+        const int jx = wx + kWin0, jy = wy + kWin0, jz = wz + kWin0;
+        const int cell = jx + kFrame * jy + kFrame * kFrame * jz;
+        if (block_present(d.mask, jx, jy, jz)) {
+          v[i].x = src0[cell];
+          v[i].y = src1[cell];
+        }
       }
-      smem[c] = v;
+    }
+    __syncthreads();   // previous round's reads of smem are done
+#pragma unroll
+    for (int i = 0; i < kStage; ++i) {
+      const int c = tid + i * NT;
+      if (c < kWinCells) smem[c] = make_double2(v[i].x * s0, v[i].y * s1);
     }
     __syncthreads();
     const double* Br = Bp + (size_t)r * kQuads * 2 * NG * 16 + kk * 4 + (lane & 3);
-    for (int q = 0; q < kQuads; ++q) {
-      uint32_t tm = 0;
-      for (int z = zlo; z <= zhi; ++z) tm |= touch[z * kQuads + q];
-      if ((tm & d.mask) == 0) continue;   // every source of this quad is absent for this wave
-      const int doff = lds_off[4 * q + kk];
-      const double* Bq = Br + (size_t)q * 2 * NG * 16;
-      double b0[NG], b1[NG];
+    // table operands of the next quad are loaded while this quad's products run
+    double nb0[NG], nb1[NG];
+    if (PF) {
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
-        b0[g] = Bq[g * 16];
-        b1[g] = Bq[(NG + g) * 16];
+        nb0[g] = Br[g * 16];
+        nb1[g] = Br[(NG + g) * 16];
       }
+    }
+    // per-quad scalars (blocks touched, LDS offsets) are fetched one quad ahead
+    const int4* off4 = reinterpret_cast<const int4*>(lds_off);
+    uint32_t tm_next = 0;
+    for (int z = zlo; z <= zhi; ++z) tm_next |= touch[z * kQuads];
+    int4 o_next = off4[0];
+    for (int q = 0; q < kQuads; ++q) {
+      const uint32_t tm = tm_next;
+      const int4 o = o_next;
+      if (q + 1 < kQuads) {
+        tm_next = 0;
+        for (int z = zlo; z <= zhi; ++z) tm_next |= touch[z * kQuads + q + 1];
+        o_next = off4[q + 1];
+      }
+      double b0[NG], b1[NG];
+      if (PF) {
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          b0[g] = nb0[g];
+          b1[g] = nb1[g];
+        }
+        if (q + 1 < kQuads) {
+          const double* Bn = Br + (size_t)(q + 1) * 2 * NG * 16;
+#pragma unroll
+          for (int g = 0; g < NG; ++g) {
+            nb0[g] = Bn[g * 16];
+            nb1[g] = Bn[(NG + g) * 16];
+          }
+        }
+      }
+      if ((tm & d.mask) == 0) continue;   // every source of this quad is absent for this wave
+      // each lane takes the offset of its k-slot (branch-free select of scalars)
+      int doff = o.x;
+      doff = kk == 1 ? o.y : doff;
+      doff = kk == 2 ? o.z : doff;
+      doff = kk == 3 ? o.w : doff;
+      if (!PF) {
+        const double* Bq = Br + (size_t)q * 2 * NG * 16;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          b0[g] = Bq[g * 16];
+          b1[g] = Bq[(NG + g) * 16];
+        }
+      }
+      double2 a[TPW];
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) a[t] = smem[abase[t] + doff];
 #pragma unroll
       for (int t = 0; t < TPW; ++t) {
-        const double2 a = smem[abase[t] + doff];
 #pragma unroll
-        for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a.x, b0[g], acc[t][g]);
+        for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a[t].x, b0[g], acc[t][g]);
 #pragma unroll
-        for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a.y, b1[g], acc[t][g]);
+        for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a[t].y, b1[g], acc[t][g]);
       }
     }
   }
@@ -135,7 +191,7 @@ __device__ __forceinline__ void fwd_subgrid(const DevDesc& d, const double* __re
   }
 }
 
-template <int WAVES>
+template <int WAVES, bool PF>
 __global__ void __launch_bounds__(WAVES * 64) m2l_fwd_kernel(
     const WorkItem* __restrict__ items, int count, unsigned* __restrict__ counter,
     const DevDesc* __restrict__ desc, const double* __restrict__ M, double* __restrict__ L,
@@ -150,9 +206,9 @@ __global__ void __launch_bounds__(WAVES * 64) m2l_fwd_kernel(
     if (item >= count) break;
     const DevDesc d = desc[items[item].sub];
     switch (d.p) {
-      case 2: fwd_subgrid<2, WAVES>(d, M, L, B2, lds_off, touch, smem); break;
-      case 3: fwd_subgrid<3, WAVES>(d, M, L, B3, lds_off, touch, smem); break;
-      case 4: fwd_subgrid<4, WAVES>(d, M, L, B4, lds_off, touch, smem); break;
+      case 2: fwd_subgrid<2, WAVES, PF && (2 < 4 || WAVES == 4)>(d, M, L, B2, lds_off, touch, smem); break;
+      case 3: fwd_subgrid<3, WAVES, PF && (3 < 4 || WAVES == 4)>(d, M, L, B3, lds_off, touch, smem); break;
+      case 4: fwd_subgrid<4, WAVES, PF && (4 < 4 || WAVES == 4)>(d, M, L, B4, lds_off, touch, smem); break;
       default: break;
     }
     __syncthreads();   // s_item and smem are free for the next item
@@ -381,10 +437,13 @@ std::vector<int> host_stencil() {
 
 // Configurations: forward waves per workgroup (tiles per wave = 32 / waves).
 struct Config {
-  int waves;
+  int waves;        // waves per workgroup (16-cell tiles per wave = 32 / waves)
+  bool prefetch;    // table operands of the next offset quad loaded one quad ahead
+                    // (not at p = 4 with 8 waves: the registers would spill)
   fmm_precision prec;
 };
-constexpr Config kConfigs[] = {{8, FMM_FP64}, {4, FMM_FP64}};
+constexpr Config kConfigs[] = {{8, false, FMM_FP64}, {8, true, FMM_FP64},
+                               {4, false, FMM_FP64}, {4, true, FMM_FP64}};
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
 }  // namespace
@@ -481,18 +540,16 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
   if (!mfma_config_supports(cfg, prec)) return hipErrorInvalidValue;
   const int grid = std::min(t.num_cu, w.count);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, w.counter);
-  switch (kConfigs[cfg].waves) {
-    case 8:
-      hipLaunchKernelGGL(m2l_fwd_kernel<8>, dim3(grid), dim3(512), 0, s, w.items, w.count, w.counter,
-                         d_desc, M, L, t.fwd[2], t.fwd[3], t.fwd[4], t.lds_off, t.touch);
-      break;
-    case 4:
-      hipLaunchKernelGGL(m2l_fwd_kernel<4>, dim3(grid), dim3(256), 0, s, w.items, w.count, w.counter,
-                         d_desc, M, L, t.fwd[2], t.fwd[3], t.fwd[4], t.lds_off, t.touch);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
+  const Config& c = kConfigs[cfg];
+#define FWD_LAUNCH(W, PFV)                                                                         \
+  hipLaunchKernelGGL((m2l_fwd_kernel<W, PFV>), dim3(grid), dim3(W * 64), 0, s, w.items, w.count,   \
+                     w.counter, d_desc, M, L, t.fwd[2], t.fwd[3], t.fwd[4], t.lds_off, t.touch)
+  if (c.waves == 8 && c.prefetch) FWD_LAUNCH(8, true);
+  else if (c.waves == 4 && c.prefetch) FWD_LAUNCH(4, true);
+  else if (c.waves == 8) FWD_LAUNCH(8, false);
+  else if (c.waves == 4) FWD_LAUNCH(4, false);
+  else return hipErrorInvalidValue;
+#undef FWD_LAUNCH
   return hipGetLastError();
 }
 
