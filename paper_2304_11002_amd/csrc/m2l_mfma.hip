@@ -216,6 +216,263 @@ __global__ void __launch_bounds__(WAVES * 64) m2l_fwd_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// split precision forward
+// ---------------------------------------------------------------------------
+//
+// M = M_hi + M_lo and T = T_hi + T_lo (float32 parts of the float64 values;
+// T_hi/T_lo are split from the float64 tables, M after its h-scaling). Per
+// offset block the three products M_hi T_hi + M_hi T_lo + M_lo T_hi are
+// summed in float32 on the matrix cores; each block sum is added to float64
+// accumulators, and the h^(-1-|n|) scaling is applied in float64. One block
+// is 16 offset quads (64 offsets) of one staged component pair.
+//
+// Columns n < 16 * NCT use v_mfma_f32_16x16x4 (A: lane -> cell l%16, offset
+// slot l/16; B: lane -> offset slot l/16, column l%16; D: lane, v -> cell
+// 4*(l/16)+v, column l%16). The remaining C - 16 * NCT columns use
+// v_mfma_f32_4x4x1_16b on the same A register: block b = l/4 takes offset
+// slot b/4 and cells 4*(b%4)..+3, so its D (lane, v -> cell 4*((l/4)%4)+v,
+// column l%4) holds one partial sum per offset slot, added across slots
+// at the end.
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma4x1(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int kSplitBlockQuads = 16;   // 64 offsets per float32 block sum
+
+// Columns handled in this call: 16-wide tiles [CT0, CT0 + NCTP) and, if WREM,
+// the remainder columns (p = 4 runs two calls so its accumulators fit).
+template <int P, int CT0, int NCTP, bool WREM>
+__device__ __forceinline__ void fwd_split_subgrid(const DevDesc& d, const double* __restrict__ M,
+                                                  double* __restrict__ L,
+                                                  const float* __restrict__ Bhi,
+                                                  const float* __restrict__ Blo,
+                                                  const int* __restrict__ lds_off,
+                                                  const uint32_t* __restrict__ touch, float4* smem) {
+  constexpr int C = ncomp(P);
+  constexpr int NG = (C + 3) / 4;                   // groups of 4 columns in the packed tables
+  constexpr int ROUNDS = (C + 1) / 2;
+  constexpr int NCT_ALL = C >= 16 ? C / 16 : 1;     // 16-wide column tiles in total
+  constexpr int NCT = NCTP;                         // ... in this call
+  constexpr int REM = WREM && C - 16 * NCT_ALL > 0 ? C - 16 * NCT_ALL : 0;   // 4x4x1 columns
+  constexpr int WAVES = 8, TPW = 4, NT = WAVES * 64;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int kk = lane >> 4, ci = lane & 15;
+  int abase[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int gt = wave * TPW + t;
+    const int z = gt >> 2, x = (gt & 1) * 4 + (ci & 3), y = ((gt >> 1) & 1) * 4 + (ci >> 2);
+    abase[t] = (x + 6) + kWin * (y + 6) + kWin * kWin * (z + 6);
+  }
+  const int zp = wave;   // one target plane per wave
+
+  double acc[TPW][NCT][4];
+  double racc[TPW][4];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[t][c][v] = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) racc[t][v] = 0.0;
+  }
+
+  // lane offsets into one (round, quad, comp) chunk of the packed tables
+  int boff[NCT];
+  bool bvalid[NCT];
+#pragma unroll
+  for (int c = 0; c < NCT; ++c) {
+    const int g = 4 * (CT0 + c) + (ci >> 2);
+    bvalid[c] = g < NG;
+    boff[c] = (bvalid[c] ? g : 0) * 16 + kk * 4 + (lane & 3);
+  }
+  const int roff = 4 * NCT_ALL * 16 + kk * 4 + (lane & 3);   // remainder group
+
+  const int l2 = d.log2_inv_h;
+  const double* src = M + d.m_off;
+  for (int r = 0; r < ROUNDS; ++r) {
+    const int k0 = 2 * r, k1 = 2 * r + 1;
+    const double s0 = ldexp(1.0, l2 * order_of(k0));
+    const double s1 = k1 < C ? ldexp(1.0, l2 * order_of(k1)) : 0.0;
+    const double* src0 = src + (size_t)k0 * kNCell;
+    const double* src1 = src + (size_t)(k1 < C ? k1 : k0) * kNCell;
+    // two halves of loads-then-stores keep the staging registers small
+    constexpr int kStage = (kWinCells + NT - 1) / NT;
+    constexpr int kHalf = (kStage + 1) / 2;
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+      double2 v[kHalf];
+#pragma unroll
+      for (int i = 0; i < kHalf; ++i) {
+        const int c = tid + (hb * kHalf + i) * NT;
+        v[i] = make_double2(0.0, 0.0);
+        if (hb * kHalf + i < kStage && c < kWinCells) {
+          const int wx = c % kWin, wy = (c / kWin) % kWin, wz = c / (kWin * kWin);
+          const int jx = wx + kWin0, jy = wy + kWin0, jz = wz + kWin0;
+          const int cell = jx + kFrame * jy + kFrame * kFrame * jz;
+          if (block_present(d.mask, jx, jy, jz)) {
+            v[i].x = src0[cell];
+            v[i].y = src1[cell];
+          }
+        }
+      }
+      if (hb == 0) __syncthreads();   // previous round's reads of smem are done
+#pragma unroll
+      for (int i = 0; i < kHalf; ++i) {
+        const int c = tid + (hb * kHalf + i) * NT;
+        if (hb * kHalf + i < kStage && c < kWinCells) {
+          const double a0 = v[i].x * s0, a1 = v[i].y * s1;
+          const float h0 = (float)a0, h1 = (float)a1;
+          smem[c] = make_float4(h0, (float)(a0 - (double)h0), h1, (float)(a1 - (double)h1));
+        }
+      }
+    }
+    __syncthreads();
+
+    const size_t chunk = (size_t)NG * 16;                     // one comp of one quad
+    const float* Rh = Bhi + (size_t)r * kQuads * 2 * chunk;
+    const float* Rl = Blo + (size_t)r * kQuads * 2 * chunk;
+    const int4* off4 = reinterpret_cast<const int4*>(lds_off);
+    uint32_t tm_next = touch[zp * kQuads];
+    int4 o_next = off4[0];
+    v4f f[TPW][NCT], fr[TPW];
+    for (int q = 0; q < kQuads; ++q) {
+      if (q % kSplitBlockQuads == 0) {
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+          for (int c = 0; c < NCT; ++c) f[t][c] = (v4f){0.f, 0.f, 0.f, 0.f};
+          fr[t] = (v4f){0.f, 0.f, 0.f, 0.f};
+        }
+      }
+      const uint32_t tm = tm_next;
+      const int4 o = o_next;
+      if (q + 1 < kQuads) {
+        tm_next = touch[zp * kQuads + q + 1];
+        o_next = off4[q + 1];
+      }
+      if ((tm & d.mask) != 0) {
+        int doff = o.x;
+        doff = kk == 1 ? o.y : doff;
+        doff = kk == 2 ? o.z : doff;
+        doff = kk == 3 ? o.w : doff;
+        const float* Qh = Rh + (size_t)q * 2 * chunk;
+        const float* Ql = Rl + (size_t)q * 2 * chunk;
+        float bh[2][NCT], bl[2][NCT], rh[2], rl[2];
+#pragma unroll
+        for (int cp = 0; cp < 2; ++cp) {
+#pragma unroll
+          for (int c = 0; c < NCT; ++c) {
+            bh[cp][c] = bvalid[c] ? Qh[cp * chunk + boff[c]] : 0.f;
+            bl[cp][c] = bvalid[c] ? Ql[cp * chunk + boff[c]] : 0.f;
+          }
+          rh[cp] = REM ? Qh[cp * chunk + roff] : 0.f;
+          rl[cp] = REM ? Ql[cp * chunk + roff] : 0.f;
+        }
+        float4 a[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) a[t] = smem[abase[t] + doff];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+          for (int cp = 0; cp < 2; ++cp) {
+            const float ah = cp ? a[t].z : a[t].x, al = cp ? a[t].w : a[t].y;
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) {
+              f[t][c] = mfma16(ah, bh[cp][c], f[t][c]);
+              f[t][c] = mfma16(ah, bl[cp][c], f[t][c]);
+              f[t][c] = mfma16(al, bh[cp][c], f[t][c]);
+            }
+            if (REM) {
+              fr[t] = mfma4x1(ah, rh[cp], fr[t]);
+              fr[t] = mfma4x1(ah, rl[cp], fr[t]);
+              fr[t] = mfma4x1(al, rh[cp], fr[t]);
+            }
+          }
+        }
+      }
+      if (q % kSplitBlockQuads == kSplitBlockQuads - 1 || q == kQuads - 1) {
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+          for (int c = 0; c < NCT; ++c)
+#pragma unroll
+            for (int v2 = 0; v2 < 4; ++v2) acc[t][c][v2] += (double)f[t][c][v2];
+#pragma unroll
+          for (int v2 = 0; v2 < 4; ++v2) racc[t][v2] += (double)fr[t][v2];
+        }
+      }
+    }
+  }
+
+  double* out = L + d.l_off;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int gt = wave * TPW + t;
+    const int z = gt >> 2, x0 = (gt & 1) * 4, y0 = ((gt >> 1) & 1) * 4;
+    // 16x16 tiles: lane, v -> cell 4*(lane/16) + v (x = v, y = lane/16), column lane%16
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      const int n = 16 * (CT0 + c) + (lane & 15);
+#pragma unroll
+      for (int v2 = 0; v2 < 4; ++v2) {
+        const int tcell = (x0 + v2) + kBlock * (y0 + (lane >> 4)) + kBlock * kBlock * z;
+        if (n < C) out[(size_t)n * kNTarget + tcell] = ldexp(acc[t][c][v2], l2 * (1 + order_of(n)));
+      }
+    }
+    if (REM) {
+      // sum the four offset-slot partials (lanes l, l^16, l^32, l^48)
+#pragma unroll
+      for (int v2 = 0; v2 < 4; ++v2) {
+        double s = racc[t][v2];
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        const int cell = 4 * ((lane >> 2) & 3) + v2;          // x = v2, y = (lane/4)%4
+        const int n = 16 * NCT_ALL + (lane & 3);
+        const int tcell = (x0 + (cell & 3)) + kBlock * (y0 + (cell >> 2)) + kBlock * kBlock * z;
+        if (lane < 16 && n < C) out[(size_t)n * kNTarget + tcell] = ldexp(s, l2 * (1 + order_of(n)));
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(512) m2l_fwd_split_kernel(
+    const WorkItem* __restrict__ items, int count, unsigned* __restrict__ counter,
+    const DevDesc* __restrict__ desc, const double* __restrict__ M, double* __restrict__ L,
+    const float* __restrict__ H2, const float* __restrict__ L2v, const float* __restrict__ H3,
+    const float* __restrict__ L3v, const float* __restrict__ H4, const float* __restrict__ L4v,
+    const int* __restrict__ lds_off, const uint32_t* __restrict__ touch) {
+  __shared__ float4 smem[kWinCells];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= count) break;
+    const DevDesc d = desc[items[item].sub];
+    switch (d.p) {
+      case 2: fwd_split_subgrid<2, 0, 1, true>(d, M, L, H2, L2v, lds_off, touch, smem); break;
+      case 3: fwd_split_subgrid<3, 0, 1, true>(d, M, L, H3, L3v, lds_off, touch, smem); break;
+      case 4:
+        fwd_split_subgrid<4, 0, 1, false>(d, M, L, H4, L4v, lds_off, touch, smem);
+        __syncthreads();
+        fwd_split_subgrid<4, 1, 1, true>(d, M, L, H4, L4v, lds_off, touch, smem);
+        break;
+      default: break;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // adjoint: dM_k(s) = h^-|k| sum_e sum_n [h^(-1-|n|) dL_n(s + e)] T_e[n][k]
 // ---------------------------------------------------------------------------
 //
@@ -443,7 +700,8 @@ struct Config {
   fmm_precision prec;
 };
 constexpr Config kConfigs[] = {{8, false, FMM_FP64}, {8, true, FMM_FP64},
-                               {4, false, FMM_FP64}, {4, true, FMM_FP64}};
+                               {4, false, FMM_FP64}, {4, true, FMM_FP64},
+                               {8, false, FMM_SPLIT_FP32}};
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
 }  // namespace
@@ -541,6 +799,12 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
   const int grid = std::min(t.num_cu, w.count);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, w.counter);
   const Config& c = kConfigs[cfg];
+  if (c.prec == FMM_SPLIT_FP32) {
+    hipLaunchKernelGGL(m2l_fwd_split_kernel, dim3(grid), dim3(512), 0, s, w.items, w.count, w.counter,
+                       d_desc, M, L, t.fwd_hi[2], t.fwd_lo[2], t.fwd_hi[3], t.fwd_lo[3], t.fwd_hi[4],
+                       t.fwd_lo[4], t.lds_off, t.touch);
+    return hipGetLastError();
+  }
 #define FWD_LAUNCH(W, PFV)                                                                         \
   hipLaunchKernelGGL((m2l_fwd_kernel<W, PFV>), dim3(grid), dim3(W * 64), 0, s, w.items, w.count,   \
                      w.counter, d_desc, M, L, t.fwd[2], t.fwd[3], t.fwd[4], t.lds_off, t.touch)
