@@ -33,8 +33,12 @@ struct MfmaTables {
   // split precision, per order p: the same layout, float32 hi and lo parts
   float* fwd_hi[kMaxP + 1] = {};
   float* fwd_lo[kMaxP + 1] = {};
-  // adjoint, per order p: [offset][k-chunk][n-group][kk*4 + j] float64
+  // adjoint, per order p: [rounds][offset pair][dL chunk][kk*4 + j] float64
   double* bwd[kMaxP + 1] = {};
+  int4* pairs = nullptr;        // adjoint offset pairs: (LDS offset 1, LDS offset 2, stencil 1, stencil 2 or -1)
+  int npairs = 0;
+  int* gstart = nullptr;        // first pair of each dz (13 groups + end)
+  uint32_t* ptouch = nullptr;   // [8][npairs] blocks a target plane writes per pair
   const int* stencil = nullptr;   // [892][3] offsets (owned by the context)
   int* lds_off = nullptr;     // [892] dx + 20 dy + 400 dz
   uint32_t* touch = nullptr;  // [8][quads] blocks touched by an 8x8 target plane per quad

@@ -473,115 +473,145 @@ __global__ void __launch_bounds__(512) m2l_fwd_split_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// adjoint: dM_k(s) = h^-|k| sum_e sum_n [h^(-1-|n|) dL_n(s + e)] T_e[n][k]
+// adjoint: dM_k(s) = h^-|k| sum_{(t, d) : t + d = s} sum_n [h^(-1-|n|) dL_n(t)] T_d[k][n]
 // ---------------------------------------------------------------------------
 //
-// Targets are the 20^3 reachable window in 4x4x1 tiles (5 x 5 x 20 = 500
-// per sub-grid); sources are dL, staged whole in LDS ([C rounded to 4][512],
-// zero-padded components). The reduction is taken four source components at
-// a time for one offset; an offset is skipped for a tile when the shifted
-// tile misses the 8^3 block, and lanes whose shifted cell misses it read 0.
+// Scatter form: every (target t, offset d) pair contributes to exactly one
+// output cell s = t + d of the 20^3 window, so no product is wasted (a
+// gather over output tiles would compute mostly zeros, since dL lives on
+// the 8^3 block only). One workgroup owns one sub-grid; for each pair of
+// output components ("round") the window's accumulators live in LDS. Wave w
+// holds target plane w (its dL values stay in registers for the whole
+// sub-grid) and applies the offsets of one dz at a time: for a fixed dz the
+// waves write disjoint output planes, so there are no atomics and the
+// summation order is fixed. One instruction multiplies [16 targets x 4 dL
+// components] by [4 components x (2 output components x 2 offsets)]; the two
+// offsets of a pair never map two cells of one 4x4 tile to the same output
+// cell (|dx2 - dx1| >= 4 or |dy2 - dy1| >= 4), so each read-modify-write is
+// collision free. The read-modify-write of one pair overlaps the next pair's
+// products.
 
 constexpr int kBwdWaves = 8;
 constexpr int kBwdThreads = kBwdWaves * 64;
-constexpr int kBwdTilesPerGroup = 5;   // one row of 4x4 patches across the window
-constexpr int kBwdGroups = 5 * 20;     // rows x planes
+constexpr int kAccStride = kWinCells + 16;     // component stride of the LDS accumulators
+constexpr int kMaxPairs = 512;
 
 template <int P>
 __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __restrict__ dL,
                                             double* __restrict__ dM, const double* __restrict__ Bp,
-                                            const int* __restrict__ stencil, double* smem) {
+                                            const int4* __restrict__ pairs, int npairs,
+                                            const int* __restrict__ gstart,
+                                            const uint32_t* __restrict__ ptouch, double* smem) {
   constexpr int C = ncomp(P);
-  constexpr int KC = (C + 3) / 4;     // source component chunks of 4
-  constexpr int NG = (C + 3) / 4;     // output column groups of 4
-  constexpr int TPG = kBwdTilesPerGroup;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int kk = lane >> 4, ci = lane & 15;
+  constexpr int KC = (C + 3) / 4;     // dL component chunks of 4 (the reduction)
+  constexpr int ROUNDS = (C + 1) / 2;
+  constexpr int TPW = 4;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // target plane
+  const int kk = lane >> 4, ci = lane & 15, j = lane & 3;
+  const int slot = j & 1, half = j >> 1;    // output component of the round, offset of the pair
   const int l2 = d.log2_inv_h;
-  double* out = dM + d.m_off;
 
-  // zero every cell this sub-grid does not compute: outside the window, absent blocks
-  for (int i = tid; i < KC * 4 * kNCell; i += kBwdThreads) {
-    const int k = i / kNCell, cell = i % kNCell;
-    if (k >= C) break;
-    const int jx = cell % kFrame, jy = (cell / kFrame) % kFrame, jz = cell / (kFrame * kFrame);
-    const bool win = jx >= kWin0 && jx < kWin0 + kWin && jy >= kWin0 && jy < kWin0 + kWin &&
-                     jz >= kWin0 && jz < kWin0 + kWin;
-    if (!win || !block_present(d.mask, jx, jy, jz)) out[(size_t)k * kNCell + cell] = 0.0;
-  }
-  // stage dL scaled by h^(-1-|n|); components beyond C are zero
+  // A operands: dL of this wave's four 4x4 tiles, scaled by h^(-1-|n|)
+  double a[TPW][KC];
+  int obase[TPW];
   const double* src = dL + d.l_off;
-  for (int i = tid; i < KC * 4 * kNTarget; i += kBwdThreads) {
-    const int n = i / kNTarget;
-    smem[i] = n < C ? ldexp(src[i], l2 * (1 + order_of(n))) : 0.0;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int x0 = (t & 1) * 4, y0 = (t >> 1) * 4;
+    const int tcell = x0 + (ci & 3) + kBlock * (y0 + (ci >> 2)) + kBlock * kBlock * wave;
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      const int n = 4 * kc + kk;
+      a[t][kc] = n < C ? ldexp(src[(size_t)n * kNTarget + tcell], l2 * (1 + order_of(n))) : 0.0;
+    }
+    // D layout: lane holds target cell (x = lane/16, y = (lane%16)/4) of the tile
+    obase[t] = (x0 + (lane >> 4) + 6) + kWin * (y0 + ((lane & 15) >> 2) + 6) + kWin * kWin * (wave + 6) +
+               slot * kAccStride;
   }
-  __syncthreads();
 
-  for (int grp = wave; grp < kBwdGroups; grp += kBwdWaves) {
-    const int z = grp / 5 + kWin0;         // frame plane
-    const int y0 = (grp % 5) * 4 + kWin0;  // frame row of the 4x4 patches
-    // skip groups whose cells all lie in absent blocks
-    bool any = false;
+  for (int i = tid; i < 2 * kAccStride; i += kBwdThreads) smem[i] = 0.0;
+
+  const int4* pr = pairs;
+  const uint32_t* tw = ptouch + wave * npairs;
+  double* out = dM + d.m_off;
+  for (int r = 0; r < ROUNDS; ++r) {
+    __syncthreads();
+    const double* Br = Bp + (size_t)r * npairs * KC * 16 + kk * 4 + j;
+    double accp[TPW];
+    int addrp = 0;          // offset of the pending read-modify-write
+    bool pend = false, wp = false;
+    // read-modify-write of the pending pair: first the lanes of its first offset
+    // (four tiles of distinct cells: loads, then stores), then those of the second.
+    // Different lanes of this wave update the same cell only across these
+    // batches (the second offset, the next pair); the wavefront fences keep the
+    // compiler from merging or reordering the batches, and one wave's LDS
+    // accesses complete in order.
+    auto flush = [&]() {
 #pragma unroll
-    for (int t = 0; t < TPG; ++t) {
-      const int x0 = t * 4 + kWin0;
-      for (int c = 0; c < 16; ++c) any |= block_present(d.mask, x0 + (c & 3), y0 + (c >> 2), z);
-    }
-    if (!any) continue;
-    double acc[TPG][NG];
+      for (int hs = 0; hs < 2; ++hs) {
+        if (half == hs && wp) {
+          double v[TPW];
 #pragma unroll
-    for (int t = 0; t < TPG; ++t)
+          for (int t = 0; t < TPW; ++t) v[t] = smem[obase[t] + addrp];
 #pragma unroll
-      for (int g = 0; g < NG; ++g) acc[t][g] = 0.0;
-    for (int e = 0; e < kNStencil; ++e) {
-      const int ex = stencil[3 * e], ey = stencil[3 * e + 1], ez = stencil[3 * e + 2];
-      const int tz = z + ez - kBlock;
-      if ((unsigned)tz >= (unsigned)kBlock) continue;
-      const int ylo = y0 + ey - kBlock;   // target-block y of the patch's first row
-      if (ylo > kBlock - 1 || ylo + 3 < 0) continue;
-      const int ty = ylo + (ci >> 2);
-      const bool yok = (unsigned)ty < (unsigned)kBlock;
-      bool active[TPG];
-      int tcell[TPG];
-      bool ok[TPG];
-      bool any_active = false;
-#pragma unroll
-      for (int t = 0; t < TPG; ++t) {
-        const int xlo = t * 4 + kWin0 + ex - kBlock;
-        active[t] = !(xlo > kBlock - 1 || xlo + 3 < 0);
-        any_active |= active[t];
-        const int tx = xlo + (ci & 3);
-        ok[t] = active[t] && yok && (unsigned)tx < (unsigned)kBlock;
-        tcell[t] = ok[t] ? tx + kBlock * ty + kBlock * kBlock * tz : 0;
-      }
-      if (!any_active) continue;
-      const double* Be = Bp + (size_t)e * KC * NG * 16 + kk * 4 + (lane & 3);
-#pragma unroll
-      for (int kc = 0; kc < KC; ++kc) {
-        double b[NG];
-#pragma unroll
-        for (int g = 0; g < NG; ++g) b[g] = Be[(kc * NG + g) * 16];
-        const double* sm = smem + (4 * kc + kk) * kNTarget;
-#pragma unroll
-        for (int t = 0; t < TPG; ++t) {
-          if (!active[t]) continue;
-          const double v = sm[tcell[t]];
-          const double a = ok[t] ? v : 0.0;
-#pragma unroll
-          for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a, b[g], acc[t][g]);
+          for (int t = 0; t < TPW; ++t) smem[obase[t] + addrp] = v[t] + accp[t];
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
       }
+    };
+    double bn[KC];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) bn[kc] = Br[(size_t)gstart[0] * KC * 16 + kc * 16];
+    for (int g = 0; g < 13; ++g) {
+      const int qe = gstart[g + 1];
+      for (int q = gstart[g]; q < qe; ++q) {
+        double b[KC];
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) b[kc] = bn[kc];
+        if (q + 1 < npairs) {           // table operands of the next pair, one pair ahead
+          const double* Bn = Br + (size_t)(q + 1) * KC * 16;
+#pragma unroll
+          for (int kc = 0; kc < KC; ++kc) bn[kc] = Bn[kc * 16];
+        }
+        if ((tw[q] & d.mask) == 0) continue;     // every output cell of this pair is absent
+        const int4 o = pr[q];
+        double acc[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = 0.0;
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) acc[t] = mfma4(a[t][kc], b[kc], acc[t]);
+        // finish the previous pair while these products run
+        if (pend) flush();
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) accp[t] = acc[t];
+        addrp = half ? o.y : o.x;
+        wp = !(half && o.w < 0);                  // a single offset: second half idle
+        pend = true;
+      }
+      if (pend) flush();
+      pend = false;
+      __syncthreads();   // the next dz writes other planes of other waves
     }
-    const int xi = lane >> 4, yi = (lane & 15) >> 2, j = lane & 3;
+    // write the round's two components of dM (whole frame) and clear the accumulators
+    for (int c = tid; c < kNCell; c += kBwdThreads) {
+      const int jx = c % kFrame, jy = (c / kFrame) % kFrame, jz = c / (kFrame * kFrame);
+      const bool win = jx >= kWin0 && jx < kWin0 + kWin && jy >= kWin0 && jy < kWin0 + kWin &&
+                       jz >= kWin0 && jz < kWin0 + kWin;
+      const bool pres = win && block_present(d.mask, jx, jy, jz);
+      const int wc = (jx - kWin0) + kWin * (jy - kWin0) + kWin * kWin * (jz - kWin0);
 #pragma unroll
-    for (int t = 0; t < TPG; ++t) {
-      const int x = t * 4 + kWin0 + xi, y = y0 + yi;
-      const bool pres = block_present(d.mask, x, y, z);
-      const int cell = x + kFrame * y + kFrame * kFrame * z;
-#pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        const int k = 4 * g + j;
-        if (k < C) out[(size_t)k * kNCell + cell] = pres ? ldexp(acc[t][g], l2 * order_of(k)) : 0.0;
+      for (int sl = 0; sl < 2; ++sl) {
+        const int k = 2 * r + sl;
+        double v = 0.0;
+        if (win) {
+          v = smem[sl * kAccStride + wc];
+          smem[sl * kAccStride + wc] = 0.0;
+        }
+        if (k < C) out[(size_t)k * kNCell + c] = pres ? ldexp(v, l2 * order_of(k)) : 0.0;
       }
     }
   }
@@ -591,8 +621,9 @@ __global__ void __launch_bounds__(kBwdThreads) m2l_bwd_kernel(
     const WorkItem* __restrict__ items, int count, unsigned* __restrict__ counter,
     const DevDesc* __restrict__ desc, const double* __restrict__ dL, double* __restrict__ dM,
     const double* __restrict__ B2, const double* __restrict__ B3, const double* __restrict__ B4,
-    const int* __restrict__ stencil) {
-  __shared__ double smem[36 * kNTarget];
+    const int4* __restrict__ pairs, int npairs, const int* __restrict__ gstart,
+    const uint32_t* __restrict__ ptouch) {
+  __shared__ double smem[2 * kAccStride];
   __shared__ int s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
@@ -601,9 +632,9 @@ __global__ void __launch_bounds__(kBwdThreads) m2l_bwd_kernel(
     if (item >= count) break;
     const DevDesc d = desc[items[item].sub];
     switch (d.p) {
-      case 2: bwd_subgrid<2>(d, dL, dM, B2, stencil, smem); break;
-      case 3: bwd_subgrid<3>(d, dL, dM, B3, stencil, smem); break;
-      case 4: bwd_subgrid<4>(d, dL, dM, B4, stencil, smem); break;
+      case 2: bwd_subgrid<2>(d, dL, dM, B2, pairs, npairs, gstart, ptouch, smem); break;
+      case 3: bwd_subgrid<3>(d, dL, dM, B3, pairs, npairs, gstart, ptouch, smem); break;
+      case 4: bwd_subgrid<4>(d, dL, dM, B4, pairs, npairs, gstart, ptouch, smem); break;
       default: break;
     }
     __syncthreads();
@@ -635,19 +666,22 @@ __global__ void pack_fwd_kernel(const double* __restrict__ T, int p, double* __r
   lo[i] = (float)(v - (double)h);
 }
 
-// adjoint: [e][kc][g][kk*4 + j] = T_e[4kc+kk][4g+j]
-__global__ void pack_bwd_kernel(const double* __restrict__ T, int p, double* __restrict__ out) {
-  const int C = ncomp(p), NG = (C + 3) / 4, KC = NG;
-  const int total = kNStencil * KC * NG * 16;
+// adjoint: [r][pair][kc][kk*4 + j] = T_{s_(j/2)}[2r + j%2][4kc + kk] (0 for a missing offset)
+__global__ void pack_bwd_kernel(const double* __restrict__ T, int p, const int4* __restrict__ pairs,
+                                int npairs, double* __restrict__ out) {
+  const int C = ncomp(p), KC = (C + 3) / 4, ROUNDS = (C + 1) / 2;
+  const int total = ROUNDS * npairs * KC * 16;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
   const int j = i & 3, kk = (i >> 2) & 3;
   int rest = i >> 4;
-  const int g = rest % NG; rest /= NG;
-  const int kc = rest % KC;
-  const int e = rest / KC;
-  const int n = 4 * kc + kk, k = 4 * g + j;
-  out[i] = (n < C && k < C) ? T[((size_t)e * C + n) * C + k] : 0.0;
+  const int kc = rest % KC; rest /= KC;
+  const int q = rest % npairs;
+  const int r = rest / npairs;
+  const int4 pr = pairs[q];
+  const int so = (j >> 1) ? pr.w : pr.z;
+  const int k = 2 * r + (j & 1), n = 4 * kc + kk;
+  out[i] = (so >= 0 && k < C && n < C) ? T[((size_t)so * C + k) * C + n] : 0.0;
 }
 
 size_t fwd_pack_elems(int p) {
@@ -655,9 +689,40 @@ size_t fwd_pack_elems(int p) {
   return (size_t)ROUNDS * kQuads * 2 * NG * 16;
 }
 
-size_t bwd_pack_elems(int p) {
-  const int C = ncomp(p), NG = (C + 3) / 4;
-  return (size_t)kNStencil * NG * NG * 16;
+size_t bwd_pack_elems(int p, int npairs) {
+  const int C = ncomp(p), KC = (C + 3) / 4, ROUNDS = (C + 1) / 2;
+  return (size_t)ROUNDS * npairs * KC * 16;
+}
+
+// Offsets of one dz paired so that the two never send two cells of a 4x4
+// tile to the same output cell; the pairs are grouped by dz (13 groups).
+void build_pairs(const std::vector<int>& st, std::vector<int4>* pairs, std::vector<int>* gstart) {
+  gstart->clear();
+  for (int dz = -kRad; dz <= kRad; ++dz) {
+    gstart->push_back((int)pairs->size());
+    std::vector<int> ids;
+    for (int i = 0; i < kNStencil; ++i)
+      if (st[3 * i + 2] == dz) ids.push_back(i);
+    std::vector<bool> used(ids.size(), false);
+    for (size_t a = 0; a < ids.size(); ++a) {
+      if (used[a]) continue;
+      used[a] = true;
+      int partner = -1;
+      for (size_t b = ids.size(); b-- > a + 1;) {
+        const int ia = ids[a], ib = ids[b];
+        if (!used[b] && (std::abs(st[3 * ia] - st[3 * ib]) >= 4 || std::abs(st[3 * ia + 1] - st[3 * ib + 1]) >= 4)) {
+          partner = (int)b;
+          break;
+        }
+      }
+      const int s1 = ids[a], s2 = partner >= 0 ? ids[partner] : -1;
+      if (partner >= 0) used[partner] = true;
+      const int o1 = st[3 * s1] + kWin * st[3 * s1 + 1] + kWin * kWin * st[3 * s1 + 2];
+      const int o2 = s2 >= 0 ? st[3 * s2] + kWin * st[3 * s2 + 1] + kWin * kWin * st[3 * s2 + 2] : o1;
+      pairs->push_back(make_int4(o1, o2, s1, s2));
+    }
+  }
+  gstart->push_back((int)pairs->size());
 }
 
 int64_t block_pair_count(uint32_t mask, const std::vector<int>& st) {
@@ -720,6 +785,18 @@ std::vector<WorkItem> build_work_list(const fmm_subgrid* desc, int64_t nsub) {
   return items;
 }
 
+namespace {
+// blocks touched by the 8x8 target plane z shifted by offset o
+uint32_t plane_blocks(const std::vector<int>& st, int z, int o) {
+  const int dx = st[3 * o], dy = st[3 * o + 1], dz = st[3 * o + 2];
+  const int bz = (8 + z + dz) / 8;
+  uint32_t m = 0;
+  for (int bx = (8 + dx) / 8; bx <= (15 + dx) / 8; ++bx)
+    for (int by = (8 + dy) / 8; by <= (15 + dy) / 8; ++by) m |= 1u << (bx + 3 * by + 9 * bz);
+  return m;
+}
+}  // namespace
+
 hipError_t mfma_tables_create(MfmaTables* t, double* const* d_T, const int* d_stencil,
                               hipStream_t s) {
   hipError_t e;
@@ -727,8 +804,40 @@ hipError_t mfma_tables_create(MfmaTables* t, double* const* d_T, const int* d_st
   int dev = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&t->num_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  const std::vector<int> st = host_stencil();
+  // forward: LDS offsets of the offsets, blocks each quad touches per target plane
+  std::vector<int> off(kNStencil);
+  for (int i = 0; i < kNStencil; ++i) off[i] = st[3 * i] + kWin * st[3 * i + 1] + kWin * kWin * st[3 * i + 2];
+  std::vector<uint32_t> touch(8 * kQuads, 0u);
+  for (int z = 0; z < 8; ++z)
+    for (int q = 0; q < kQuads; ++q)
+      for (int o = 4 * q; o < 4 * q + 4; ++o) touch[z * kQuads + q] |= plane_blocks(st, z, o);
+  // adjoint: offset pairs grouped by dz, blocks each pair writes per target plane
+  std::vector<int4> pairs;
+  std::vector<int> gstart;
+  build_pairs(st, &pairs, &gstart);
+  if ((int)pairs.size() > kMaxPairs || gstart.size() != 14) return hipErrorInvalidValue;
+  t->npairs = (int)pairs.size();
+  std::vector<uint32_t> ptouch(8 * pairs.size(), 0u);
+  for (int z = 0; z < 8; ++z)
+    for (size_t q = 0; q < pairs.size(); ++q) {
+      uint32_t m = plane_blocks(st, z, pairs[q].z);
+      if (pairs[q].w >= 0) m |= plane_blocks(st, z, pairs[q].w);
+      ptouch[z * pairs.size() + q] = m;
+    }
+  if ((e = hipMalloc(&t->lds_off, off.size() * sizeof(int))) != hipSuccess) return e;
+  if ((e = hipMalloc(&t->touch, touch.size() * sizeof(uint32_t))) != hipSuccess) return e;
+  if ((e = hipMalloc(&t->pairs, pairs.size() * sizeof(int4))) != hipSuccess) return e;
+  if ((e = hipMalloc(&t->gstart, gstart.size() * sizeof(int))) != hipSuccess) return e;
+  if ((e = hipMalloc(&t->ptouch, ptouch.size() * sizeof(uint32_t))) != hipSuccess) return e;
+  // synchronous copies: the host vectors die at return
+  if ((e = hipMemcpy(t->lds_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMemcpy(t->touch, touch.data(), touch.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMemcpy(t->pairs, pairs.data(), pairs.size() * sizeof(int4), hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMemcpy(t->gstart, gstart.data(), gstart.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMemcpy(t->ptouch, ptouch.data(), ptouch.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess) return e;
   for (int p = 2; p <= kMaxP; ++p) {
-    const size_t nf = fwd_pack_elems(p), nb = bwd_pack_elems(p);
+    const size_t nf = fwd_pack_elems(p), nb = bwd_pack_elems(p, t->npairs);
     if ((e = hipMalloc(&t->fwd[p], nf * sizeof(double))) != hipSuccess) return e;
     if ((e = hipMalloc(&t->fwd_hi[p], nf * sizeof(float))) != hipSuccess) return e;
     if ((e = hipMalloc(&t->fwd_lo[p], nf * sizeof(float))) != hipSuccess) return e;
@@ -737,30 +846,9 @@ hipError_t mfma_tables_create(MfmaTables* t, double* const* d_T, const int* d_st
                        t->fwd[p], t->fwd_hi[p], t->fwd_lo[p]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(pack_bwd_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, d_T[p], p,
-                       t->bwd[p]);
+                       t->pairs, t->npairs, t->bwd[p]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  // LDS offsets of the offsets and the blocks each quad touches per target plane
-  const std::vector<int> st = host_stencil();
-  std::vector<int> off(kNStencil);
-  for (int i = 0; i < kNStencil; ++i) off[i] = st[3 * i] + kWin * st[3 * i + 1] + kWin * kWin * st[3 * i + 2];
-  std::vector<uint32_t> touch(8 * kQuads, 0u);
-  for (int z = 0; z < 8; ++z)
-    for (int q = 0; q < kQuads; ++q) {
-      uint32_t m = 0;
-      for (int o = 4 * q; o < 4 * q + 4; ++o) {
-        const int dx = st[3 * o], dy = st[3 * o + 1], dz = st[3 * o + 2];
-        const int bz = (8 + z + dz) / 8;
-        for (int bx = (8 + dx) / 8; bx <= (15 + dx) / 8; ++bx)
-          for (int by = (8 + dy) / 8; by <= (15 + dy) / 8; ++by) m |= 1u << (bx + 3 * by + 9 * bz);
-      }
-      touch[z * kQuads + q] = m;
-    }
-  if ((e = hipMalloc(&t->lds_off, off.size() * sizeof(int))) != hipSuccess) return e;
-  if ((e = hipMalloc(&t->touch, touch.size() * sizeof(uint32_t))) != hipSuccess) return e;
-  // synchronous copies: the host vectors die at return
-  if ((e = hipMemcpy(t->lds_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) return e;
-  if ((e = hipMemcpy(t->touch, touch.data(), touch.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -775,8 +863,14 @@ void mfma_tables_destroy(MfmaTables* t) {
   }
   if (t->lds_off) (void)hipFree(t->lds_off);
   if (t->touch) (void)hipFree(t->touch);
+  if (t->pairs) (void)hipFree(t->pairs);
+  if (t->gstart) (void)hipFree(t->gstart);
+  if (t->ptouch) (void)hipFree(t->ptouch);
   t->lds_off = nullptr;
   t->touch = nullptr;
+  t->pairs = nullptr;
+  t->gstart = nullptr;
+  t->ptouch = nullptr;
 }
 
 int mfma_num_configs() { return kNumConfigs; }
@@ -823,7 +917,8 @@ hipError_t launch_m2l_mfma_backward(const MfmaTables& t, const WorkList& w, cons
   const int grid = std::min(t.num_cu, w.count);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, w.counter);
   hipLaunchKernelGGL(m2l_bwd_kernel, dim3(grid), dim3(kBwdThreads), 0, s, w.items, w.count, w.counter,
-                     d_desc, dL, dM, t.bwd[2], t.bwd[3], t.bwd[4], t.stencil);
+                     d_desc, dL, dM, t.bwd[2], t.bwd[3], t.bwd[4], t.pairs, t.npairs, t.gstart,
+                     t.ptouch);
   return hipGetLastError();
 }
 
