@@ -2,9 +2,9 @@
  * fmm.h -- C ABI of the MI355X (gfx950) same-level FMM interaction library.
  *
  * The operations are the steps of the gravity solver's cell-to-cell
- * interaction on N = 8 sub-grids (paper Sec. IV, "Octo-Tiger": FMM gravity
+ * interaction on N = 8 sub-grids (paper Sec. IV-C, "Octo-Tiger": FMM gravity
  * co-located with the 8^3 hydro sub-grids, cells carrying multipole moments;
- * Sec. VI, "Usage of multiple HPX tasks per Kokkos kernel invocation": the
+ * Sec. VII-C, "Usage of multiple HPX tasks per Kokkos kernel invocation": the
  * three-step gravity iteration whose second step is the same-level
  * cell-to-cell "Multipole" interaction). The paper gives no formulas; the
  * definitions below are the Cartesian Taylor expansion of 1/|x - y|:

@@ -8,9 +8,9 @@ is the seeded input generator in ``synth/``, which holds none of the method's
 arithmetic.
 
 What it computes follows the gravity solver described in the paper's
-Octo-Tiger subsection (Sec. IV, "Octo-Tiger"): cell moments on N^3 = 8^3
+Octo-Tiger subsection (Sec. IV-C, "Octo-Tiger"): cell moments on N^3 = 8^3
 sub-grids co-located with the hydro grid, and the same-level cell-to-cell
-interaction step of the three-step gravity iteration (Sec. VI, "Usage of
+interaction step of the three-step gravity iteration (Sec. VII-C, "Usage of
 multiple HPX tasks per Kokkos kernel invocation"). The paper gives no
 formulas; the definitions written out here are textbook Cartesian FMM and are
 listed, with every reading taken where the paper is silent, in the design doc.

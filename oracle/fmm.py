@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring): slow, plain, float64.
 
-Geometry (one sub-grid, the paper's N = 8 sub-grid of Sec. IV "Octo-Tiger"):
+Geometry (one sub-grid, the paper's N = 8 sub-grid of Sec. IV-C "Octo-Tiger"):
   * a frame of 24^3 cells j = (x, y, z), x fastest, linear index x + 24 y + 576 z:
     the 8^3 target sub-grid in the middle plus its 26 same-level neighbours;
   * cell j spans [j h, (j + 1) h) per axis, centre c_j = (j + 1/2) h;

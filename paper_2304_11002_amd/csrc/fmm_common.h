@@ -1,7 +1,7 @@
 // Shared definitions of the HIP library (host and device). gfx950 only.
 //
 // Geometry of one sub-grid (the N = 8 sub-grid of the paper's Octo-Tiger
-// subsection, Sec. IV): a 24^3 frame of cells, x fastest, linear index
+// subsection, Sec. IV-C): a 24^3 frame of cells, x fastest, linear index
 // x + 24 y + 576 z; the 8^3 target block is [8,16)^3; neighbour block of a
 // cell is j / 8 per axis with mask bit bx + 3 by + 9 bz. The interaction
 // stencil is the shell 5 <= |d|^2 <= 36 (892 offsets), so only the 20^3

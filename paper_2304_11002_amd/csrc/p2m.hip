@@ -4,7 +4,7 @@
 //   M_k(j)   = sum_i m_i a_i^k / k!,      a_i = y_i - c_j, c_j = (j + 1/2) h
 //   dm_i     = sum_k dM_k(j) a_i^k / k!
 //
-// The paper approximates each leaf cell by a monopole at its centre (Sec. IV,
+// The paper approximates each leaf cell by a monopole at its centre (Sec. IV-C,
 // "Octo-Tiger"); that is the a = 0 case of these moments.
 #include "kernels.h"
 

@@ -15,8 +15,8 @@ spacings, masks, loss weights, finite-difference entries) come from
 default_rng([s, 2**31 - 1]).
 
 The workloads stand in for the paper's production runs (thousands to
-millions of 8^3 sub-grids per step, Sec. IV "HPX-Kokkos"), whose inputs are
-not available; shapes follow the Octo-Tiger sub-grid layout (Sec. IV
+millions of 8^3 sub-grids per step, Sec. IV-B "Kokkos and HPX-Kokkos"), whose inputs are
+not available; shapes follow the Octo-Tiger sub-grid layout (Sec. IV-C
 "Octo-Tiger").
 """
 

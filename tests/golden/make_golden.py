@@ -27,7 +27,7 @@ def main():
         f.write("# Derivatives of 1/r at integer points: D_m(d) = P_m(d) / (|d|^2)^|m| / sqrt(|d|^2)\n")
         f.write("# The potential of a point mass and its Cartesian derivatives are what the\n")
         f.write("# cell-to-cell multipole interactions of the gravity solver evaluate\n")
-        f.write("# (Sec. IV, Octo-Tiger: FMM gravity on the 8^3 sub-grids).\n")
+        f.write("# (Sec. IV-C, Octo-Tiger: FMM gravity on the 8^3 sub-grids).\n")
         f.write("# Exact integer numerator P_m(d) by symbolic differentiation; value rounded once.\n")
         f.write("# columns: dx dy dz mx my mz numerator value\n")
         for d in POINTS:
