@@ -91,6 +91,7 @@ struct DescEntry {
   int* d_ids[kMaxP + 1] = {};     // reference kernels: sub-grids per order
   int count[kMaxP + 1] = {};
   WorkList work;                  // matrix-core kernels
+  bool part_even = true;          // every part_off even: particle blocks 16-byte aligned
   int tuned[2] = {-1, -1};        // autotuned configuration per precision
   hipEvent_t ready = nullptr;     // upload finished
   hipEvent_t last_launch = nullptr;
@@ -257,7 +258,10 @@ fmm_status get_desc(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, hipStre
   e->last_use = ++ctx->clock;
   // layout: descriptors | ids per order | work list
   std::vector<int> ids[kMaxP + 1];
-  for (int64_t b = 0; b < nsub; ++b) ids[desc[b].p].push_back((int)b);
+  for (int64_t b = 0; b < nsub; ++b) {
+    ids[desc[b].p].push_back((int)b);
+    if (desc[b].part_off & 1) e->part_even = false;
+  }
   std::vector<WorkItem> items = build_work_list(desc, nsub);
   size_t off_desc = 0;
   size_t off = align_up(nbytes, 256);
@@ -437,7 +441,7 @@ fmm_status fmm_p2m(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const do
   HIP_TRY(ctx, guard.err);
   DescEntry* e = nullptr;
   CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
-  HIP_TRY(ctx, launch_p2m(e->d_desc, nsub, pos, mass, ppc, M, s));
+  HIP_TRY(ctx, launch_p2m(e->d_desc, nsub, pos, mass, ppc, M, e->part_even, s));
   return mark_used(ctx, e, s);
 }
 
@@ -456,7 +460,7 @@ fmm_status fmm_p2m_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
   HIP_TRY(ctx, guard.err);
   DescEntry* e = nullptr;
   CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
-  HIP_TRY(ctx, launch_p2m_backward(e->d_desc, nsub, pos, ppc, dM, dmass, s));
+  HIP_TRY(ctx, launch_p2m_backward(e->d_desc, nsub, pos, ppc, dM, dmass, e->part_even, s));
   return mark_used(ctx, e, s);
 }
 

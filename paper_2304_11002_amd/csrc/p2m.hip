@@ -118,24 +118,186 @@ __global__ void __launch_bounds__(kP2MThreads) p2m_bwd_kernel(const DevDesc* __r
   }
 }
 
+// ---------------------------------------------------------------------------
+// 8 particles per cell: the workgroup's 256 cells of particles are read with
+// coalesced 16-byte loads into LDS (cell stride padded to 25 doubles against
+// bank conflicts), then each thread works on its own cell from LDS.
+// Particles of absent blocks are not read.
+// ---------------------------------------------------------------------------
+
+constexpr int kPpc8 = 8;
+constexpr int kPosStride = 3 * kPpc8 + 1;   // doubles per cell in LDS
+
+__device__ __forceinline__ bool cell_present(uint32_t mask, int cell) {
+  return block_present(mask, cell % kFrame, (cell / kFrame) % kFrame, cell / (kFrame * kFrame));
+}
+
+__device__ __forceinline__ void stage_pos8(const DevDesc& d, const double* __restrict__ pos, int cell0,
+                                           double* s_pos) {
+  // 256 cells x 24 doubles = 3072 double2, 12 per thread
+  const double2* src = reinterpret_cast<const double2*>(pos + 3 * (d.part_off + (int64_t)cell0 * kPpc8));
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    const int v = threadIdx.x + i * kP2MThreads;
+    const int c = v / 12, w = v % 12;
+    if (cell_present(d.mask, cell0 + c)) {
+      const double2 x = src[v];
+      s_pos[c * kPosStride + 2 * w] = x.x;
+      s_pos[c * kPosStride + 2 * w + 1] = x.y;
+    }
+  }
+}
+
+template <int P>
+__device__ void p2m_cell8(const DevDesc& d, const double* __restrict__ pos,
+                          const double* __restrict__ mass, double* __restrict__ M, int cell0,
+                          double* s_pos, double* s_mass) {
+  constexpr int C = ncomp(P);
+  stage_pos8(d, pos, cell0, s_pos);
+  const double2* msrc = reinterpret_cast<const double2*>(mass + d.part_off + (int64_t)cell0 * kPpc8);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int v = threadIdx.x + i * kP2MThreads;
+    if (cell_present(d.mask, cell0 + v / 4)) {
+      const double2 x = msrc[v];
+      s_mass[2 * v] = x.x;
+      s_mass[2 * v + 1] = x.y;
+    }
+  }
+  __syncthreads();
+  const int cell = cell0 + threadIdx.x;
+  const int jx = cell % kFrame, jy = (cell / kFrame) % kFrame, jz = cell / (kFrame * kFrame);
+  double* out = M + d.m_off + cell;
+  if (!block_present(d.mask, jx, jy, jz)) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[(size_t)c * kNCell] = 0.0;
+    return;
+  }
+  const double h = ldexp(1.0, -d.log2_inv_h);
+  const double cx = (jx + 0.5) * h, cy = (jy + 0.5) * h, cz = (jz + 0.5) * h;
+  double acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = 0.0;
+  const double* y = s_pos + threadIdx.x * kPosStride;
+#pragma unroll 2
+  for (int i = 0; i < kPpc8; ++i) {
+    const double m = s_mass[threadIdx.x * kPpc8 + i];
+    double mono[C];
+    monomials<P>(y[3 * i] - cx, y[3 * i + 1] - cy, y[3 * i + 2] - cz, mono);
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = __builtin_fma(m, mono[c], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) out[(size_t)c * kNCell] = acc[c];
+}
+
+__global__ void __launch_bounds__(kP2MThreads) p2m8_kernel(const DevDesc* __restrict__ desc,
+                                                           const double* __restrict__ pos,
+                                                           const double* __restrict__ mass,
+                                                           double* __restrict__ M) {
+  __shared__ double s_pos[kP2MThreads * kPosStride];
+  __shared__ double s_mass[kP2MThreads * kPpc8];
+  const int b = blockIdx.x / kCellBlocks;
+  const int cell0 = (blockIdx.x % kCellBlocks) * kP2MThreads;
+  const DevDesc d = desc[b];
+  switch (d.p) {
+    case 2: p2m_cell8<2>(d, pos, mass, M, cell0, s_pos, s_mass); break;
+    case 3: p2m_cell8<3>(d, pos, mass, M, cell0, s_pos, s_mass); break;
+    case 4: p2m_cell8<4>(d, pos, mass, M, cell0, s_pos, s_mass); break;
+    default: break;
+  }
+}
+
+template <int P>
+__device__ void p2m_bwd_cell8(const DevDesc& d, const double* __restrict__ pos,
+                              const double* __restrict__ dM, double* __restrict__ dmass, int cell0,
+                              double* s_pos, double* s_out) {
+  constexpr int C = ncomp(P);
+  stage_pos8(d, pos, cell0, s_pos);
+  __syncthreads();
+  const int cell = cell0 + threadIdx.x;
+  const int jx = cell % kFrame, jy = (cell / kFrame) % kFrame, jz = cell / (kFrame * kFrame);
+  if (!block_present(d.mask, jx, jy, jz)) {
+#pragma unroll
+    for (int i = 0; i < kPpc8; ++i) s_out[threadIdx.x * (kPpc8 + 1) + i] = 0.0;
+  } else {
+    double g[C];
+    const double* src = dM + d.m_off + cell;
+#pragma unroll
+    for (int c = 0; c < C; ++c) g[c] = src[(size_t)c * kNCell];
+    const double h = ldexp(1.0, -d.log2_inv_h);
+    const double cx = (jx + 0.5) * h, cy = (jy + 0.5) * h, cz = (jz + 0.5) * h;
+    const double* y = s_pos + threadIdx.x * kPosStride;
+#pragma unroll 2
+    for (int i = 0; i < kPpc8; ++i) {
+      double mono[C];
+      monomials<P>(y[3 * i] - cx, y[3 * i + 1] - cy, y[3 * i + 2] - cz, mono);
+      double sum = 0.0;
+#pragma unroll
+      for (int c = 0; c < C; ++c) sum = __builtin_fma(g[c], mono[c], sum);
+      s_out[threadIdx.x * (kPpc8 + 1) + i] = sum;
+    }
+  }
+  __syncthreads();
+  // coalesced write of the workgroup's 256 x 8 gradients
+  double2* dst = reinterpret_cast<double2*>(dmass + d.part_off + (int64_t)cell0 * kPpc8);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int v = threadIdx.x + i * kP2MThreads;
+    const int c = v / 4, w = v % 4;
+    dst[v] = make_double2(s_out[c * (kPpc8 + 1) + 2 * w], s_out[c * (kPpc8 + 1) + 2 * w + 1]);
+  }
+}
+
+__global__ void __launch_bounds__(kP2MThreads) p2m8_bwd_kernel(const DevDesc* __restrict__ desc,
+                                                               const double* __restrict__ pos,
+                                                               const double* __restrict__ dM,
+                                                               double* __restrict__ dmass) {
+  __shared__ double s_pos[kP2MThreads * kPosStride];
+  __shared__ double s_out[kP2MThreads * (kPpc8 + 1)];
+  const int b = blockIdx.x / kCellBlocks;
+  const int cell0 = (blockIdx.x % kCellBlocks) * kP2MThreads;
+  const DevDesc d = desc[b];
+  switch (d.p) {
+    case 2: p2m_bwd_cell8<2>(d, pos, dM, dmass, cell0, s_pos, s_out); break;
+    case 3: p2m_bwd_cell8<3>(d, pos, dM, dmass, cell0, s_pos, s_out); break;
+    case 4: p2m_bwd_cell8<4>(d, pos, dM, dmass, cell0, s_pos, s_out); break;
+    default: break;
+  }
+}
+
+// The 8-particle kernels use 16-byte loads: they need 16-byte aligned particle
+// arrays (always true for part_off of a whole sub-grid and hipMalloc'd buffers).
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
 hipError_t launch_p2m(const DevDesc* d_desc, int64_t nsub, const double* pos, const double* mass,
-                      int ppc, double* M, hipStream_t s) {
+                      int ppc, double* M, bool all_aligned, hipStream_t s) {
+  const bool fast = ppc == kPpc8 && all_aligned && aligned16(pos) && aligned16(mass);
   const int64_t per_launch = (int64_t)(0x7fffffff / kCellBlocks);
   for (int64_t b0 = 0; b0 < nsub; b0 += per_launch) {
     const int64_t n = nsub - b0 < per_launch ? nsub - b0 : per_launch;
-    hipLaunchKernelGGL(p2m_kernel, dim3((unsigned)(n * kCellBlocks)), dim3(kP2MThreads), 0, s,
-                       d_desc + b0, pos, mass, ppc, M);
+    if (fast)
+      hipLaunchKernelGGL(p2m8_kernel, dim3((unsigned)(n * kCellBlocks)), dim3(kP2MThreads), 0, s,
+                         d_desc + b0, pos, mass, M);
+    else
+      hipLaunchKernelGGL(p2m_kernel, dim3((unsigned)(n * kCellBlocks)), dim3(kP2MThreads), 0, s,
+                         d_desc + b0, pos, mass, ppc, M);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_p2m_backward(const DevDesc* d_desc, int64_t nsub, const double* pos, int ppc,
-                               const double* dM, double* dmass, hipStream_t s) {
+                               const double* dM, double* dmass, bool all_aligned, hipStream_t s) {
+  const bool fast = ppc == kPpc8 && all_aligned && aligned16(pos) && aligned16(dmass);
   const int64_t per_launch = (int64_t)(0x7fffffff / kCellBlocks);
   for (int64_t b0 = 0; b0 < nsub; b0 += per_launch) {
     const int64_t n = nsub - b0 < per_launch ? nsub - b0 : per_launch;
-    hipLaunchKernelGGL(p2m_bwd_kernel, dim3((unsigned)(n * kCellBlocks)), dim3(kP2MThreads), 0, s,
-                       d_desc + b0, pos, ppc, dM, dmass);
+    if (fast)
+      hipLaunchKernelGGL(p2m8_bwd_kernel, dim3((unsigned)(n * kCellBlocks)), dim3(kP2MThreads), 0, s,
+                         d_desc + b0, pos, dM, dmass);
+    else
+      hipLaunchKernelGGL(p2m_bwd_kernel, dim3((unsigned)(n * kCellBlocks)), dim3(kP2MThreads), 0, s,
+                         d_desc + b0, pos, ppc, dM, dmass);
   }
   return hipGetLastError();
 }

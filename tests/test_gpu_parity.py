@@ -259,3 +259,26 @@ def test_split_fp32_matches_expectation_model_scale(ctx, torch):
     assert gpu.max() < 10 * emu.max() and np.median(gpu) < 10 * np.median(emu)
     # and it is far from float64 agreement: the split really ran in float32
     assert gpu.max() > 1e-11
+
+
+def test_p2m_generic_particle_count_and_adjoint(ctx, torch):
+    # 3 particles per cell takes the general P2M kernels (8 takes the LDS-staged ones)
+    w = synth.Workload("ppc3", 23, np.array([4, 2], np.int32), np.array([1, 0], np.int32),
+                       np.array([synth.FULL_MASK, (1 << 13) | (1 << 4) | (1 << 22)], np.uint32), ppc=3)
+    desc, pos, mass, M, L = forward(ctx, torch, w, [0, 1], MFMA)
+    Mg = split_views(M.cpu().numpy(), desc, "M")
+    rng = np.random.default_rng(5)
+    G = rng.standard_normal(M.numel())
+    dmass = torch.full((2 * fmm.NCELL * 3,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.p2m_backward(desc, to_dev(pos), 3, to_dev(G), dmass)
+    torch.cuda.synchronize()
+    gm = dmass.cpu().numpy().reshape(2, fmm.NCELL, 3)
+    Gv = split_views(G, desc, "M")
+    for b in range(2):
+        p, h, mask = int(w.p[b]), w.h(b), int(w.mask[b])
+        Mo = O.p2m(pos[b], mass[b], p, h, mask)
+        assert_close(Mg[b], Mo, moment_abs_scale(pos[b], mass[b], p, h, mask), 1e-14, "M ppc3")
+        go = O.p2m_adjoint(pos[b], Gv[b], p, h, mask)
+        c = O.cell_centres(h)[:, None, :]
+        scale = O.p2m_adjoint(c + np.abs(pos[b] - c), np.abs(Gv[b]), p, h, mask)
+        assert_close(gm[b], go, scale, 1e-14, "dmass ppc3")
