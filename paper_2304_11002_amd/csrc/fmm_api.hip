@@ -523,6 +523,8 @@ fmm_status fmm_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const do
   if (prec != FMM_FP64 && prec != FMM_SPLIT_FP32) return set_err(ctx, FMM_EINVAL, "unknown precision");
   if (prec == FMM_SPLIT_FP32 && ctx->m2l_kernel == 1)
     return set_err(ctx, FMM_EINVAL, "the reference kernel computes FMM_FP64 only");
+  if (ctx->m2l_kernel != 1 && ctx->tile_config >= 0 && !mfma_config_supports(ctx->tile_config, prec))
+    return set_err(ctx, FMM_EINVAL, "FMM_OPT_TILE_CONFIG selects a configuration of the other precision");
   if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
   if (nsub == 0) return FMM_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -282,3 +282,31 @@ def test_p2m_generic_particle_count_and_adjoint(ctx, torch):
         c = O.cell_centres(h)[:, None, :]
         scale = O.p2m_adjoint(c + np.abs(pos[b] - c), np.abs(Gv[b]), p, h, mask)
         assert_close(gm[b], go, scale, 1e-14, "dmass ppc3")
+
+
+def test_every_tile_configuration_agrees_bitwise(ctx, torch):
+    # all FP64 configurations do the same products in the same order: identical L
+    w = synth.config(3, nsub=5)
+    desc, pos, mass, M, L0 = forward(ctx, torch, w, range(5), MFMA)
+    Lg = split_views(L0.cpu().numpy(), desc, "L")
+    for b in range(5):
+        _, Lo, La = oracle_subgrid(w, b, pos[b], mass[b])
+        assert_close(Lg[b], Lo, La, TOL, "sub-grid %d" % b)
+    cfg = 0
+    while True:
+        try:
+            ctx.set_option(fmm.FMM_OPT_TILE_CONFIG, cfg)
+        except fmm.FMMError:
+            break
+        L = torch.full_like(L0, float("nan"))
+        try:
+            ctx.m2l(desc, M, L, fmm.FMM_FP64)
+        except fmm.FMMError as e:
+            assert e.status == fmm.FMM_EINVAL   # a split-precision configuration
+            cfg += 1
+            continue
+        torch.cuda.synchronize()
+        assert torch.equal(L, L0), cfg
+        cfg += 1
+    ctx.set_option(fmm.FMM_OPT_TILE_CONFIG, -1)
+    assert cfg >= 4
