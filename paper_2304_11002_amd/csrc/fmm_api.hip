@@ -441,7 +441,7 @@ fmm_status fmm_p2m(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const do
   HIP_TRY(ctx, guard.err);
   DescEntry* e = nullptr;
   CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
-  HIP_TRY(ctx, launch_p2m(e->d_desc, nsub, pos, mass, ppc, M, e->part_even, s));
+  HIP_TRY(ctx, launch_p2m(e->d_desc, nsub, e->d_ids, e->count, pos, mass, ppc, M, e->part_even, s));
   return mark_used(ctx, e, s);
 }
 
@@ -460,7 +460,7 @@ fmm_status fmm_p2m_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
   HIP_TRY(ctx, guard.err);
   DescEntry* e = nullptr;
   CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
-  HIP_TRY(ctx, launch_p2m_backward(e->d_desc, nsub, pos, ppc, dM, dmass, e->part_even, s));
+  HIP_TRY(ctx, launch_p2m_backward(e->d_desc, nsub, e->d_ids, e->count, pos, ppc, dM, dmass, e->part_even, s));
   return mark_used(ctx, e, s);
 }
 

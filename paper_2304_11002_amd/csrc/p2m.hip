@@ -119,14 +119,18 @@ __global__ void __launch_bounds__(kP2MThreads) p2m_bwd_kernel(const DevDesc* __r
 }
 
 // ---------------------------------------------------------------------------
-// 8 particles per cell: the workgroup's 256 cells of particles are read with
+// 8 particles per cell: one kernel per order (so p = 3 is not held to p = 4's
+// registers), 128-cell workgroups. The workgroup's particles are read with
 // coalesced 16-byte loads into LDS (cell stride padded to 25 doubles against
 // bank conflicts), then each thread works on its own cell from LDS.
 // Particles of absent blocks are not read.
 // ---------------------------------------------------------------------------
 
 constexpr int kPpc8 = 8;
-constexpr int kPosStride = 3 * kPpc8 + 1;   // doubles per cell in LDS
+constexpr int kT8 = 128;                     // cells (threads) per workgroup
+constexpr int kCellBlocks8 = kNCell / kT8;   // 108
+constexpr int kPosStride = 3 * kPpc8 + 1;    // doubles per cell in LDS
+static_assert(kNCell % kT8 == 0, "cells per block");
 
 __device__ __forceinline__ bool cell_present(uint32_t mask, int cell) {
   return block_present(mask, cell % kFrame, (cell / kFrame) % kFrame, cell / (kFrame * kFrame));
@@ -134,11 +138,11 @@ __device__ __forceinline__ bool cell_present(uint32_t mask, int cell) {
 
 __device__ __forceinline__ void stage_pos8(const DevDesc& d, const double* __restrict__ pos, int cell0,
                                            double* s_pos) {
-  // 256 cells x 24 doubles = 3072 double2, 12 per thread
+  // 128 cells x 24 doubles = 1536 double2, 12 per thread
   const double2* src = reinterpret_cast<const double2*>(pos + 3 * (d.part_off + (int64_t)cell0 * kPpc8));
 #pragma unroll
   for (int i = 0; i < 12; ++i) {
-    const int v = threadIdx.x + i * kP2MThreads;
+    const int v = threadIdx.x + i * kT8;
     const int c = v / 12, w = v % 12;
     if (cell_present(d.mask, cell0 + c)) {
       const double2 x = src[v];
@@ -149,15 +153,21 @@ __device__ __forceinline__ void stage_pos8(const DevDesc& d, const double* __res
 }
 
 template <int P>
-__device__ void p2m_cell8(const DevDesc& d, const double* __restrict__ pos,
-                          const double* __restrict__ mass, double* __restrict__ M, int cell0,
-                          double* s_pos, double* s_mass) {
+__global__ void __launch_bounds__(kT8) p2m8_kernel(const DevDesc* __restrict__ desc,
+                                                   const int* __restrict__ ids,
+                                                   const double* __restrict__ pos,
+                                                   const double* __restrict__ mass,
+                                                   double* __restrict__ M) {
   constexpr int C = ncomp(P);
+  __shared__ double s_pos[kT8 * kPosStride];
+  __shared__ double s_mass[kT8 * kPpc8];
+  const DevDesc d = desc[ids[blockIdx.x / kCellBlocks8]];
+  const int cell0 = (blockIdx.x % kCellBlocks8) * kT8;
   stage_pos8(d, pos, cell0, s_pos);
   const double2* msrc = reinterpret_cast<const double2*>(mass + d.part_off + (int64_t)cell0 * kPpc8);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int v = threadIdx.x + i * kP2MThreads;
+    const int v = threadIdx.x + i * kT8;
     if (cell_present(d.mask, cell0 + v / 4)) {
       const double2 x = msrc[v];
       s_mass[2 * v] = x.x;
@@ -191,28 +201,17 @@ __device__ void p2m_cell8(const DevDesc& d, const double* __restrict__ pos,
   for (int c = 0; c < C; ++c) out[(size_t)c * kNCell] = acc[c];
 }
 
-__global__ void __launch_bounds__(kP2MThreads) p2m8_kernel(const DevDesc* __restrict__ desc,
-                                                           const double* __restrict__ pos,
-                                                           const double* __restrict__ mass,
-                                                           double* __restrict__ M) {
-  __shared__ double s_pos[kP2MThreads * kPosStride];
-  __shared__ double s_mass[kP2MThreads * kPpc8];
-  const int b = blockIdx.x / kCellBlocks;
-  const int cell0 = (blockIdx.x % kCellBlocks) * kP2MThreads;
-  const DevDesc d = desc[b];
-  switch (d.p) {
-    case 2: p2m_cell8<2>(d, pos, mass, M, cell0, s_pos, s_mass); break;
-    case 3: p2m_cell8<3>(d, pos, mass, M, cell0, s_pos, s_mass); break;
-    case 4: p2m_cell8<4>(d, pos, mass, M, cell0, s_pos, s_mass); break;
-    default: break;
-  }
-}
-
 template <int P>
-__device__ void p2m_bwd_cell8(const DevDesc& d, const double* __restrict__ pos,
-                              const double* __restrict__ dM, double* __restrict__ dmass, int cell0,
-                              double* s_pos, double* s_out) {
+__global__ void __launch_bounds__(kT8) p2m8_bwd_kernel(const DevDesc* __restrict__ desc,
+                                                       const int* __restrict__ ids,
+                                                       const double* __restrict__ pos,
+                                                       const double* __restrict__ dM,
+                                                       double* __restrict__ dmass) {
   constexpr int C = ncomp(P);
+  __shared__ double s_pos[kT8 * kPosStride];
+  __shared__ double s_out[kT8 * (kPpc8 + 1)];
+  const DevDesc d = desc[ids[blockIdx.x / kCellBlocks8]];
+  const int cell0 = (blockIdx.x % kCellBlocks8) * kT8;
   stage_pos8(d, pos, cell0, s_pos);
   __syncthreads();
   const int cell = cell0 + threadIdx.x;
@@ -239,30 +238,13 @@ __device__ void p2m_bwd_cell8(const DevDesc& d, const double* __restrict__ pos,
     }
   }
   __syncthreads();
-  // coalesced write of the workgroup's 256 x 8 gradients
+  // coalesced write of the workgroup's 128 x 8 gradients
   double2* dst = reinterpret_cast<double2*>(dmass + d.part_off + (int64_t)cell0 * kPpc8);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int v = threadIdx.x + i * kP2MThreads;
+    const int v = threadIdx.x + i * kT8;
     const int c = v / 4, w = v % 4;
     dst[v] = make_double2(s_out[c * (kPpc8 + 1) + 2 * w], s_out[c * (kPpc8 + 1) + 2 * w + 1]);
-  }
-}
-
-__global__ void __launch_bounds__(kP2MThreads) p2m8_bwd_kernel(const DevDesc* __restrict__ desc,
-                                                               const double* __restrict__ pos,
-                                                               const double* __restrict__ dM,
-                                                               double* __restrict__ dmass) {
-  __shared__ double s_pos[kP2MThreads * kPosStride];
-  __shared__ double s_out[kP2MThreads * (kPpc8 + 1)];
-  const int b = blockIdx.x / kCellBlocks;
-  const int cell0 = (blockIdx.x % kCellBlocks) * kP2MThreads;
-  const DevDesc d = desc[b];
-  switch (d.p) {
-    case 2: p2m_bwd_cell8<2>(d, pos, dM, dmass, cell0, s_pos, s_out); break;
-    case 3: p2m_bwd_cell8<3>(d, pos, dM, dmass, cell0, s_pos, s_out); break;
-    case 4: p2m_bwd_cell8<4>(d, pos, dM, dmass, cell0, s_pos, s_out); break;
-    default: break;
   }
 }
 
@@ -270,34 +252,55 @@ __global__ void __launch_bounds__(kP2MThreads) p2m8_bwd_kernel(const DevDesc* __
 // arrays (always true for part_off of a whole sub-grid and hipMalloc'd buffers).
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-hipError_t launch_p2m(const DevDesc* d_desc, int64_t nsub, const double* pos, const double* mass,
-                      int ppc, double* M, bool all_aligned, hipStream_t s) {
+hipError_t launch_p2m(const DevDesc* d_desc, int64_t nsub, const int* const* d_ids, const int* counts,
+                      const double* pos, const double* mass, int ppc, double* M, bool all_aligned,
+                      hipStream_t s) {
   const bool fast = ppc == kPpc8 && all_aligned && aligned16(pos) && aligned16(mass);
+  if (fast) {
+    // one launch per order present, over that order's sub-grids
+    const int64_t per_launch = (int64_t)(0x7fffffff / kCellBlocks8);
+    for (int p = 2; p <= kMaxP; ++p) {
+      for (int64_t b0 = 0; b0 < counts[p]; b0 += per_launch) {
+        const int64_t n = counts[p] - b0 < per_launch ? counts[p] - b0 : per_launch;
+        const dim3 grid((unsigned)(n * kCellBlocks8));
+        if (p == 2) hipLaunchKernelGGL(p2m8_kernel<2>, grid, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, pos, mass, M);
+        if (p == 3) hipLaunchKernelGGL(p2m8_kernel<3>, grid, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, pos, mass, M);
+        if (p == 4) hipLaunchKernelGGL(p2m8_kernel<4>, grid, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, pos, mass, M);
+      }
+    }
+    return hipGetLastError();
+  }
   const int64_t per_launch = (int64_t)(0x7fffffff / kCellBlocks);
   for (int64_t b0 = 0; b0 < nsub; b0 += per_launch) {
     const int64_t n = nsub - b0 < per_launch ? nsub - b0 : per_launch;
-    if (fast)
-      hipLaunchKernelGGL(p2m8_kernel, dim3((unsigned)(n * kCellBlocks)), dim3(kP2MThreads), 0, s,
-                         d_desc + b0, pos, mass, M);
-    else
-      hipLaunchKernelGGL(p2m_kernel, dim3((unsigned)(n * kCellBlocks)), dim3(kP2MThreads), 0, s,
-                         d_desc + b0, pos, mass, ppc, M);
+    hipLaunchKernelGGL(p2m_kernel, dim3((unsigned)(n * kCellBlocks)), dim3(kP2MThreads), 0, s,
+                       d_desc + b0, pos, mass, ppc, M);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_p2m_backward(const DevDesc* d_desc, int64_t nsub, const double* pos, int ppc,
-                               const double* dM, double* dmass, bool all_aligned, hipStream_t s) {
+hipError_t launch_p2m_backward(const DevDesc* d_desc, int64_t nsub, const int* const* d_ids,
+                               const int* counts, const double* pos, int ppc, const double* dM,
+                               double* dmass, bool all_aligned, hipStream_t s) {
   const bool fast = ppc == kPpc8 && all_aligned && aligned16(pos) && aligned16(dmass);
+  if (fast) {
+    const int64_t per_launch = (int64_t)(0x7fffffff / kCellBlocks8);
+    for (int p = 2; p <= kMaxP; ++p) {
+      for (int64_t b0 = 0; b0 < counts[p]; b0 += per_launch) {
+        const int64_t n = counts[p] - b0 < per_launch ? counts[p] - b0 : per_launch;
+        const dim3 grid((unsigned)(n * kCellBlocks8));
+        if (p == 2) hipLaunchKernelGGL(p2m8_bwd_kernel<2>, grid, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, pos, dM, dmass);
+        if (p == 3) hipLaunchKernelGGL(p2m8_bwd_kernel<3>, grid, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, pos, dM, dmass);
+        if (p == 4) hipLaunchKernelGGL(p2m8_bwd_kernel<4>, grid, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, pos, dM, dmass);
+      }
+    }
+    return hipGetLastError();
+  }
   const int64_t per_launch = (int64_t)(0x7fffffff / kCellBlocks);
   for (int64_t b0 = 0; b0 < nsub; b0 += per_launch) {
     const int64_t n = nsub - b0 < per_launch ? nsub - b0 : per_launch;
-    if (fast)
-      hipLaunchKernelGGL(p2m8_bwd_kernel, dim3((unsigned)(n * kCellBlocks)), dim3(kP2MThreads), 0, s,
-                         d_desc + b0, pos, dM, dmass);
-    else
-      hipLaunchKernelGGL(p2m_bwd_kernel, dim3((unsigned)(n * kCellBlocks)), dim3(kP2MThreads), 0, s,
-                         d_desc + b0, pos, ppc, dM, dmass);
+    hipLaunchKernelGGL(p2m_bwd_kernel, dim3((unsigned)(n * kCellBlocks)), dim3(kP2MThreads), 0, s,
+                       d_desc + b0, pos, ppc, dM, dmass);
   }
   return hipGetLastError();
 }
