@@ -30,6 +30,8 @@ static_assert(kNStencil % 4 == 0, "offset quads");
 struct MfmaTables {
   // forward, per order p: [rounds][quad][comp of pair][n-group][kk*4 + j] float64
   double* fwd[kMaxP + 1] = {};
+  // forward with LDS-staged tables, per order p: [rounds][quad][n-group][kk*4 + j][comp of pair]
+  double* fwdl[kMaxP + 1] = {};
   // split precision, per order p: the same layout, float32 hi and lo parts
   float* fwd_hi[kMaxP + 1] = {};
   float* fwd_lo[kMaxP + 1] = {};

@@ -216,6 +216,194 @@ __global__ void __launch_bounds__(WAVES * 64) m2l_fwd_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// forward, table operands staged in LDS
+// ---------------------------------------------------------------------------
+//
+// Same products and order as fwd_subgrid. Instead of every wave loading its
+// table operands from L2 (16 distinct values per 64-lane load, replicated over
+// the four MFMA blocks, which keeps the texture-address path ~70% busy), the
+// workgroup copies the tables of a chunk of offset quads into the LDS left over
+// by the window (double-buffered, one barrier per chunk) and each wave reads
+// them with broadcast ds_read_b128 (both components of a column group at once).
+// Table layout for this form: [round][quad][group][kk*4 + j][component].
+
+template <int P>
+struct BlShape {
+  static constexpr int C = ncomp(P);
+  static constexpr int NG = (C + 3) / 4;
+  static constexpr int QC = P == 4 ? 6 : 12;         // quads per staged chunk
+  static constexpr int CHUNK = QC * NG * 32;         // doubles per chunk buffer
+};
+constexpr int kBlChunkMax = 12 * 5 * 32;             // max over p = 2, 3, 4
+static_assert(BlShape<2>::CHUNK <= kBlChunkMax && BlShape<3>::CHUNK <= kBlChunkMax &&
+              BlShape<4>::CHUNK <= kBlChunkMax, "chunk buffer");
+constexpr int kBlThreads = 512;
+
+template <int P>
+__device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* __restrict__ M,
+                                               double* __restrict__ L,
+                                               const double* __restrict__ Bl,
+                                               const int* __restrict__ lds_off,
+                                               const uint32_t* __restrict__ touch, double2* smem,
+                                               double* sB) {
+  constexpr int C = ncomp(P);
+  constexpr int NG = BlShape<P>::NG;
+  constexpr int QC = BlShape<P>::QC;
+  constexpr int CH2 = BlShape<P>::CHUNK / 2;          // double2 per chunk
+  constexpr int ROUNDS = (C + 1) / 2;
+  constexpr int TPW = 4, NT = kBlThreads;
+  constexpr int NCHUNK = (kQuads + QC - 1) / QC;
+  static_assert((CH2 + NT - 1) / NT == 2, "two staged table values per thread");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // target plane
+  const int kk = lane >> 4, ci = lane & 15;
+  int abase[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int x = (t & 1) * 4 + (ci & 3), y = (t >> 1) * 4 + (ci >> 2);
+    abase[t] = (x + 6) + kWin * (y + 6) + kWin * kWin * (wave + 6);
+  }
+  double acc[TPW][NG];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) acc[t][g] = 0.0;
+
+  const int l2 = d.log2_inv_h;
+  const double* src = M + d.m_off;
+  const int4* off4 = reinterpret_cast<const int4*>(lds_off);
+  const uint32_t* tw = touch + wave * kQuads;
+  double2* sB2 = reinterpret_cast<double2*>(sB);
+  const int boff = kk * 4 + (lane & 3);                // this lane's slot in a column group
+  for (int r = 0; r < ROUNDS; ++r) {
+    const int k0 = 2 * r, k1 = 2 * r + 1;
+    const double s0 = ldexp(1.0, l2 * order_of(k0));
+    const double s1 = k1 < C ? ldexp(1.0, l2 * order_of(k1)) : 0.0;
+    const double* src0 = src + (size_t)k0 * kNCell;
+    const double* src1 = src + (size_t)(k1 < C ? k1 : k0) * kNCell;
+    // tables of chunk 0 (contiguous in this layout)
+    const double2* gB = reinterpret_cast<const double2*>(Bl + (size_t)r * kQuads * NG * 32);
+    // (clamped indices: every element is loaded, so the staging stays in registers;
+    // slots past the chunk's quads are never read)
+    double2 bst0 = gB[min(tid, CH2 - 1)], bst1 = gB[min(tid + NT, CH2 - 1)];
+    // window: two halves of loads-then-stores keep the staging registers small
+    constexpr int kStage = (kWinCells + NT - 1) / NT;
+    constexpr int kHalf = (kStage + 1) / 2;
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+      double2 v[kHalf];
+#pragma unroll
+      for (int i = 0; i < kHalf; ++i) {
+        const int c = tid + (hb * kHalf + i) * NT;
+        v[i] = make_double2(0.0, 0.0);
+        if (hb * kHalf + i < kStage && c < kWinCells) {
+          const int wx = c % kWin, wy = (c / kWin) % kWin, wz = c / (kWin * kWin);
+          const int jx = wx + kWin0, jy = wy + kWin0, jz = wz + kWin0;
+          const int cell = jx + kFrame * jy + kFrame * kFrame * jz;
+          if (block_present(d.mask, jx, jy, jz)) {
+            v[i].x = src0[cell];
+            v[i].y = src1[cell];
+          }
+        }
+      }
+      if (hb == 0) __syncthreads();   // previous round's reads of smem and sB are done
+#pragma unroll
+      for (int i = 0; i < kHalf; ++i) {
+        const int c = tid + (hb * kHalf + i) * NT;
+        if (hb * kHalf + i < kStage && c < kWinCells) smem[c] = make_double2(v[i].x * s0, v[i].y * s1);
+      }
+    }
+    sB2[tid] = bst0;
+    if (tid + NT < CH2) sB2[tid + NT] = bst1;
+    __syncthreads();
+    for (int ch = 0; ch < NCHUNK; ++ch) {
+      const int q0 = ch * QC;
+      const int nq = min(QC, kQuads - q0);
+      // next chunk's tables: global loads now, LDS stores after this chunk
+      const bool more = ch + 1 < NCHUNK;
+      if (more) {
+        const int n2 = min(QC, kQuads - q0 - QC) * NG * 16;
+        const double2* gn = gB + (size_t)(q0 + QC) * NG * 16;
+        bst0 = gn[min(tid, n2 - 1)];
+        bst1 = gn[min(tid + NT, n2 - 1)];
+      }
+      const double2* bb = sB2 + (ch & 1) * CH2 + boff;
+      uint32_t tm_next = tw[q0];
+      int4 o_next = off4[q0];
+      for (int qi = 0; qi < nq; ++qi) {
+        const uint32_t tm = tm_next;
+        const int4 o = o_next;
+        if (qi + 1 < nq) {
+          tm_next = tw[q0 + qi + 1];
+          o_next = off4[q0 + qi + 1];
+        }
+        if ((tm & d.mask) == 0) continue;   // every source of this quad is absent for this wave
+        int doff = o.x;
+        doff = kk == 1 ? o.y : doff;
+        doff = kk == 2 ? o.z : doff;
+        doff = kk == 3 ? o.w : doff;
+        double2 a[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) a[t] = smem[abase[t] + doff];
+        double2 b[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) b[g] = bb[(qi * NG + g) * 16];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+          for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a[t].x, b[g].x, acc[t][g]);
+#pragma unroll
+          for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a[t].y, b[g].y, acc[t][g]);
+        }
+      }
+      if (more) {
+        double2* dst = sB2 + ((ch + 1) & 1) * CH2;
+        dst[tid] = bst0;
+        if (tid + NT < CH2) dst[tid + NT] = bst1;
+      }
+      __syncthreads();   // next chunk's tables visible; this chunk's buffer free
+    }
+  }
+
+  double* out = L + d.l_off;
+  const int xi = lane >> 4, yi = (lane & 15) >> 2, j = lane & 3;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int x = (t & 1) * 4 + xi, y = (t >> 1) * 4 + yi;
+    const int tcell = x + kBlock * y + kBlock * kBlock * wave;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int n = 4 * g + j;
+      if (n < C) out[(size_t)n * kNTarget + tcell] = ldexp(acc[t][g], l2 * (1 + order_of(n)));
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlThreads) m2l_fwd_bl_kernel(
+    const WorkItem* __restrict__ items, int count, unsigned* __restrict__ counter,
+    const DevDesc* __restrict__ desc, const double* __restrict__ M, double* __restrict__ L,
+    const double* __restrict__ B2, const double* __restrict__ B3, const double* __restrict__ B4,
+    const int* __restrict__ lds_off, const uint32_t* __restrict__ touch) {
+  __shared__ double2 smem[kWinCells];
+  __shared__ double sB[2 * kBlChunkMax];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= count) break;
+    const DevDesc d = desc[items[item].sub];
+    switch (d.p) {
+      case 2: fwd_bl_subgrid<2>(d, M, L, B2, lds_off, touch, smem, sB); break;
+      case 3: fwd_bl_subgrid<3>(d, M, L, B3, lds_off, touch, smem, sB); break;
+      case 4: fwd_bl_subgrid<4>(d, M, L, B4, lds_off, touch, smem, sB); break;
+      default: break;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // split precision forward
 // ---------------------------------------------------------------------------
 //
@@ -541,42 +729,41 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
     double accp[TPW];
     int addrp = 0;          // offset of the pending read-modify-write
     bool pend = false, wp = false;
-    // read-modify-write of the pending pair: first the lanes of its first offset
-    // (four tiles of distinct cells: loads, then stores), then those of the second.
-    // Different lanes of this wave update the same cell only across these
-    // batches (the second offset, the next pair); the wavefront fences keep the
-    // compiler from merging or reordering the batches, and one wave's LDS
-    // accesses complete in order.
+    // Add the pending pair into the accumulators: one LDS float64 atomic add per
+    // tile (no return value, so the wave does not wait). The order of the sums
+    // stays fixed: within one dz every output cell is updated by one wave only,
+    // a wave's LDS instructions execute in program order, and no instruction
+    // sends two lanes to one cell (the pairing rule above).
     auto flush = [&]() {
+      if (wp) {
 #pragma unroll
-      for (int hs = 0; hs < 2; ++hs) {
-        if (half == hs && wp) {
-          double v[TPW];
-#pragma unroll
-          for (int t = 0; t < TPW; ++t) v[t] = smem[obase[t] + addrp];
-#pragma unroll
-          for (int t = 0; t < TPW; ++t) smem[obase[t] + addrp] = v[t] + accp[t];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        for (int t = 0; t < TPW; ++t)
+          __hip_atomic_fetch_add(smem + obase[t] + addrp, accp[t], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     };
     double bn[KC];
 #pragma unroll
-    for (int kc = 0; kc < KC; ++kc) bn[kc] = Br[(size_t)gstart[0] * KC * 16 + kc * 16];
+    for (int kc = 0; kc < KC; ++kc) bn[kc] = Br[kc * 16];
+    // per-pair scalars (blocks written, offsets) fetched one pair ahead
+    uint32_t tm_next = tw[0];
+    int4 o_next = pr[0];
     for (int g = 0; g < 13; ++g) {
       const int qe = gstart[g + 1];
       for (int q = gstart[g]; q < qe; ++q) {
+        const uint32_t tm = tm_next;
+        const int4 o = o_next;
         double b[KC];
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) b[kc] = bn[kc];
-        if (q + 1 < npairs) {           // table operands of the next pair, one pair ahead
+        if (q + 1 < npairs) {           // next pair: scalars and table operands
+          tm_next = tw[q + 1];
+          o_next = pr[q + 1];
           const double* Bn = Br + (size_t)(q + 1) * KC * 16;
 #pragma unroll
           for (int kc = 0; kc < KC; ++kc) bn[kc] = Bn[kc * 16];
         }
-        if ((tw[q] & d.mask) == 0) continue;     // every output cell of this pair is absent
-        const int4 o = pr[q];
+        if ((tm & d.mask) == 0) continue;     // every output cell of this pair is absent
         double acc[TPW];
 #pragma unroll
         for (int t = 0; t < TPW; ++t) acc[t] = 0.0;
@@ -646,8 +833,10 @@ __global__ void __launch_bounds__(kBwdThreads) m2l_bwd_kernel(
 // ---------------------------------------------------------------------------
 
 // forward: [r][q][c][g][kk*4 + j] = T_{4q+kk}[2r+c][4g+j]
+// LDS-staged forward: [r][q][g][kk*4 + j][c], same values
 __global__ void pack_fwd_kernel(const double* __restrict__ T, int p, double* __restrict__ out,
-                                float* __restrict__ hi, float* __restrict__ lo) {
+                                float* __restrict__ hi, float* __restrict__ lo,
+                                double* __restrict__ outl) {
   const int C = ncomp(p), NG = (C + 3) / 4, ROUNDS = (C + 1) / 2;
   const int total = ROUNDS * kQuads * 2 * NG * 16;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -661,6 +850,7 @@ __global__ void pack_fwd_kernel(const double* __restrict__ T, int p, double* __r
   const int k = 2 * r + c, n = 4 * g + j, s = 4 * q + kk;
   const double v = (k < C && n < C) ? T[((size_t)s * C + k) * C + n] : 0.0;
   out[i] = v;
+  outl[((((size_t)r * kQuads + q) * NG + g) * 16 + kk * 4 + j) * 2 + c] = v;
   const float h = (float)v;
   hi[i] = h;
   lo[i] = (float)(v - (double)h);
@@ -759,14 +949,15 @@ std::vector<int> host_stencil() {
 
 // Configurations: forward waves per workgroup (tiles per wave = 32 / waves).
 struct Config {
+  bool ldstab;      // table operands staged through LDS (8 waves); else loaded per wave
   int waves;        // waves per workgroup (16-cell tiles per wave = 32 / waves)
   bool prefetch;    // table operands of the next offset quad loaded one quad ahead
                     // (not at p = 4 with 8 waves: the registers would spill)
   fmm_precision prec;
 };
-constexpr Config kConfigs[] = {{8, false, FMM_FP64}, {8, true, FMM_FP64},
-                               {4, false, FMM_FP64}, {4, true, FMM_FP64},
-                               {8, false, FMM_SPLIT_FP32}};
+constexpr Config kConfigs[] = {{true, 8, false, FMM_FP64},  {false, 8, true, FMM_FP64},
+                               {false, 8, false, FMM_FP64}, {false, 4, false, FMM_FP64},
+                               {false, 4, true, FMM_FP64},  {false, 8, false, FMM_SPLIT_FP32}};
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
 }  // namespace
@@ -839,11 +1030,12 @@ hipError_t mfma_tables_create(MfmaTables* t, double* const* d_T, const int* d_st
   for (int p = 2; p <= kMaxP; ++p) {
     const size_t nf = fwd_pack_elems(p), nb = bwd_pack_elems(p, t->npairs);
     if ((e = hipMalloc(&t->fwd[p], nf * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc(&t->fwdl[p], nf * sizeof(double))) != hipSuccess) return e;
     if ((e = hipMalloc(&t->fwd_hi[p], nf * sizeof(float))) != hipSuccess) return e;
     if ((e = hipMalloc(&t->fwd_lo[p], nf * sizeof(float))) != hipSuccess) return e;
     if ((e = hipMalloc(&t->bwd[p], nb * sizeof(double))) != hipSuccess) return e;
     hipLaunchKernelGGL(pack_fwd_kernel, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s, d_T[p], p,
-                       t->fwd[p], t->fwd_hi[p], t->fwd_lo[p]);
+                       t->fwd[p], t->fwd_hi[p], t->fwd_lo[p], t->fwdl[p]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(pack_bwd_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, d_T[p], p,
                        t->pairs, t->npairs, t->bwd[p]);
@@ -855,6 +1047,8 @@ hipError_t mfma_tables_create(MfmaTables* t, double* const* d_T, const int* d_st
 void mfma_tables_destroy(MfmaTables* t) {
   for (int p = 0; p <= kMaxP; ++p) {
     if (t->fwd[p]) (void)hipFree(t->fwd[p]);
+    if (t->fwdl[p]) (void)hipFree(t->fwdl[p]);
+    t->fwdl[p] = nullptr;
     if (t->fwd_hi[p]) (void)hipFree(t->fwd_hi[p]);
     if (t->fwd_lo[p]) (void)hipFree(t->fwd_lo[p]);
     if (t->bwd[p]) (void)hipFree(t->bwd[p]);
@@ -897,6 +1091,11 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
     hipLaunchKernelGGL(m2l_fwd_split_kernel, dim3(grid), dim3(512), 0, s, w.items, w.count, w.counter,
                        d_desc, M, L, t.fwd_hi[2], t.fwd_lo[2], t.fwd_hi[3], t.fwd_lo[3], t.fwd_hi[4],
                        t.fwd_lo[4], t.lds_off, t.touch);
+    return hipGetLastError();
+  }
+  if (c.ldstab) {
+    hipLaunchKernelGGL(m2l_fwd_bl_kernel, dim3(grid), dim3(kBlThreads), 0, s, w.items, w.count,
+                       w.counter, d_desc, M, L, t.fwdl[2], t.fwdl[3], t.fwdl[4], t.lds_off, t.touch);
     return hipGetLastError();
   }
 #define FWD_LAUNCH(W, PFV)                                                                         \

@@ -310,3 +310,19 @@ def test_every_tile_configuration_agrees_bitwise(ctx, torch):
         cfg += 1
     ctx.set_option(fmm.FMM_OPT_TILE_CONFIG, -1)
     assert cfg >= 4
+
+
+def test_backward_is_deterministic(ctx, torch):
+    # the adjoint sums into LDS in a fixed order: bitwise identical run to run
+    w = synth.config(3, nsub=6)
+    desc, m_el, l_el = descriptors(w, range(6))
+    W = to_dev(np.random.default_rng(9).standard_normal(l_el))
+    ctx.set_option(fmm.FMM_OPT_M2L_KERNEL, MFMA)
+    outs = []
+    for _ in range(3):
+        dM = torch.full((m_el,), float("nan"), dtype=torch.float64, device="cuda")
+        ctx.m2l_backward(desc, W, dM)
+        torch.cuda.synchronize()
+        outs.append(dM)
+    assert torch.isfinite(outs[0]).all()
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
