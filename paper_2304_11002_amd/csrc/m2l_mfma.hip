@@ -239,13 +239,16 @@ static_assert(BlShape<2>::CHUNK <= kBlChunkMax && BlShape<3>::CHUNK <= kBlChunkM
               BlShape<4>::CHUNK <= kBlChunkMax, "chunk buffer");
 constexpr int kBlThreads = 512;
 
-template <int P>
+// PIPE: the inner loop reads only LDS (offsets staged once per workgroup, skip
+// decisions as per-wave bitmasks), so the next quad's operand reads can be issued
+// before this quad's products and waited for with partial counters.
+template <int P, bool PIPE>
 __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* __restrict__ M,
                                                double* __restrict__ L,
                                                const double* __restrict__ Bl,
                                                const int* __restrict__ lds_off,
                                                const uint32_t* __restrict__ touch, double2* smem,
-                                               double* sB) {
+                                               double* sB, const int4* s_off) {
   constexpr int C = ncomp(P);
   constexpr int NG = BlShape<P>::NG;
   constexpr int QC = BlShape<P>::QC;
@@ -319,6 +322,11 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
     for (int ch = 0; ch < NCHUNK; ++ch) {
       const int q0 = ch * QC;
       const int nq = min(QC, kQuads - q0);
+      uint32_t cl = 0;   // bit i: quad q0 + i has a present source for this wave's plane
+      if constexpr (PIPE) {
+        const bool on = lane < nq && (tw[q0 + min(lane, nq - 1)] & d.mask) != 0;
+        cl = (uint32_t)__builtin_amdgcn_readfirstlane((int)(__ballot(on) & 0xffffffffu));
+      }
       // next chunk's tables: global loads now, LDS stores after this chunk
       const bool more = ch + 1 < NCHUNK;
       if (more) {
@@ -328,32 +336,68 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
         bst1 = gn[min(tid + NT, n2 - 1)];
       }
       const double2* bb = sB2 + (ch & 1) * CH2 + boff;
-      uint32_t tm_next = tw[q0];
-      int4 o_next = off4[q0];
-      for (int qi = 0; qi < nq; ++qi) {
-        const uint32_t tm = tm_next;
-        const int4 o = o_next;
-        if (qi + 1 < nq) {
-          tm_next = tw[q0 + qi + 1];
-          o_next = off4[q0 + qi + 1];
+      if constexpr (PIPE) {
+        // two operand sets: the reads of quad qi + 1 are issued before the products
+        // of quad qi, and the offset of qi + 2 one step further ahead
+        const int* so = reinterpret_cast<const int*>(s_off) + kk;
+        double2 a0[TPW], b0[NG], a1[TPW], b1[NG];
+#define BL_LOAD(DA, DB, QI, OFF)                                               \
+  {                                                                            \
+    const int doff_ = (OFF);                                                   \
+    _Pragma("unroll") for (int t = 0; t < TPW; ++t) DA[t] = smem[abase[t] + doff_]; \
+    _Pragma("unroll") for (int g = 0; g < NG; ++g) DB[g] = bb[((QI) * NG + g) * 16]; \
+  }
+#define BL_MMA(SA, SB, QI)                                                          \
+  if ((cl >> (QI)) & 1u) {                                                          \
+    _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                               \
+      _Pragma("unroll") for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(SA[t].x, SB[g].x, acc[t][g]); \
+      _Pragma("unroll") for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(SA[t].y, SB[g].y, acc[t][g]); \
+    }                                                                               \
+  }
+        // (the reads are unconditional, with indices clamped into the chunk, so every
+        // path into a product sees the same outstanding reads; operands read past
+        // the chunk's last quad are never multiplied)
+        BL_LOAD(a0, b0, 0, so[q0 * 4]);
+        int offn = so[min(q0 + 1, kQuads - 1) * 4];
+        for (int qi = 0; qi < nq; qi += 2) {
+          BL_LOAD(a1, b1, min(qi + 1, nq - 1), offn);
+          offn = so[min(q0 + qi + 2, kQuads - 1) * 4];
+          BL_MMA(a0, b0, qi);
+          if (qi + 1 >= nq) break;
+          BL_LOAD(a0, b0, min(qi + 2, nq - 1), offn);
+          offn = so[min(q0 + qi + 3, kQuads - 1) * 4];
+          BL_MMA(a1, b1, qi + 1);
         }
-        if ((tm & d.mask) == 0) continue;   // every source of this quad is absent for this wave
-        int doff = o.x;
-        doff = kk == 1 ? o.y : doff;
-        doff = kk == 2 ? o.z : doff;
-        doff = kk == 3 ? o.w : doff;
-        double2 a[TPW];
+#undef BL_LOAD
+#undef BL_MMA
+      } else {
+        uint32_t tm_next = tw[q0];
+        int4 o_next = off4[q0];
+        for (int qi = 0; qi < nq; ++qi) {
+          const uint32_t tm = tm_next;
+          const int4 o = o_next;
+          if (qi + 1 < nq) {
+            tm_next = tw[q0 + qi + 1];
+            o_next = off4[q0 + qi + 1];
+          }
+          if ((tm & d.mask) == 0) continue;   // every source of this quad is absent for this wave
+          int doff = o.x;
+          doff = kk == 1 ? o.y : doff;
+          doff = kk == 2 ? o.z : doff;
+          doff = kk == 3 ? o.w : doff;
+          double2 a[TPW];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) a[t] = smem[abase[t] + doff];
-        double2 b[NG];
+          for (int t = 0; t < TPW; ++t) a[t] = smem[abase[t] + doff];
+          double2 b[NG];
 #pragma unroll
-        for (int g = 0; g < NG; ++g) b[g] = bb[(qi * NG + g) * 16];
+          for (int g = 0; g < NG; ++g) b[g] = bb[(qi * NG + g) * 16];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) {
+          for (int t = 0; t < TPW; ++t) {
 #pragma unroll
-          for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a[t].x, b[g].x, acc[t][g]);
+            for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a[t].x, b[g].x, acc[t][g]);
 #pragma unroll
-          for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a[t].y, b[g].y, acc[t][g]);
+            for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a[t].y, b[g].y, acc[t][g]);
+          }
         }
       }
       if (more) {
@@ -379,6 +423,7 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
   }
 }
 
+template <bool PIPE>
 __global__ void __launch_bounds__(kBlThreads) m2l_fwd_bl_kernel(
     const WorkItem* __restrict__ items, int count, unsigned* __restrict__ counter,
     const DevDesc* __restrict__ desc, const double* __restrict__ M, double* __restrict__ L,
@@ -386,7 +431,12 @@ __global__ void __launch_bounds__(kBlThreads) m2l_fwd_bl_kernel(
     const int* __restrict__ lds_off, const uint32_t* __restrict__ touch) {
   __shared__ double2 smem[kWinCells];
   __shared__ double sB[2 * kBlChunkMax];
+  __shared__ int4 s_off[kQuads];
   __shared__ int s_item;
+  if (PIPE) {
+    const int4* off4 = reinterpret_cast<const int4*>(lds_off);
+    for (int i = threadIdx.x; i < kQuads; i += blockDim.x) s_off[i] = off4[i];
+  }
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
     __syncthreads();
@@ -394,9 +444,9 @@ __global__ void __launch_bounds__(kBlThreads) m2l_fwd_bl_kernel(
     if (item >= count) break;
     const DevDesc d = desc[items[item].sub];
     switch (d.p) {
-      case 2: fwd_bl_subgrid<2>(d, M, L, B2, lds_off, touch, smem, sB); break;
-      case 3: fwd_bl_subgrid<3>(d, M, L, B3, lds_off, touch, smem, sB); break;
-      case 4: fwd_bl_subgrid<4>(d, M, L, B4, lds_off, touch, smem, sB); break;
+      case 2: fwd_bl_subgrid<2, PIPE>(d, M, L, B2, lds_off, touch, smem, sB, s_off); break;
+      case 3: fwd_bl_subgrid<3, PIPE>(d, M, L, B3, lds_off, touch, smem, sB, s_off); break;
+      case 4: fwd_bl_subgrid<4, false>(d, M, L, B4, lds_off, touch, smem, sB, s_off); break;
       default: break;
     }
     __syncthreads();
@@ -949,15 +999,17 @@ std::vector<int> host_stencil() {
 
 // Configurations: forward waves per workgroup (tiles per wave = 32 / waves).
 struct Config {
-  bool ldstab;      // table operands staged through LDS (8 waves); else loaded per wave
+  int ldstab;       // table operands staged through LDS (8 waves): 1, or 2 with the
+                    // next quad's operand reads issued ahead; 0: loaded per wave
   int waves;        // waves per workgroup (16-cell tiles per wave = 32 / waves)
   bool prefetch;    // table operands of the next offset quad loaded one quad ahead
                     // (not at p = 4 with 8 waves: the registers would spill)
   fmm_precision prec;
 };
-constexpr Config kConfigs[] = {{true, 8, false, FMM_FP64},  {false, 8, true, FMM_FP64},
-                               {false, 8, false, FMM_FP64}, {false, 4, false, FMM_FP64},
-                               {false, 4, true, FMM_FP64},  {false, 8, false, FMM_SPLIT_FP32}};
+constexpr Config kConfigs[] = {{2, 8, false, FMM_FP64}, {1, 8, false, FMM_FP64},
+                               {0, 8, true, FMM_FP64},  {0, 8, false, FMM_FP64},
+                               {0, 4, false, FMM_FP64}, {0, 4, true, FMM_FP64},
+                               {0, 8, false, FMM_SPLIT_FP32}};
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
 }  // namespace
@@ -1094,8 +1146,12 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
     return hipGetLastError();
   }
   if (c.ldstab) {
-    hipLaunchKernelGGL(m2l_fwd_bl_kernel, dim3(grid), dim3(kBlThreads), 0, s, w.items, w.count,
-                       w.counter, d_desc, M, L, t.fwdl[2], t.fwdl[3], t.fwdl[4], t.lds_off, t.touch);
+    if (c.ldstab == 2)
+      hipLaunchKernelGGL(m2l_fwd_bl_kernel<true>, dim3(grid), dim3(kBlThreads), 0, s, w.items, w.count,
+                         w.counter, d_desc, M, L, t.fwdl[2], t.fwdl[3], t.fwdl[4], t.lds_off, t.touch);
+    else
+      hipLaunchKernelGGL(m2l_fwd_bl_kernel<false>, dim3(grid), dim3(kBlThreads), 0, s, w.items, w.count,
+                         w.counter, d_desc, M, L, t.fwdl[2], t.fwdl[3], t.fwdl[4], t.lds_off, t.touch);
     return hipGetLastError();
   }
 #define FWD_LAUNCH(W, PFV)                                                                         \
