@@ -347,12 +347,36 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
     _Pragma("unroll") for (int t = 0; t < TPW; ++t) DA[t] = smem[abase[t] + doff_]; \
     _Pragma("unroll") for (int g = 0; g < NG; ++g) DB[g] = bb[((QI) * NG + g) * 16]; \
   }
-#define BL_MMA(SA, SB, QI)                                                          \
-  if ((cl >> (QI)) & 1u) {                                                          \
-    _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                               \
-      _Pragma("unroll") for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(SA[t].x, SB[g].x, acc[t][g]); \
-      _Pragma("unroll") for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(SA[t].y, SB[g].y, acc[t][g]); \
+#define BL_MMA(SA, SB)                                                              \
+  _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                 \
+    _Pragma("unroll") for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(SA[t].x, SB[g].x, acc[t][g]); \
+    _Pragma("unroll") for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(SA[t].y, SB[g].y, acc[t][g]); \
+  }
+// the reads for the next quad are spread through the first half of this quad's
+// products, so no wave has a long stretch without matrix instructions (the two
+// waves of a SIMD run in step between barriers and would otherwise leave the unit
+// idle together), and the last read has half the products to complete
+#define BL_INTERLEAVE()                                                             \
+  {                                                                                 \
+    constexpr int NLD = TPW + NG + 1, NMF = 2 * TPW * NG, PER = NMF / NLD > 2 ? 2 : 1; \
+    _Pragma("unroll") for (int i_ = 0; i_ < NLD; ++i_) {                            \
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                            \
+      __builtin_amdgcn_sched_group_barrier(0x008, PER, 0);                          \
     }                                                                               \
+    __builtin_amdgcn_sched_group_barrier(0x008, NMF - PER * NLD, 0);                \
+  }
+// product of quad QI from (SA, SB) while the reads of quad QN go into (DA, DB) and
+// the offset of quad OQ into offn
+#define BL_STEP(SA, SB, QI, DA, DB, QN, OQ)                                         \
+  if ((cl >> (QI)) & 1u) {                                                          \
+    BL_LOAD(DA, DB, QN, offn);                                                      \
+    offn = so[(OQ) * 4];                                                            \
+    BL_MMA(SA, SB);                                                                 \
+    BL_INTERLEAVE();                                                                \
+  } else {                                                                          \
+    __builtin_amdgcn_sched_barrier(0); /* keeps the reads in each branch's block */ \
+    BL_LOAD(DA, DB, QN, offn);                                                      \
+    offn = so[(OQ) * 4];                                                            \
   }
         // (the reads are unconditional, with indices clamped into the chunk, so every
         // path into a product sees the same outstanding reads; operands read past
@@ -360,16 +384,14 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
         BL_LOAD(a0, b0, 0, so[q0 * 4]);
         int offn = so[min(q0 + 1, kQuads - 1) * 4];
         for (int qi = 0; qi < nq; qi += 2) {
-          BL_LOAD(a1, b1, min(qi + 1, nq - 1), offn);
-          offn = so[min(q0 + qi + 2, kQuads - 1) * 4];
-          BL_MMA(a0, b0, qi);
+          BL_STEP(a0, b0, qi, a1, b1, min(qi + 1, nq - 1), min(q0 + qi + 2, kQuads - 1));
           if (qi + 1 >= nq) break;
-          BL_LOAD(a0, b0, min(qi + 2, nq - 1), offn);
-          offn = so[min(q0 + qi + 3, kQuads - 1) * 4];
-          BL_MMA(a1, b1, qi + 1);
+          BL_STEP(a1, b1, qi + 1, a0, b0, min(qi + 2, nq - 1), min(q0 + qi + 3, kQuads - 1));
         }
 #undef BL_LOAD
 #undef BL_MMA
+#undef BL_INTERLEAVE
+#undef BL_STEP
       } else {
         uint32_t tm_next = tw[q0];
         int4 o_next = off4[q0];
