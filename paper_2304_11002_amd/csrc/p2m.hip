@@ -120,9 +120,9 @@ __global__ void __launch_bounds__(kP2MThreads) p2m_bwd_kernel(const DevDesc* __r
 
 // ---------------------------------------------------------------------------
 // 8 particles per cell: one kernel per order (so p = 3 is not held to p = 4's
-// registers), 128-cell workgroups. The workgroup's particles are read with
-// coalesced 16-byte loads into LDS (cell stride padded to 25 doubles against
-// bank conflicts), then each thread works on its own cell from LDS.
+// registers), blocks of 128 cells. A block's particles are read with coalesced
+// 16-byte loads and staged through LDS (cell stride padded to 25 doubles
+// against bank conflicts), then each thread works on its own cell from LDS.
 // Particles of absent blocks are not read.
 // ---------------------------------------------------------------------------
 
@@ -136,116 +136,164 @@ __device__ __forceinline__ bool cell_present(uint32_t mask, int cell) {
   return block_present(mask, cell % kFrame, (cell / kFrame) % kFrame, cell / (kFrame * kFrame));
 }
 
-__device__ __forceinline__ void stage_pos8(const DevDesc& d, const double* __restrict__ pos, int cell0,
-                                           double* s_pos) {
-  // 128 cells x 24 doubles = 1536 double2, 12 per thread
-  const double2* src = reinterpret_cast<const double2*>(pos + 3 * (d.part_off + (int64_t)cell0 * kPpc8));
-#pragma unroll
-  for (int i = 0; i < 12; ++i) {
-    const int v = threadIdx.x + i * kT8;
-    const int c = v / 12, w = v % 12;
-    if (cell_present(d.mask, cell0 + c)) {
-      const double2 x = src[v];
-      s_pos[c * kPosStride + 2 * w] = x.x;
-      s_pos[c * kPosStride + 2 * w + 1] = x.y;
-    }
-  }
-}
-
-template <int P>
+// Each workgroup takes K cell blocks (strided by the grid). The coalesced loads
+// of the next block are issued into registers before this block's moments are
+// computed, so every workgroup keeps loads in flight through its compute and
+// store phases (4 workgroups fit a CU by LDS). p = 4 needs those registers for
+// its moments and takes one block per workgroup.
+template <int P, int K>
 __global__ void __launch_bounds__(kT8) p2m8_kernel(const DevDesc* __restrict__ desc,
-                                                   const int* __restrict__ ids,
+                                                   const int* __restrict__ ids, int nblocks,
                                                    const double* __restrict__ pos,
                                                    const double* __restrict__ mass,
                                                    double* __restrict__ M) {
   constexpr int C = ncomp(P);
   __shared__ double s_pos[kT8 * kPosStride];
   __shared__ double s_mass[kT8 * kPpc8];
-  const DevDesc d = desc[ids[blockIdx.x / kCellBlocks8]];
-  const int cell0 = (blockIdx.x % kCellBlocks8) * kT8;
-  stage_pos8(d, pos, cell0, s_pos);
-  const double2* msrc = reinterpret_cast<const double2*>(mass + d.part_off + (int64_t)cell0 * kPpc8);
+  const int tid = threadIdx.x;
+  double2 rp[12], rm[4];
+  // coalesced loads of block B's positions (12 double2 per thread) and masses (4)
+#define P2M8_ISSUE(B)                                                                          \
+  {                                                                                            \
+    const DevDesc dn = desc[ids[(B) / kCellBlocks8]];                                          \
+    const int c0 = ((B) % kCellBlocks8) * kT8;                                                 \
+    const double2* ps = reinterpret_cast<const double2*>(pos + 3 * (dn.part_off + (int64_t)c0 * kPpc8)); \
+    const double2* ms = reinterpret_cast<const double2*>(mass + dn.part_off + (int64_t)c0 * kPpc8); \
+    _Pragma("unroll") for (int i = 0; i < 12; ++i) {                                           \
+      const int v = tid + i * kT8;                                                             \
+      rp[i] = cell_present(dn.mask, c0 + v / 12) ? ps[v] : make_double2(0.0, 0.0);             \
+    }                                                                                          \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                            \
+      const int v = tid + i * kT8;                                                             \
+      rm[i] = cell_present(dn.mask, c0 + v / 4) ? ms[v] : make_double2(0.0, 0.0);              \
+    }                                                                                          \
+  }
+  int blk = blockIdx.x;
+  P2M8_ISSUE(blk);
+  for (int k = 0; k < K && blk < nblocks; ++k, blk += gridDim.x) {
+    if (k > 0) __syncthreads();   // the previous block's LDS reads are done
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int v = threadIdx.x + i * kT8;
-    if (cell_present(d.mask, cell0 + v / 4)) {
-      const double2 x = msrc[v];
-      s_mass[2 * v] = x.x;
-      s_mass[2 * v + 1] = x.y;
+    for (int i = 0; i < 12; ++i) {
+      const int v = tid + i * kT8;
+      const int c = v / 12, w = v % 12;
+      s_pos[c * kPosStride + 2 * w] = rp[i].x;
+      s_pos[c * kPosStride + 2 * w + 1] = rp[i].y;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int v = tid + i * kT8;
+      s_mass[2 * v] = rm[i].x;
+      s_mass[2 * v + 1] = rm[i].y;
+    }
+    __syncthreads();
+    const int nb = blk + (int)gridDim.x;
+    if (k + 1 < K && nb < nblocks) P2M8_ISSUE(nb);
+    const DevDesc d = desc[ids[blk / kCellBlocks8]];
+    const int cell = (blk % kCellBlocks8) * kT8 + tid;
+    const int jx = cell % kFrame, jy = (cell / kFrame) % kFrame, jz = cell / (kFrame * kFrame);
+    double* out = M + d.m_off + cell;
+    if (!block_present(d.mask, jx, jy, jz)) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) out[(size_t)c * kNCell] = 0.0;
+    } else {
+      const double h = ldexp(1.0, -d.log2_inv_h);
+      const double cx = (jx + 0.5) * h, cy = (jy + 0.5) * h, cz = (jz + 0.5) * h;
+      double acc[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = 0.0;
+      const double* y = s_pos + tid * kPosStride;
+#pragma unroll 2
+      for (int i = 0; i < kPpc8; ++i) {
+        const double m = s_mass[tid * kPpc8 + i];
+        double mono[C];
+        monomials<P>(y[3 * i] - cx, y[3 * i + 1] - cy, y[3 * i + 2] - cz, mono);
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = __builtin_fma(m, mono[c], acc[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) out[(size_t)c * kNCell] = acc[c];
     }
   }
-  __syncthreads();
-  const int cell = cell0 + threadIdx.x;
-  const int jx = cell % kFrame, jy = (cell / kFrame) % kFrame, jz = cell / (kFrame * kFrame);
-  double* out = M + d.m_off + cell;
-  if (!block_present(d.mask, jx, jy, jz)) {
-#pragma unroll
-    for (int c = 0; c < C; ++c) out[(size_t)c * kNCell] = 0.0;
-    return;
-  }
-  const double h = ldexp(1.0, -d.log2_inv_h);
-  const double cx = (jx + 0.5) * h, cy = (jy + 0.5) * h, cz = (jz + 0.5) * h;
-  double acc[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) acc[c] = 0.0;
-  const double* y = s_pos + threadIdx.x * kPosStride;
-#pragma unroll 2
-  for (int i = 0; i < kPpc8; ++i) {
-    const double m = s_mass[threadIdx.x * kPpc8 + i];
-    double mono[C];
-    monomials<P>(y[3 * i] - cx, y[3 * i + 1] - cy, y[3 * i + 2] - cz, mono);
-#pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = __builtin_fma(m, mono[c], acc[c]);
-  }
-#pragma unroll
-  for (int c = 0; c < C; ++c) out[(size_t)c * kNCell] = acc[c];
+#undef P2M8_ISSUE
 }
 
-template <int P>
+// Adjoint: K cell blocks per workgroup as in the forward; the next block's
+// positions and moment gradients are loaded while this block's are used.
+template <int P, int K>
 __global__ void __launch_bounds__(kT8) p2m8_bwd_kernel(const DevDesc* __restrict__ desc,
-                                                       const int* __restrict__ ids,
+                                                       const int* __restrict__ ids, int nblocks,
                                                        const double* __restrict__ pos,
                                                        const double* __restrict__ dM,
                                                        double* __restrict__ dmass) {
   constexpr int C = ncomp(P);
   __shared__ double s_pos[kT8 * kPosStride];
   __shared__ double s_out[kT8 * (kPpc8 + 1)];
-  const DevDesc d = desc[ids[blockIdx.x / kCellBlocks8]];
-  const int cell0 = (blockIdx.x % kCellBlocks8) * kT8;
-  stage_pos8(d, pos, cell0, s_pos);
-  __syncthreads();
-  const int cell = cell0 + threadIdx.x;
-  const int jx = cell % kFrame, jy = (cell / kFrame) % kFrame, jz = cell / (kFrame * kFrame);
-  if (!block_present(d.mask, jx, jy, jz)) {
+  const int tid = threadIdx.x;
+  double2 rp[12];
+  double rg[C];
+  // coalesced loads of block B's positions, and this thread's cell's C gradients
+#define P2M8B_ISSUE(B)                                                                         \
+  {                                                                                            \
+    const DevDesc dn = desc[ids[(B) / kCellBlocks8]];                                          \
+    const int c0 = ((B) % kCellBlocks8) * kT8;                                                 \
+    const double2* ps = reinterpret_cast<const double2*>(pos + 3 * (dn.part_off + (int64_t)c0 * kPpc8)); \
+    _Pragma("unroll") for (int i = 0; i < 12; ++i) {                                           \
+      const int v = tid + i * kT8;                                                             \
+      rp[i] = cell_present(dn.mask, c0 + v / 12) ? ps[v] : make_double2(0.0, 0.0);             \
+    }                                                                                          \
+    const bool on_ = cell_present(dn.mask, c0 + tid);                                          \
+    const double* gs = dM + dn.m_off + c0 + tid;                                               \
+    _Pragma("unroll") for (int c = 0; c < C; ++c) rg[c] = on_ ? gs[(size_t)c * kNCell] : 0.0;  \
+  }
+  int blk = blockIdx.x;
+  P2M8B_ISSUE(blk);
+  for (int k = 0; k < K && blk < nblocks; ++k, blk += gridDim.x) {
+    if (k > 0) __syncthreads();   // the previous block's LDS reads are done
 #pragma unroll
-    for (int i = 0; i < kPpc8; ++i) s_out[threadIdx.x * (kPpc8 + 1) + i] = 0.0;
-  } else {
+    for (int i = 0; i < 12; ++i) {
+      const int v = tid + i * kT8;
+      const int c = v / 12, w = v % 12;
+      s_pos[c * kPosStride + 2 * w] = rp[i].x;
+      s_pos[c * kPosStride + 2 * w + 1] = rp[i].y;
+    }
     double g[C];
-    const double* src = dM + d.m_off + cell;
 #pragma unroll
-    for (int c = 0; c < C; ++c) g[c] = src[(size_t)c * kNCell];
-    const double h = ldexp(1.0, -d.log2_inv_h);
-    const double cx = (jx + 0.5) * h, cy = (jy + 0.5) * h, cz = (jz + 0.5) * h;
-    const double* y = s_pos + threadIdx.x * kPosStride;
+    for (int c = 0; c < C; ++c) g[c] = rg[c];
+    __syncthreads();
+    const int nb = blk + (int)gridDim.x;
+    if (k + 1 < K && nb < nblocks) P2M8B_ISSUE(nb);
+    const DevDesc d = desc[ids[blk / kCellBlocks8]];
+    const int cell0 = (blk % kCellBlocks8) * kT8;
+    const int cell = cell0 + tid;
+    const int jx = cell % kFrame, jy = (cell / kFrame) % kFrame, jz = cell / (kFrame * kFrame);
+    if (!block_present(d.mask, jx, jy, jz)) {
+#pragma unroll
+      for (int i = 0; i < kPpc8; ++i) s_out[tid * (kPpc8 + 1) + i] = 0.0;
+    } else {
+      const double h = ldexp(1.0, -d.log2_inv_h);
+      const double cx = (jx + 0.5) * h, cy = (jy + 0.5) * h, cz = (jz + 0.5) * h;
+      const double* y = s_pos + tid * kPosStride;
 #pragma unroll 2
-    for (int i = 0; i < kPpc8; ++i) {
-      double mono[C];
-      monomials<P>(y[3 * i] - cx, y[3 * i + 1] - cy, y[3 * i + 2] - cz, mono);
-      double sum = 0.0;
+      for (int i = 0; i < kPpc8; ++i) {
+        double mono[C];
+        monomials<P>(y[3 * i] - cx, y[3 * i + 1] - cy, y[3 * i + 2] - cz, mono);
+        double sum = 0.0;
 #pragma unroll
-      for (int c = 0; c < C; ++c) sum = __builtin_fma(g[c], mono[c], sum);
-      s_out[threadIdx.x * (kPpc8 + 1) + i] = sum;
+        for (int c = 0; c < C; ++c) sum = __builtin_fma(g[c], mono[c], sum);
+        s_out[tid * (kPpc8 + 1) + i] = sum;
+      }
+    }
+    __syncthreads();
+    // coalesced write of the block's 128 x 8 gradients
+    double2* dst = reinterpret_cast<double2*>(dmass + d.part_off + (int64_t)cell0 * kPpc8);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int v = tid + i * kT8;
+      const int c = v / 4, w = v % 4;
+      dst[v] = make_double2(s_out[c * (kPpc8 + 1) + 2 * w], s_out[c * (kPpc8 + 1) + 2 * w + 1]);
     }
   }
-  __syncthreads();
-  // coalesced write of the workgroup's 128 x 8 gradients
-  double2* dst = reinterpret_cast<double2*>(dmass + d.part_off + (int64_t)cell0 * kPpc8);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int v = threadIdx.x + i * kT8;
-    const int c = v / 4, w = v % 4;
-    dst[v] = make_double2(s_out[c * (kPpc8 + 1) + 2 * w], s_out[c * (kPpc8 + 1) + 2 * w + 1]);
-  }
+#undef P2M8B_ISSUE
 }
 
 // The 8-particle kernels use 16-byte loads: they need 16-byte aligned particle
@@ -262,10 +310,11 @@ hipError_t launch_p2m(const DevDesc* d_desc, int64_t nsub, const int* const* d_i
     for (int p = 2; p <= kMaxP; ++p) {
       for (int64_t b0 = 0; b0 < counts[p]; b0 += per_launch) {
         const int64_t n = counts[p] - b0 < per_launch ? counts[p] - b0 : per_launch;
-        const dim3 grid((unsigned)(n * kCellBlocks8));
-        if (p == 2) hipLaunchKernelGGL(p2m8_kernel<2>, grid, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, pos, mass, M);
-        if (p == 3) hipLaunchKernelGGL(p2m8_kernel<3>, grid, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, pos, mass, M);
-        if (p == 4) hipLaunchKernelGGL(p2m8_kernel<4>, grid, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, pos, mass, M);
+        const int nblocks = (int)(n * kCellBlocks8);
+        const dim3 grid8((unsigned)((nblocks + 7) / 8)), grid1((unsigned)nblocks);
+        if (p == 2) hipLaunchKernelGGL((p2m8_kernel<2, 8>), grid8, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, nblocks, pos, mass, M);
+        if (p == 3) hipLaunchKernelGGL((p2m8_kernel<3, 8>), grid8, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, nblocks, pos, mass, M);
+        if (p == 4) hipLaunchKernelGGL((p2m8_kernel<4, 1>), grid1, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, nblocks, pos, mass, M);
       }
     }
     return hipGetLastError();
@@ -288,10 +337,11 @@ hipError_t launch_p2m_backward(const DevDesc* d_desc, int64_t nsub, const int* c
     for (int p = 2; p <= kMaxP; ++p) {
       for (int64_t b0 = 0; b0 < counts[p]; b0 += per_launch) {
         const int64_t n = counts[p] - b0 < per_launch ? counts[p] - b0 : per_launch;
-        const dim3 grid((unsigned)(n * kCellBlocks8));
-        if (p == 2) hipLaunchKernelGGL(p2m8_bwd_kernel<2>, grid, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, pos, dM, dmass);
-        if (p == 3) hipLaunchKernelGGL(p2m8_bwd_kernel<3>, grid, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, pos, dM, dmass);
-        if (p == 4) hipLaunchKernelGGL(p2m8_bwd_kernel<4>, grid, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, pos, dM, dmass);
+        const int nblocks = (int)(n * kCellBlocks8);
+        const dim3 grid8((unsigned)((nblocks + 7) / 8)), grid1((unsigned)nblocks);
+        if (p == 2) hipLaunchKernelGGL((p2m8_bwd_kernel<2, 8>), grid8, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, nblocks, pos, dM, dmass);
+        if (p == 3) hipLaunchKernelGGL((p2m8_bwd_kernel<3, 8>), grid8, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, nblocks, pos, dM, dmass);
+        if (p == 4) hipLaunchKernelGGL((p2m8_bwd_kernel<4, 1>), grid1, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, nblocks, pos, dM, dmass);
       }
     }
     return hipGetLastError();
