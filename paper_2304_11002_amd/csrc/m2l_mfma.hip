@@ -278,6 +278,11 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
   const uint32_t* tw = touch + wave * kQuads;
   double2* sB2 = reinterpret_cast<double2*>(sB);
   const int boff = kk * 4 + (lane & 3);                // this lane's slot in a column group
+  uint32_t cl0 = 0;                                    // live quads of chunk 0
+  if constexpr (PIPE) {
+    const bool on = lane < QC && (tw[min(lane, QC - 1)] & d.mask) != 0;
+    cl0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(__ballot(on) & 0xffffffffu));
+  }
   for (int r = 0; r < ROUNDS; ++r) {
     const int k0 = 2 * r, k1 = 2 * r + 1;
     const double s0 = ldexp(1.0, l2 * order_of(k0));
@@ -319,34 +324,47 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
     sB2[tid] = bst0;
     if (tid + NT < CH2) sB2[tid + NT] = bst1;
     __syncthreads();
+    // bit i of cl: quad q0 + i has a present source for this wave's plane (the
+    // next chunk's touch words are loaded with its tables and reduced at its end)
+    uint32_t cl = cl0;
+    [[maybe_unused]] double2 a0[TPW], b0[NG], a1[TPW], b1[NG];   // operand sets (PIPE)
+    [[maybe_unused]] int offn = 0;
+    [[maybe_unused]] const int* so = reinterpret_cast<const int*>(s_off) + kk;
+    static_assert(QC % 2 == 0, "a full chunk ends on the second operand set");
     for (int ch = 0; ch < NCHUNK; ++ch) {
       const int q0 = ch * QC;
       const int nq = min(QC, kQuads - q0);
-      uint32_t cl = 0;   // bit i: quad q0 + i has a present source for this wave's plane
-      if constexpr (PIPE) {
-        const bool on = lane < nq && (tw[q0 + min(lane, nq - 1)] & d.mask) != 0;
-        cl = (uint32_t)__builtin_amdgcn_readfirstlane((int)(__ballot(on) & 0xffffffffu));
-      }
       // next chunk's tables: global loads now, LDS stores after this chunk
       const bool more = ch + 1 < NCHUNK;
+      const int nq2 = more ? min(QC, kQuads - q0 - QC) : 1;
+      uint32_t tn = 0;
       if (more) {
-        const int n2 = min(QC, kQuads - q0 - QC) * NG * 16;
+        if constexpr (PIPE) tn = tw[q0 + QC + min(lane, nq2 - 1)];
+        const int n2 = nq2 * NG * 16;
         const double2* gn = gB + (size_t)(q0 + QC) * NG * 16;
         bst0 = gn[min(tid, n2 - 1)];
         bst1 = gn[min(tid + NT, n2 - 1)];
       }
       const double2* bb = sB2 + (ch & 1) * CH2 + boff;
       if constexpr (PIPE) {
-        // two operand sets: the reads of quad qi + 1 are issued before the products
-        // of quad qi, and the offset of qi + 2 one step further ahead
-        const int* so = reinterpret_cast<const int*>(s_off) + kk;
-        double2 a0[TPW], b0[NG], a1[TPW], b1[NG];
-#define BL_LOAD(DA, DB, QI, OFF)                                               \
+        // Two operand sets: the reads of quad qi + 1 are issued before the products
+        // of quad qi, and the offset of qi + 2 one step further ahead. The reads
+        // are unconditional, with table indices clamped into the chunk, so every
+        // path into a product sees the same outstanding reads; operands read past
+        // the chunk's last quad are never multiplied. Window offsets are not
+        // clamped to the chunk, so a full chunk's last step leaves the window
+        // operands of the next chunk's first quad in (a0, offn): after the
+        // barrier only its table operands are read.
+#define BL_LOADA(DA, OFF)                                                      \
   {                                                                            \
     const int doff_ = (OFF);                                                   \
     _Pragma("unroll") for (int t = 0; t < TPW; ++t) DA[t] = smem[abase[t] + doff_]; \
-    _Pragma("unroll") for (int g = 0; g < NG; ++g) DB[g] = bb[((QI) * NG + g) * 16]; \
   }
+#define BL_LOADB(DB, QI)                                                       \
+  { _Pragma("unroll") for (int g = 0; g < NG; ++g) DB[g] = bb[((QI) * NG + g) * 16]; }
+#define BL_LOAD(DA, DB, QI, OFF) \
+  BL_LOADA(DA, OFF);             \
+  BL_LOADB(DB, QI);
 #define BL_MMA(SA, SB)                                                              \
   _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                 \
     _Pragma("unroll") for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(SA[t].x, SB[g].x, acc[t][g]); \
@@ -378,16 +396,25 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
     BL_LOAD(DA, DB, QN, offn);                                                      \
     offn = so[(OQ) * 4];                                                            \
   }
-        // (the reads are unconditional, with indices clamped into the chunk, so every
-        // path into a product sees the same outstanding reads; operands read past
-        // the chunk's last quad are never multiplied)
-        BL_LOAD(a0, b0, 0, so[q0 * 4]);
-        int offn = so[min(q0 + 1, kQuads - 1) * 4];
+        if (ch == 0) {
+          BL_LOADA(a0, so[q0 * 4]);
+          offn = so[min(q0 + 1, kQuads - 1) * 4];
+        }
+        BL_LOADB(b0, 0);
         for (int qi = 0; qi < nq; qi += 2) {
           BL_STEP(a0, b0, qi, a1, b1, min(qi + 1, nq - 1), min(q0 + qi + 2, kQuads - 1));
           if (qi + 1 >= nq) break;
           BL_STEP(a1, b1, qi + 1, a0, b0, min(qi + 2, nq - 1), min(q0 + qi + 3, kQuads - 1));
+          if (qi == 4 && more) {
+            // next chunk's tables, stored mid-chunk (the buffer was freed by the
+            // previous chunk's barrier) so the barrier does not wait on them
+            double2* dst = sB2 + ((ch + 1) & 1) * CH2;
+            dst[tid] = bst0;
+            if (tid + NT < CH2) dst[tid + NT] = bst1;
+          }
         }
+#undef BL_LOADA
+#undef BL_LOADB
 #undef BL_LOAD
 #undef BL_MMA
 #undef BL_INTERLEAVE
@@ -423,9 +450,15 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
         }
       }
       if (more) {
-        double2* dst = sB2 + ((ch + 1) & 1) * CH2;
-        dst[tid] = bst0;
-        if (tid + NT < CH2) dst[tid + NT] = bst1;
+        if constexpr (!PIPE || QC < 6) {
+          double2* dst = sB2 + ((ch + 1) & 1) * CH2;
+          dst[tid] = bst0;
+          if (tid + NT < CH2) dst[tid + NT] = bst1;
+        }
+        if constexpr (PIPE) {
+          const bool on = lane < nq2 && (tn & d.mask) != 0;
+          cl = (uint32_t)__builtin_amdgcn_readfirstlane((int)(__ballot(on) & 0xffffffffu));
+        }
       }
       __syncthreads();   // next chunk's tables visible; this chunk's buffer free
     }
