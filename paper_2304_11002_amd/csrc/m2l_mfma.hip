@@ -242,7 +242,9 @@ constexpr int kBlThreads = 512;
 // PIPE: the inner loop reads only LDS (offsets staged once per workgroup, skip
 // decisions as per-wave bitmasks), so the next quad's operand reads can be issued
 // before this quad's products and waited for with partial counters.
-template <int P, bool PIPE>
+// FULL: every neighbour block is present, so no quad is skipped and the quad
+// loop carries no skip branches.
+template <int P, bool PIPE, bool FULL = false>
 __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* __restrict__ M,
                                                double* __restrict__ L,
                                                const double* __restrict__ Bl,
@@ -386,7 +388,7 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
 // product of quad QI from (SA, SB) while the reads of quad QN go into (DA, DB) and
 // the offset of quad OQ into offn
 #define BL_STEP(SA, SB, QI, DA, DB, QN, OQ)                                         \
-  if ((cl >> (QI)) & 1u) {                                                          \
+  if (FULL || ((cl >> (QI)) & 1u)) {                                                \
     BL_LOAD(DA, DB, QN, offn);                                                      \
     offn = so[(OQ) * 4];                                                            \
     BL_MMA(SA, SB);                                                                 \
@@ -401,6 +403,7 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
           offn = so[min(q0 + 1, kQuads - 1) * 4];
         }
         BL_LOADB(b0, 0);
+#pragma unroll 1
         for (int qi = 0; qi < nq; qi += 2) {
           BL_STEP(a0, b0, qi, a1, b1, min(qi + 1, nq - 1), min(q0 + qi + 2, kQuads - 1));
           if (qi + 1 >= nq) break;
@@ -499,8 +502,18 @@ __global__ void __launch_bounds__(kBlThreads) m2l_fwd_bl_kernel(
     if (item >= count) break;
     const DevDesc d = desc[items[item].sub];
     switch (d.p) {
-      case 2: fwd_bl_subgrid<2, PIPE>(d, M, L, B2, lds_off, touch, smem, sB, s_off); break;
-      case 3: fwd_bl_subgrid<3, PIPE>(d, M, L, B3, lds_off, touch, smem, sB, s_off); break;
+      case 2:
+        if (PIPE && d.mask == kFullMask)
+          fwd_bl_subgrid<2, PIPE, true>(d, M, L, B2, lds_off, touch, smem, sB, s_off);
+        else
+          fwd_bl_subgrid<2, PIPE>(d, M, L, B2, lds_off, touch, smem, sB, s_off);
+        break;
+      case 3:
+        if (PIPE && d.mask == kFullMask)
+          fwd_bl_subgrid<3, PIPE, true>(d, M, L, B3, lds_off, touch, smem, sB, s_off);
+        else
+          fwd_bl_subgrid<3, PIPE>(d, M, L, B3, lds_off, touch, smem, sB, s_off);
+        break;
       case 4: fwd_bl_subgrid<4, false>(d, M, L, B4, lds_off, touch, smem, sB, s_off); break;
       default: break;
     }
