@@ -57,10 +57,16 @@ __host__ __device__ constexpr MI mi_of(int idx) {
   return MI{0, 0, 0};
 }
 
+// Order |k| of the multi-index at position idx: the number of orders whose
+// whole block ends at or before idx (blocks end at ncomp(n) = 1, 4, 10, ...).
+// Branch-free for the orders used here (idx < ncomp(9) = 220).
 __host__ __device__ constexpr int order_of(int idx) {
-  MI m = mi_of(idx);
-  return m.x + m.y + m.z;
+  return (idx >= 1) + (idx >= 4) + (idx >= 10) + (idx >= 20) + (idx >= 35) + (idx >= 56) +
+         (idx >= 84) + (idx >= 120) + (idx >= 165);
 }
+static_assert(order_of(0) == 0 && order_of(3) == 1 && order_of(4) == 2 && order_of(19) == 3 &&
+                  order_of(20) == 4 && order_of(34) == 4 && order_of(164) == 8 && order_of(165) == 9,
+              "order_of");
 
 __host__ __device__ constexpr double inv_fact(int n) {
   double f = 1.0;

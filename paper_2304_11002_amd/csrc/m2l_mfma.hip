@@ -902,6 +902,8 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
       __syncthreads();   // the next dz writes other planes of other waves
     }
     // write the round's two components of dM (whole frame) and clear the accumulators
+    const double sc0 = ldexp(1.0, l2 * order_of(2 * r));
+    const double sc1 = ldexp(1.0, l2 * order_of(2 * r + 1));
     for (int c = tid; c < kNCell; c += kBwdThreads) {
       const int jx = c % kFrame, jy = (c / kFrame) % kFrame, jz = c / (kFrame * kFrame);
       const bool win = jx >= kWin0 && jx < kWin0 + kWin && jy >= kWin0 && jy < kWin0 + kWin &&
@@ -916,7 +918,7 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
           v = smem[sl * kAccStride + wc];
           smem[sl * kAccStride + wc] = 0.0;
         }
-        if (k < C) out[(size_t)k * kNCell + c] = pres ? ldexp(v, l2 * order_of(k)) : 0.0;
+        if (k < C) out[(size_t)k * kNCell + c] = pres ? v * (sl ? sc1 : sc0) : 0.0;
       }
     }
   }
