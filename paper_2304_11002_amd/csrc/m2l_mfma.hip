@@ -788,21 +788,23 @@ __global__ void __launch_bounds__(512) m2l_fwd_split_kernel(
 // the 8^3 block only). One workgroup owns one sub-grid; for each pair of
 // output components ("round") the window's accumulators live in LDS. Wave w
 // holds target plane w (its dL values stay in registers for the whole
-// sub-grid) and applies the offsets of one dz at a time: for a fixed dz the
-// waves write disjoint output planes, so there are no atomics and the
-// summation order is fixed. One instruction multiplies [16 targets x 4 dL
-// components] by [4 components x (2 output components x 2 offsets)]; the two
-// offsets of a pair never map two cells of one 4x4 tile to the same output
-// cell (|dx2 - dx1| >= 4 or |dy2 - dy1| >= 4), so each read-modify-write is
-// collision free. The read-modify-write of one pair overlaps the next pair's
-// products.
+// sub-grid) and applies the offsets of one dz at a time, so for a fixed dz
+// every output cell has one writing wave. One instruction multiplies
+// [16 targets x 4 dL components] by [4 components x (2 output components x
+// 2 offsets)]; the two offsets of a pair never map two cells of one 4x4 tile
+// to the same output cell (|dx2 - dx1| >= 4 or |dy2 - dy1| >= 4). Results
+// are added with LDS atomic adds that return nothing; one wave's LDS
+// operations execute in issue order, so each cell's sum is taken in pair
+// order and the result is reproducible bit for bit.
 
 constexpr int kBwdWaves = 8;
 constexpr int kBwdThreads = kBwdWaves * 64;
 constexpr int kAccStride = kWinCells + 16;     // component stride of the LDS accumulators
 constexpr int kMaxPairs = 512;
 
-template <int P>
+// FULL: every neighbour block is present, so no pair is skipped and the pair
+// loop carries no branches.
+template <int P, bool FULL>
 __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __restrict__ dL,
                                             double* __restrict__ dM, const double* __restrict__ Bp,
                                             const int4* __restrict__ pairs, int npairs,
@@ -838,69 +840,94 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
 
   for (int i = tid; i < 2 * kAccStride; i += kBwdThreads) smem[i] = 0.0;
 
-  const int4* pr = pairs;
   const uint32_t* tw = ptouch + wave * npairs;
   double* out = dM + d.m_off;
   for (int r = 0; r < ROUNDS; ++r) {
     __syncthreads();
     const double* Br = Bp + (size_t)r * npairs * KC * 16 + kk * 4 + j;
-    double accp[TPW];
-    int addrp = 0;          // offset of the pending read-modify-write
-    bool pend = false, wp = false;
-    // Add the pending pair into the accumulators: one LDS float64 atomic add per
-    // tile (no return value, so the wave does not wait). The order of the sums
-    // stays fixed: within one dz every output cell is updated by one wave only,
-    // a wave's LDS instructions execute in program order, and no instruction
-    // sends two lanes to one cell (the pairing rule above).
-    auto flush = [&]() {
-      if (wp) {
+    // Two sets (tables, offsets, products, output offset) alternate over the
+    // pairs: the tables of pair q + 2 are loaded while pair q is multiplied, and
+    // a set's previous products are added into LDS just before the set is
+    // reused. After a barrier the sets hold zeros, so those adds change nothing.
+    double b0[KC], b1[KC], acc0[TPW], acc1[TPW];
+    int4 o0, o1;
+    uint32_t tm0 = 0, tm1 = 0;
+    int ad0 = 0, ad1 = 0;
 #pragma unroll
-        for (int t = 0; t < TPW; ++t)
-          __hip_atomic_fetch_add(smem + obase[t] + addrp, accp[t], __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
-    };
-    double bn[KC];
-#pragma unroll
-    for (int kc = 0; kc < KC; ++kc) bn[kc] = Br[kc * 16];
-    // per-pair scalars (blocks written, offsets) fetched one pair ahead
-    uint32_t tm_next = tw[0];
-    int4 o_next = pr[0];
-    for (int g = 0; g < 13; ++g) {
-      const int qe = gstart[g + 1];
-      for (int q = gstart[g]; q < qe; ++q) {
-        const uint32_t tm = tm_next;
-        const int4 o = o_next;
-        double b[KC];
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc) b[kc] = bn[kc];
-        if (q + 1 < npairs) {           // next pair: scalars and table operands
-          tm_next = tw[q + 1];
-          o_next = pr[q + 1];
-          const double* Bn = Br + (size_t)(q + 1) * KC * 16;
-#pragma unroll
-          for (int kc = 0; kc < KC; ++kc) bn[kc] = Bn[kc * 16];
-        }
-        if ((tm & d.mask) == 0) continue;     // every output cell of this pair is absent
-        double acc[TPW];
-#pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = 0.0;
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc)
-#pragma unroll
-          for (int t = 0; t < TPW; ++t) acc[t] = mfma4(a[t][kc], b[kc], acc[t]);
-        // finish the previous pair while these products run
-        if (pend) flush();
-#pragma unroll
-        for (int t = 0; t < TPW; ++t) accp[t] = acc[t];
-        addrp = half ? o.y : o.x;
-        wp = !(half && o.w < 0);                  // a single offset: second half idle
-        pend = true;
-      }
-      if (pend) flush();
-      pend = false;
-      __syncthreads();   // the next dz writes other planes of other waves
+    for (int t = 0; t < TPW; ++t) acc0[t] = acc1[t] = 0.0;
+#define BW_LOAD(BS, OS, TS, Q)                                                      \
+  {                                                                                 \
+    const int q_ = (Q);                                                             \
+    const double* Bq_ = Br + (size_t)q_ * KC * 16;                                  \
+    _Pragma("unroll") for (int kc = 0; kc < KC; ++kc) BS[kc] = Bq_[kc * 16];        \
+    OS = pairs[q_];                                                                 \
+    if (!FULL) TS = tw[q_];                                                         \
+  }
+#define BW_FLUSH(AS, AD)                                                            \
+  _Pragma("unroll") for (int t = 0; t < TPW; ++t)                                   \
+    __hip_atomic_fetch_add(smem + obase[t] + (AD), AS[t], __ATOMIC_RELAXED,         \
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+#define BW_MMA(AS, BS)                                                              \
+  {                                                                                 \
+    _Pragma("unroll") for (int t = 0; t < TPW; ++t) AS[t] = 0.0;                    \
+    _Pragma("unroll") for (int kc = 0; kc < KC; ++kc)                               \
+      _Pragma("unroll") for (int t = 0; t < TPW; ++t) AS[t] = mfma4(a[t][kc], BS[kc], AS[t]); \
+  }
+// the adds and the loads are spread through the products
+#define BW_INTERLEAVE()                                                             \
+  {                                                                                 \
+    constexpr int NMF = TPW * KC;                                                   \
+    _Pragma("unroll") for (int i_ = 0; i_ < TPW; ++i_) {                            \
+      __builtin_amdgcn_sched_group_barrier(0x080, 1, 0);                            \
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
+    }                                                                               \
+    _Pragma("unroll") for (int i_ = 0; i_ < KC; ++i_) {                             \
+      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);                            \
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
+    }                                                                               \
+    __builtin_amdgcn_sched_group_barrier(0x008, NMF - TPW - KC, 0);                 \
+  }
+// pair Q from set (BS, OS, TS) into products AS; then the set takes pair Q + 2
+#define BW_STEP(BS, OS, TS, AS, AD, Q)                                              \
+  if (FULL || ((TS) & d.mask) != 0) {                                               \
+    BW_FLUSH(AS, AD);                                                               \
+    AD = half ? OS.y : OS.x;                                                        \
+    BW_MMA(AS, BS);                                                                 \
+    BW_LOAD(BS, OS, TS, min((Q) + 2, npairs - 1));                                  \
+    BW_INTERLEAVE();                                                                \
+  } else {                                                                          \
+    __builtin_amdgcn_sched_barrier(0);                                              \
+    BW_FLUSH(AS, AD);                                                               \
+    _Pragma("unroll") for (int t = 0; t < TPW; ++t) AS[t] = 0.0;                    \
+    BW_LOAD(BS, OS, TS, min((Q) + 2, npairs - 1));                                  \
+  }
+// at the end of a dz group: both sets' products go in, then the barrier
+#define BW_GROUP_END(QN)                                                            \
+  if ((QN) == gend) {                                                               \
+    BW_FLUSH(acc0, ad0);                                                            \
+    BW_FLUSH(acc1, ad1);                                                            \
+    _Pragma("unroll") for (int t = 0; t < TPW; ++t) acc0[t] = acc1[t] = 0.0;        \
+    __syncthreads();   /* the next dz writes other planes of other waves */         \
+    ++g;                                                                            \
+    gend = gstart[g + 1];                                                           \
+  }
+    BW_LOAD(b0, o0, tm0, 0);
+    BW_LOAD(b1, o1, tm1, min(1, npairs - 1));
+    int g = 0, gend = gstart[1];
+#pragma unroll 1
+    for (int q = 0; q < npairs; q += 2) {
+      BW_STEP(b0, o0, tm0, acc0, ad0, q);
+      BW_GROUP_END(q + 1);
+      if (q + 1 >= npairs) break;
+      BW_STEP(b1, o1, tm1, acc1, ad1, q + 1);
+      BW_GROUP_END(q + 2);
     }
+#undef BW_LOAD
+#undef BW_FLUSH
+#undef BW_MMA
+#undef BW_INTERLEAVE
+#undef BW_STEP
+#undef BW_GROUP_END
     // write the round's two components of dM (whole frame) and clear the accumulators
     const double sc0 = ldexp(1.0, l2 * order_of(2 * r));
     const double sc1 = ldexp(1.0, l2 * order_of(2 * r + 1));
@@ -939,9 +966,18 @@ __global__ void __launch_bounds__(kBwdThreads) m2l_bwd_kernel(
     if (item >= count) break;
     const DevDesc d = desc[items[item].sub];
     switch (d.p) {
-      case 2: bwd_subgrid<2>(d, dL, dM, B2, pairs, npairs, gstart, ptouch, smem); break;
-      case 3: bwd_subgrid<3>(d, dL, dM, B3, pairs, npairs, gstart, ptouch, smem); break;
-      case 4: bwd_subgrid<4>(d, dL, dM, B4, pairs, npairs, gstart, ptouch, smem); break;
+      case 2:
+        if (d.mask == kFullMask) bwd_subgrid<2, true>(d, dL, dM, B2, pairs, npairs, gstart, ptouch, smem);
+        else bwd_subgrid<2, false>(d, dL, dM, B2, pairs, npairs, gstart, ptouch, smem);
+        break;
+      case 3:
+        if (d.mask == kFullMask) bwd_subgrid<3, true>(d, dL, dM, B3, pairs, npairs, gstart, ptouch, smem);
+        else bwd_subgrid<3, false>(d, dL, dM, B3, pairs, npairs, gstart, ptouch, smem);
+        break;
+      case 4:
+        if (d.mask == kFullMask) bwd_subgrid<4, true>(d, dL, dM, B4, pairs, npairs, gstart, ptouch, smem);
+        else bwd_subgrid<4, false>(d, dL, dM, B4, pairs, npairs, gstart, ptouch, smem);
+        break;
       default: break;
     }
     __syncthreads();
