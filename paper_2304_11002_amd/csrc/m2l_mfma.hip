@@ -807,9 +807,9 @@ constexpr int kMaxPairs = 512;
 template <int P, bool FULL>
 __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __restrict__ dL,
                                             double* __restrict__ dM, const double* __restrict__ Bp,
-                                            const int4* __restrict__ pairs, int npairs,
-                                            const int* __restrict__ gstart,
-                                            const uint32_t* __restrict__ ptouch, double* smem) {
+                                            int npairs, const int* s_gs,
+                                            const uint32_t* __restrict__ ptouch, double* smem,
+                                            const int* s_po) {
   constexpr int C = ncomp(P);
   constexpr int KC = (C + 3) / 4;     // dL component chunks of 4 (the reduction)
   constexpr int ROUNDS = (C + 1) / 2;
@@ -844,23 +844,34 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
   double* out = dM + d.m_off;
   for (int r = 0; r < ROUNDS; ++r) {
     __syncthreads();
-    const double* Br = Bp + (size_t)r * npairs * KC * 16 + kk * 4 + j;
-    // Two sets (tables, offsets, products, output offset) alternate over the
-    // pairs: the tables of pair q + 2 are loaded while pair q is multiplied, and
-    // a set's previous products are added into LDS just before the set is
-    // reused. After a barrier the sets hold zeros, so those adds change nothing.
-    double b0[KC], b1[KC], acc0[TPW], acc1[TPW];
-    int4 o0, o1;
-    uint32_t tm0 = 0, tm1 = 0;
-    int ad0 = 0, ad1 = 0;
+    // tables through a buffer resource: a per-pair scalar offset and this lane's
+    // fixed byte offset, so no per-pair address registers (reads past the end of
+    // the tables would return zeros)
+    const __amdgpu_buffer_rsrc_t brs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double*>(Bp), (short)0, ROUNDS * npairs * KC * 16 * (int)sizeof(double), 0x00020000);
+    const int sbase = r * npairs * KC * 16 * (int)sizeof(double);
+    const int vboff = (kk * 4 + j) * (int)sizeof(double);
+    // Three sets (tables, offsets, products, output offset) rotate over the
+    // pairs: at pair q the set of pair q - 1, whose products are issued, takes
+    // the tables of pair q + 2, and a set's products are added into LDS just
+    // before the set is multiplied again. After a barrier the sets hold zeros,
+    // so those adds change nothing.
+    double b0[KC], b1[KC], b2[KC], acc0[TPW], acc1[TPW], acc2[TPW];
+    int o0, o1, o2;              // this lane's output offset of the set's pair
+    uint32_t tm0 = 0, tm1 = 0, tm2 = 0;
+    int ad0 = 0, ad1 = 0, ad2 = 0;
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) acc0[t] = acc1[t] = 0.0;
+    for (int t = 0; t < TPW; ++t) acc0[t] = acc1[t] = acc2[t] = 0.0;
+    // (offsets are read from LDS, whose operations complete in order, so waiting
+    // for one does not wait for the adds issued after it)
 #define BW_LOAD(BS, OS, TS, Q)                                                      \
   {                                                                                 \
     const int q_ = (Q);                                                             \
-    const double* Bq_ = Br + (size_t)q_ * KC * 16;                                  \
-    _Pragma("unroll") for (int kc = 0; kc < KC; ++kc) BS[kc] = Bq_[kc * 16];        \
-    OS = pairs[q_];                                                                 \
+    const int so_ = sbase + q_ * KC * 16 * (int)sizeof(double);                     \
+    _Pragma("unroll") for (int kc = 0; kc < KC; ++kc)                               \
+      BS[kc] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(     \
+                   brs, vboff + kc * 16 * (int)sizeof(double), so_, 0));            \
+    OS = s_po[2 * q_ + half];                                                       \
     if (!FULL) TS = tw[q_];                                                         \
   }
 #define BW_FLUSH(AS, AD)                                                            \
@@ -873,54 +884,56 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
     _Pragma("unroll") for (int kc = 0; kc < KC; ++kc)                               \
       _Pragma("unroll") for (int t = 0; t < TPW; ++t) AS[t] = mfma4(a[t][kc], BS[kc], AS[t]); \
   }
-// the adds and the loads are spread through the products
+// the loads and the adds are spread through the products
 #define BW_INTERLEAVE()                                                             \
   {                                                                                 \
     constexpr int NMF = TPW * KC;                                                   \
-    _Pragma("unroll") for (int i_ = 0; i_ < TPW; ++i_) {                            \
-      __builtin_amdgcn_sched_group_barrier(0x080, 1, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
-    }                                                                               \
     _Pragma("unroll") for (int i_ = 0; i_ < KC; ++i_) {                             \
       __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);                            \
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
     }                                                                               \
+    _Pragma("unroll") for (int i_ = 0; i_ < TPW; ++i_) {                            \
+      __builtin_amdgcn_sched_group_barrier(0x080, 1, 0);                            \
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
+    }                                                                               \
     __builtin_amdgcn_sched_group_barrier(0x008, NMF - TPW - KC, 0);                 \
   }
-// pair Q from set (BS, OS, TS) into products AS; then the set takes pair Q + 2
-#define BW_STEP(BS, OS, TS, AS, AD, Q)                                              \
+// pair Q from set S (products AS); set N (pair Q - 1) takes the tables of Q + 2
+#define BW_STEP(BS, OS, TS, AS, AD, BN, ON, TN, Q)                                  \
+  BW_LOAD(BN, ON, TN, min((Q) + 2, npairs - 1));                                    \
   if (FULL || ((TS) & d.mask) != 0) {                                               \
     BW_FLUSH(AS, AD);                                                               \
-    AD = half ? OS.y : OS.x;                                                        \
+    AD = OS;                                                                        \
     BW_MMA(AS, BS);                                                                 \
-    BW_LOAD(BS, OS, TS, min((Q) + 2, npairs - 1));                                  \
     BW_INTERLEAVE();                                                                \
   } else {                                                                          \
-    __builtin_amdgcn_sched_barrier(0);                                              \
     BW_FLUSH(AS, AD);                                                               \
     _Pragma("unroll") for (int t = 0; t < TPW; ++t) AS[t] = 0.0;                    \
-    BW_LOAD(BS, OS, TS, min((Q) + 2, npairs - 1));                                  \
   }
-// at the end of a dz group: both sets' products go in, then the barrier
+// at the end of a dz group: every set's products go in, then the barrier
 #define BW_GROUP_END(QN)                                                            \
   if ((QN) == gend) {                                                               \
     BW_FLUSH(acc0, ad0);                                                            \
     BW_FLUSH(acc1, ad1);                                                            \
-    _Pragma("unroll") for (int t = 0; t < TPW; ++t) acc0[t] = acc1[t] = 0.0;        \
+    BW_FLUSH(acc2, ad2);                                                            \
+    _Pragma("unroll") for (int t = 0; t < TPW; ++t) acc0[t] = acc1[t] = acc2[t] = 0.0; \
     __syncthreads();   /* the next dz writes other planes of other waves */         \
     ++g;                                                                            \
-    gend = gstart[g + 1];                                                           \
+    gend = __builtin_amdgcn_readfirstlane(s_gs[g + 1]);                             \
   }
     BW_LOAD(b0, o0, tm0, 0);
     BW_LOAD(b1, o1, tm1, min(1, npairs - 1));
-    int g = 0, gend = gstart[1];
+    int g = 0, gend = __builtin_amdgcn_readfirstlane(s_gs[1]);
 #pragma unroll 1
-    for (int q = 0; q < npairs; q += 2) {
-      BW_STEP(b0, o0, tm0, acc0, ad0, q);
+    for (int q = 0; q < npairs; q += 3) {
+      BW_STEP(b0, o0, tm0, acc0, ad0, b2, o2, tm2, q);
       BW_GROUP_END(q + 1);
       if (q + 1 >= npairs) break;
-      BW_STEP(b1, o1, tm1, acc1, ad1, q + 1);
+      BW_STEP(b1, o1, tm1, acc1, ad1, b0, o0, tm0, q + 1);
       BW_GROUP_END(q + 2);
+      if (q + 2 >= npairs) break;
+      BW_STEP(b2, o2, tm2, acc2, ad2, b1, o1, tm1, q + 2);
+      BW_GROUP_END(q + 3);
     }
 #undef BW_LOAD
 #undef BW_FLUSH
@@ -958,25 +971,36 @@ __global__ void __launch_bounds__(kBwdThreads) m2l_bwd_kernel(
     const int4* __restrict__ pairs, int npairs, const int* __restrict__ gstart,
     const uint32_t* __restrict__ ptouch) {
   __shared__ double smem[2 * kAccStride];
+  __shared__ int s_po[2 * kMaxPairs];     // output offsets of each pair's two offsets
+  __shared__ int s_gs[16];                // first pair of each dz group, and the end
   __shared__ int s_item;
+  for (int i = threadIdx.x; i < npairs; i += blockDim.x) {
+    const int4 o = pairs[i];
+    s_po[2 * i] = o.x;
+    s_po[2 * i + 1] = o.y;
+  }
+  if (threadIdx.x < 14) s_gs[threadIdx.x] = gstart[threadIdx.x];
+  // (LDS operations complete in order; the staged values are read after the
+  // barrier at the top of the item loop)
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
     __syncthreads();
     const int item = s_item;
     if (item >= count) break;
     const DevDesc d = desc[items[item].sub];
+    const bool full = d.mask == kFullMask;
     switch (d.p) {
       case 2:
-        if (d.mask == kFullMask) bwd_subgrid<2, true>(d, dL, dM, B2, pairs, npairs, gstart, ptouch, smem);
-        else bwd_subgrid<2, false>(d, dL, dM, B2, pairs, npairs, gstart, ptouch, smem);
+        if (full) bwd_subgrid<2, true>(d, dL, dM, B2, npairs, s_gs, ptouch, smem, s_po);
+        else bwd_subgrid<2, false>(d, dL, dM, B2, npairs, s_gs, ptouch, smem, s_po);
         break;
       case 3:
-        if (d.mask == kFullMask) bwd_subgrid<3, true>(d, dL, dM, B3, pairs, npairs, gstart, ptouch, smem);
-        else bwd_subgrid<3, false>(d, dL, dM, B3, pairs, npairs, gstart, ptouch, smem);
+        if (full) bwd_subgrid<3, true>(d, dL, dM, B3, npairs, s_gs, ptouch, smem, s_po);
+        else bwd_subgrid<3, false>(d, dL, dM, B3, npairs, s_gs, ptouch, smem, s_po);
         break;
       case 4:
-        if (d.mask == kFullMask) bwd_subgrid<4, true>(d, dL, dM, B4, pairs, npairs, gstart, ptouch, smem);
-        else bwd_subgrid<4, false>(d, dL, dM, B4, pairs, npairs, gstart, ptouch, smem);
+        if (full) bwd_subgrid<4, true>(d, dL, dM, B4, npairs, s_gs, ptouch, smem, s_po);
+        else bwd_subgrid<4, false>(d, dL, dM, B4, npairs, s_gs, ptouch, smem, s_po);
         break;
       default: break;
     }
