@@ -912,7 +912,7 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
   }
 // at the end of a dz group: every set's products go in, then the barrier
 #define BW_GROUP_END(QN)                                                            \
-  if ((QN) == gend) {                                                               \
+  if (__builtin_expect((QN) == gend, 0)) {                                          \
     BW_FLUSH(acc0, ad0);                                                            \
     BW_FLUSH(acc1, ad1);                                                            \
     BW_FLUSH(acc2, ad2);                                                            \
@@ -928,10 +928,10 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
     for (int q = 0; q < npairs; q += 3) {
       BW_STEP(b0, o0, tm0, acc0, ad0, b2, o2, tm2, q);
       BW_GROUP_END(q + 1);
-      if (q + 1 >= npairs) break;
+      if (__builtin_expect(q + 1 >= npairs, 0)) break;
       BW_STEP(b1, o1, tm1, acc1, ad1, b0, o0, tm0, q + 1);
       BW_GROUP_END(q + 2);
-      if (q + 2 >= npairs) break;
+      if (__builtin_expect(q + 2 >= npairs, 0)) break;
       BW_STEP(b2, o2, tm2, acc2, ad2, b1, o1, tm1, q + 2);
       BW_GROUP_END(q + 3);
     }
