@@ -187,7 +187,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs its hot path on a single MI355X "
-              "(sub-grids are independent; see DESIGN.md for how the batch would shard). "
+              "(sub-grids are independent, so a batch would shard by sub-grid across GPUs). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 

@@ -12,8 +12,8 @@ Octo-Tiger subsection (Sec. IV-C, "Octo-Tiger"): cell moments on N^3 = 8^3
 sub-grids co-located with the hydro grid, and the same-level cell-to-cell
 interaction step of the three-step gravity iteration (Sec. VII-C, "Usage of
 multiple HPX tasks per Kokkos kernel invocation"). The paper gives no
-formulas; the definitions written out here are textbook Cartesian FMM and are
-listed, with every reading taken where the paper is silent, in the design doc.
+formulas; the definitions written out here are textbook Cartesian FMM, and
+each function states the reading it takes where the paper is silent.
 
 Every floating-point step is plain NumPy float64 (float32 only in the
 split-precision emulation, which is an expectation model, not a reference).
