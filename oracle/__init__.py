@@ -38,6 +38,9 @@ from .fmm import (  # noqa: F401
     m2l,
     m2l_abs,
     m2l_adjoint,
+    harmonic_indices,
+    harmonic_fold,
+    m2l_harmonic,
     m2l_adjoint_abs,
     p2m_adjoint,
     direct_sum,

@@ -320,6 +320,72 @@ def direct_sum(pos, mass, h, order, mask=FULL_MASK, offsets=None, targets=None):
 
 
 # ---------------------------------------------------------------------------
+# harmonic (traceless) form of M2L
+# ---------------------------------------------------------------------------
+
+def harmonic_indices(p):
+    """K'_p = {k in I_p : k_z <= 1}, in the graded order of I_p: the (p+1)^2
+    multi-indices that carry the independent components of a tensor family
+    that is harmonic in its index (sum_i T[k + 2 e_i] = 0)."""
+    return [k for k in multi_indices(p) if k[2] <= 1]
+
+
+def harmonic_fold(p):
+    """F [C, C'] with T[k] = sum_{k'} F[k, k'] T[k'] for every k in I_p and every
+    family T that is harmonic in k.
+
+    For k_z >= 2, harmonicity at k - 2 e_z gives
+    T[(a, b, c)] = -T[(a+2, b, c-2)] - T[(a, b+2, c-2)]; applying it until the
+    z-index is 0 or 1 expresses every T[k] through K'_p with integer
+    coefficients (rows of k in K'_p are unit rows).
+    """
+    ks = multi_indices(p)
+    hs = harmonic_indices(p)
+    col = {k: i for i, k in enumerate(hs)}
+    F = np.zeros((len(ks), len(hs)))
+
+    def expand(row, k, coef):
+        a, b, c = k
+        if c <= 1:
+            F[row, col[k]] += coef
+            return
+        expand(row, (a + 2, b, c - 2), -coef)
+        expand(row, (a, b + 2, c - 2), -coef)
+
+    for row, k in enumerate(ks):
+        expand(row, k, 1.0)
+    return F
+
+
+def m2l_harmonic(M, p, h, mask=FULL_MASK, offsets=None):
+    """The M2L of m2l() computed in the harmonic form.
+
+    T_d[k][n] = (-1)^|k| D_{k+n}(R_d) is harmonic in k and in n, because 1/r is
+    harmonic away from the origin. So with F = harmonic_fold(p):
+      * sum_k M_k T_d[k][n] = sum_{k'} Mh_{k'} T_d[k'][n], with Mh = F^T M
+        (the folded moments, C' = (p+1)^2 per cell);
+      * L is harmonic in n, so only the C' columns n' in K'_p are contracted
+        and L_n = sum_{n'} F[n, n'] L_{n'}.
+    Per offset this is one [512 x C'] . [C' x C'] product with the dense table
+    restricted to K'_p x K'_p. The result equals m2l() up to rounding.
+    """
+    offsets = stencil() if offsets is None else offsets
+    ks = multi_indices(p)
+    hs = harmonic_indices(p)
+    hidx = [ks.index(k) for k in hs]
+    Cp = len(hs)
+    F = harmonic_fold(p)
+    src = _masked(M, mask)
+    Mh = np.tensordot(F.T, src, axes=(1, 0))                 # [C', 24, 24, 24]
+    T = stencil_tensors(p, h, offsets)[:, hidx][:, :, hidx]  # [S, C', C']
+    Lh = np.zeros((Cp, BLOCK ** 3))
+    for d, Td in zip(offsets, T):
+        Lh += Td.T @ _source_window(Mh, d).reshape(Cp, -1)
+    L = F @ Lh
+    return L.reshape(len(ks), BLOCK, BLOCK, BLOCK)
+
+
+# ---------------------------------------------------------------------------
 # split-precision expectation model
 # ---------------------------------------------------------------------------
 

@@ -440,3 +440,57 @@ def test_half_spacing_frame_geometry_against_direct_sum():
     L = O.m2l(M, 4, h, offsets=offs)
     for it, (x, y, z) in enumerate(targets):
         assert np.max(np.abs(L[:10, z, y, x] - ex[it]) / np.abs(ex[it]).max()) < 2e-3
+
+
+# ---------------------------------------------------------------------------
+# harmonic (traceless) form
+# ---------------------------------------------------------------------------
+
+def test_harmonic_fold_structure_and_trace_annihilation():
+    for p in range(0, 7):
+        hs = O.harmonic_indices(p)
+        assert len(hs) == (p + 1) ** 2
+        assert all(k[2] <= 1 for k in hs)
+        ks = O.multi_indices(p)
+        F = O.harmonic_fold(p)
+        assert np.array_equal(F, np.round(F))              # integer coefficients
+        for row, k in enumerate(ks):
+            nz = np.nonzero(F[row])[0]
+            assert all(sum(hs[c]) == sum(k) for c in nz)   # folding keeps the order
+            if k in hs:
+                assert list(nz) == [hs.index(k)] and F[row, nz[0]] == 1.0
+        # a pure trace (sum_i delta_{m + 2 e_i}) carries no field: it folds to zero exactly
+        for m in O.multi_indices(p - 2) if p >= 2 else []:
+            Mt = np.zeros(len(ks))
+            for e in ((2, 0, 0), (0, 2, 0), (0, 0, 2)):
+                Mt[ks.index((m[0] + e[0], m[1] + e[1], m[2] + e[2]))] += 1.0
+            assert np.array_equal(F.T @ Mt, np.zeros(len(hs)))
+
+
+def test_harmonic_fold_reproduces_derivative_tensors():
+    # D_{k+n}(R) is harmonic in k (Laplace, via Hobson's formula): the fold must
+    # rebuild every D_{k+n} from the k_z <= 1 ones
+    rng = np.random.default_rng(7)
+    R = rng.normal(size=3) * 3.0
+    for p in (2, 3, 4):
+        ks = O.multi_indices(p)
+        F = O.harmonic_fold(p)
+        hs = O.harmonic_indices(p)
+        D = O.dtensor_all(2 * p, R)
+        for n in ks:
+            col = np.array([D[(k[0] + n[0], k[1] + n[1], k[2] + n[2])] for k in ks])
+            colh = np.array([D[(k[0] + n[0], k[1] + n[1], k[2] + n[2])] for k in hs])
+            scale = np.abs(col).max()
+            assert np.max(np.abs(F @ colh - col)) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("p,h,seed,masked", [(2, 1.0, 0, False), (3, 1.0, 0, False),
+                                              (3, 0.5, 11, True), (4, 0.25, 12, True)])
+def test_harmonic_m2l_equals_dense(p, h, seed, masked):
+    pos, mass = synth.subgrid_particles(seed, h=h)
+    mask = synth.random_mask(np.random.default_rng(seed)) if masked else O.FULL_MASK
+    M = O.p2m(pos, mass, p, h, mask)
+    Ld = O.m2l(M, p, h, mask)
+    Lh = O.m2l_harmonic(M, p, h, mask)
+    La = O.m2l_abs(M, p, h, mask)
+    assert np.max(np.abs(Lh - Ld) / La) <= 1e-13
