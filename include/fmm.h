@@ -43,7 +43,7 @@
  *     caches. HIP failures return FMM_EHIP; fmm_last_error() gives detail.
  *   - A context is not thread-safe: use one per host thread.
  *   - Results are deterministic run to run: every output element is owned
- *     by one work item and summed in a fixed order (no atomics on outputs).
+ *     by one work item and summed in a fixed order.
  */
 #ifndef FMM_H
 #define FMM_H
@@ -67,6 +67,13 @@ typedef int32_t fmm_precision;
 #define FMM_FP64        0  /* float64 products and sums throughout */
 #define FMM_SPLIT_FP32  1  /* hi/lo float32 products, float32 sums per offset block,
                               float64 across blocks, float64 tables and scaling */
+#define FMM_FP64_HARMONIC 2 /* float64 in the harmonic (traceless) form: T_d is harmonic in k
+                              and in n (1/r is harmonic), so the moments are folded to the
+                              (p+1)^2 components with kz <= 1 (integer coefficients, within each
+                              order), contracted with T_d restricted to those rows and columns,
+                              and L is expanded back to all C components from its harmonic
+                              ones (L_(a,b,c+2) = -L_(a+2,b,c) - L_(a,b+2,c)). Equal to
+                              FMM_FP64 up to rounding; (p+1)^4 instead of C^2 products per pair */
 
 /* One descriptor per sub-grid (host memory). */
 typedef struct {

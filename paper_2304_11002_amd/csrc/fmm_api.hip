@@ -92,7 +92,7 @@ struct DescEntry {
   int count[kMaxP + 1] = {};
   WorkList work;                  // matrix-core kernels
   bool part_even = true;          // every part_off even: particle blocks 16-byte aligned
-  int tuned[2] = {-1, -1};        // autotuned configuration per precision
+  int tuned[3] = {-1, -1, -1};    // autotuned configuration per precision
   hipEvent_t ready = nullptr;     // upload finished
   hipEvent_t last_launch = nullptr;
 };
@@ -520,8 +520,9 @@ fmm_status fmm_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const do
   CHECK_OK(check_desc(ctx, desc, nsub));
   CHECK_OK(check_ptr(ctx, M, "M", nsub));
   CHECK_OK(check_ptr(ctx, L, "L", nsub));
-  if (prec != FMM_FP64 && prec != FMM_SPLIT_FP32) return set_err(ctx, FMM_EINVAL, "unknown precision");
-  if (prec == FMM_SPLIT_FP32 && ctx->m2l_kernel == 1)
+  if (prec != FMM_FP64 && prec != FMM_SPLIT_FP32 && prec != FMM_FP64_HARMONIC)
+    return set_err(ctx, FMM_EINVAL, "unknown precision");
+  if (prec != FMM_FP64 && ctx->m2l_kernel == 1)
     return set_err(ctx, FMM_EINVAL, "the reference kernel computes FMM_FP64 only");
   if (ctx->m2l_kernel != 1 && ctx->tile_config >= 0 && !mfma_config_supports(ctx->tile_config, prec))
     return set_err(ctx, FMM_EINVAL, "FMM_OPT_TILE_CONFIG selects a configuration of the other precision");
@@ -580,7 +581,8 @@ fmm_status fmm_autotune(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, con
   CHECK_OK(check_desc(ctx, desc, nsub));
   CHECK_OK(check_ptr(ctx, M, "M", nsub));
   CHECK_OK(check_ptr(ctx, L, "L", nsub));
-  if (prec != FMM_FP64 && prec != FMM_SPLIT_FP32) return set_err(ctx, FMM_EINVAL, "unknown precision");
+  if (prec != FMM_FP64 && prec != FMM_SPLIT_FP32 && prec != FMM_FP64_HARMONIC)
+    return set_err(ctx, FMM_EINVAL, "unknown precision");
   if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
   if (nsub == 0) {
     if (chosen) *chosen = pick_config(ctx, nullptr, prec);

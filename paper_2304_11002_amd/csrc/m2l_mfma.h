@@ -27,6 +27,26 @@ std::vector<WorkItem> build_work_list(const fmm_subgrid* desc, int64_t nsub);
 constexpr int kQuads = kNStencil / 4;   // offsets are consumed four at a time
 static_assert(kNStencil % 4 == 0, "offset quads");
 
+// Harmonic form (FMM_FP64_HARMONIC). The folded moments Mh_k' (k' with kz <= 1)
+// are staged two per round; each is a combination of at most kHMaxSup moment
+// components of its own order, with integer coefficients.
+constexpr int kHMaxSup = 6;
+struct HRound {
+  int32_t nsup;            // moment components read in this round
+  int32_t ord0, ord1;      // orders of the two folded components (ord1 < 0: only one)
+  int32_t pad;
+  int32_t comp[kHMaxSup];  // component indices in I_p
+  double c0[kHMaxSup];     // fold coefficients of the round's first folded component
+  double c1[kHMaxSup];     // and of its second
+};
+// One output component L_n as a combination of the harmonic ones L_n'.
+constexpr int kHMaxExp = 3;
+struct HExp {
+  int32_t nterm;
+  int32_t col[kHMaxExp];   // harmonic column indices n'
+  double coef[kHMaxExp];
+};
+
 struct MfmaTables {
   // forward, per order p: [rounds][quad][comp of pair][n-group][kk*4 + j] float64
   double* fwd[kMaxP + 1] = {};
@@ -44,6 +64,12 @@ struct MfmaTables {
   const int* stencil = nullptr;   // [892][3] offsets (owned by the context)
   int* lds_off = nullptr;     // [892] dx + 20 dy + 400 dz
   uint32_t* touch = nullptr;  // [8][quads] blocks touched by an 8x8 target plane per quad
+  // harmonic form, per order p: tables [rounds][quad][n'-group][kk*4 + j][folded comp of pair]
+  // (T_d restricted to kz <= 1 rows and columns), the rounds' fold plans and the
+  // expansion of L
+  double* fwdh[kMaxP + 1] = {};
+  HRound* hround[kMaxP + 1] = {};
+  HExp* hexp[kMaxP + 1] = {};
   int num_cu = 0;
 };
 

@@ -227,16 +227,20 @@ __global__ void __launch_bounds__(WAVES * 64) m2l_fwd_kernel(
 // them with broadcast ds_read_b128 (both components of a column group at once).
 // Table layout for this form: [round][quad][group][kk*4 + j][component].
 
-template <int P>
+constexpr int kBlChunkMax = 12 * 5 * 32;             // doubles per chunk buffer
+// HARM: the harmonic form, (p+1)^2 folded components instead of C
+template <int P, bool HARM = false>
 struct BlShape {
-  static constexpr int C = ncomp(P);
-  static constexpr int NG = (C + 3) / 4;
-  static constexpr int QC = P == 4 ? 6 : 12;         // quads per staged chunk
+  static constexpr int CR = HARM ? (P + 1) * (P + 1) : ncomp(P);   // reduced components
+  static constexpr int NG = (CR + 3) / 4;
+  // quads per staged chunk (even: a full chunk ends on the second operand set)
+  static constexpr int QC = HARM ? (kBlChunkMax / (NG * 32)) & ~1 : (P == 4 ? 6 : 12);
   static constexpr int CHUNK = QC * NG * 32;         // doubles per chunk buffer
 };
-constexpr int kBlChunkMax = 12 * 5 * 32;             // max over p = 2, 3, 4
 static_assert(BlShape<2>::CHUNK <= kBlChunkMax && BlShape<3>::CHUNK <= kBlChunkMax &&
-              BlShape<4>::CHUNK <= kBlChunkMax, "chunk buffer");
+              BlShape<4>::CHUNK <= kBlChunkMax && BlShape<2, true>::CHUNK <= kBlChunkMax &&
+              BlShape<3, true>::CHUNK <= kBlChunkMax && BlShape<4, true>::CHUNK <= kBlChunkMax,
+              "chunk buffer");
 constexpr int kBlThreads = 512;
 
 // PIPE: the inner loop reads only LDS (offsets staged once per workgroup, skip
@@ -244,18 +248,25 @@ constexpr int kBlThreads = 512;
 // before this quad's products and waited for with partial counters.
 // FULL: every neighbour block is present, so no quad is skipped and the quad
 // loop carries no skip branches.
-template <int P, bool PIPE, bool FULL = false>
+// HARM: the harmonic form. Each round stages two folded moment components
+// (combinations of moment components of one order, per the round's plan), the
+// products run over the (p+1)^2 harmonic columns, and L is expanded to all C
+// components at the end through LDS.
+template <int P, bool PIPE, bool FULL = false, bool HARM = false>
 __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* __restrict__ M,
                                                double* __restrict__ L,
                                                const double* __restrict__ Bl,
                                                const int* __restrict__ lds_off,
                                                const uint32_t* __restrict__ touch, double2* smem,
-                                               double* sB, const int4* s_off) {
+                                               double* sB, const int4* s_off,
+                                               const HRound* __restrict__ hround = nullptr,
+                                               const HExp* __restrict__ hexp = nullptr) {
   constexpr int C = ncomp(P);
-  constexpr int NG = BlShape<P>::NG;
-  constexpr int QC = BlShape<P>::QC;
-  constexpr int CH2 = BlShape<P>::CHUNK / 2;          // double2 per chunk
-  constexpr int ROUNDS = (C + 1) / 2;
+  constexpr int CR = BlShape<P, HARM>::CR;
+  constexpr int NG = BlShape<P, HARM>::NG;
+  constexpr int QC = BlShape<P, HARM>::QC;
+  constexpr int CH2 = BlShape<P, HARM>::CHUNK / 2;    // double2 per chunk
+  constexpr int ROUNDS = (CR + 1) / 2;
   constexpr int TPW = 4, NT = kBlThreads;
   constexpr int NCHUNK = (kQuads + QC - 1) / QC;
   static_assert((CH2 + NT - 1) / NT == 2, "two staged table values per thread");
@@ -286,11 +297,18 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
     cl0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(__ballot(on) & 0xffffffffu));
   }
   for (int r = 0; r < ROUNDS; ++r) {
-    const int k0 = 2 * r, k1 = 2 * r + 1;
-    const double s0 = ldexp(1.0, l2 * order_of(k0));
-    const double s1 = k1 < C ? ldexp(1.0, l2 * order_of(k1)) : 0.0;
-    const double* src0 = src + (size_t)k0 * kNCell;
-    const double* src1 = src + (size_t)(k1 < C ? k1 : k0) * kNCell;
+    double s0, s1;
+    const double *src0 = nullptr, *src1 = nullptr;
+    if constexpr (HARM) {
+      s0 = ldexp(1.0, l2 * hround[r].ord0);
+      s1 = hround[r].ord1 >= 0 ? ldexp(1.0, l2 * hround[r].ord1) : 0.0;
+    } else {
+      const int k0 = 2 * r, k1 = 2 * r + 1;
+      s0 = ldexp(1.0, l2 * order_of(k0));
+      s1 = k1 < C ? ldexp(1.0, l2 * order_of(k1)) : 0.0;
+      src0 = src + (size_t)k0 * kNCell;
+      src1 = src + (size_t)(k1 < C ? k1 : k0) * kNCell;
+    }
     // tables of chunk 0 (contiguous in this layout)
     const double2* gB = reinterpret_cast<const double2*>(Bl + (size_t)r * kQuads * NG * 32);
     // (clamped indices: every element is loaded, so the staging stays in registers;
@@ -302,17 +320,45 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
 #pragma unroll
     for (int hb = 0; hb < 2; ++hb) {
       double2 v[kHalf];
+      if constexpr (HARM) {
+        // folded components: sum over the round's moment components, in plan order
+        int cell[kHalf];
+        bool on[kHalf];
 #pragma unroll
-      for (int i = 0; i < kHalf; ++i) {
-        const int c = tid + (hb * kHalf + i) * NT;
-        v[i] = make_double2(0.0, 0.0);
-        if (hb * kHalf + i < kStage && c < kWinCells) {
+        for (int i = 0; i < kHalf; ++i) {
+          const int c = tid + (hb * kHalf + i) * NT;
+          v[i] = make_double2(0.0, 0.0);
           const int wx = c % kWin, wy = (c / kWin) % kWin, wz = c / (kWin * kWin);
           const int jx = wx + kWin0, jy = wy + kWin0, jz = wz + kWin0;
-          const int cell = jx + kFrame * jy + kFrame * kFrame * jz;
-          if (block_present(d.mask, jx, jy, jz)) {
-            v[i].x = src0[cell];
-            v[i].y = src1[cell];
+          cell[i] = jx + kFrame * jy + kFrame * kFrame * jz;
+          on[i] = hb * kHalf + i < kStage && c < kWinCells && block_present(d.mask, jx, jy, jz);
+        }
+        const int nsup = hround[r].nsup;
+        for (int u = 0; u < nsup; ++u) {
+          const double* su = src + (size_t)hround[r].comp[u] * kNCell;
+          const double f0 = hround[r].c0[u], f1 = hround[r].c1[u];
+          double x[kHalf];
+#pragma unroll
+          for (int i = 0; i < kHalf; ++i) x[i] = on[i] ? su[cell[i]] : 0.0;
+#pragma unroll
+          for (int i = 0; i < kHalf; ++i) {
+            v[i].x = __builtin_fma(f0, x[i], v[i].x);
+            v[i].y = __builtin_fma(f1, x[i], v[i].y);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < kHalf; ++i) {
+          const int c = tid + (hb * kHalf + i) * NT;
+          v[i] = make_double2(0.0, 0.0);
+          if (hb * kHalf + i < kStage && c < kWinCells) {
+            const int wx = c % kWin, wy = (c / kWin) % kWin, wz = c / (kWin * kWin);
+            const int jx = wx + kWin0, jy = wy + kWin0, jz = wz + kWin0;
+            const int cell = jx + kFrame * jy + kFrame * kFrame * jz;
+            if (block_present(d.mask, jx, jy, jz)) {
+              v[i].x = src0[cell];
+              v[i].y = src1[cell];
+            }
           }
         }
       }
@@ -469,6 +515,33 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
 
   double* out = L + d.l_off;
   const int xi = lane >> 4, yi = (lane & 15) >> 2, j = lane & 3;
+  if constexpr (HARM) {
+    // harmonic columns to LDS ([n'][target], over the window, which every wave
+    // has finished reading), then each thread expands one target to all C
+    __syncthreads();
+    double* lh = reinterpret_cast<double*>(smem);
+    static_assert(CR * kNTarget <= 2 * kWinCells, "harmonic columns fit the window buffer");
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int x = (t & 1) * 4 + xi, y = (t >> 1) * 4 + yi;
+      const int tcell = x + kBlock * y + kBlock * kBlock * wave;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const int n = 4 * g + j;
+        if (n < CR) lh[n * kNTarget + tcell] = acc[t][g];
+      }
+    }
+    __syncthreads();
+    static_assert(kBlThreads == kNTarget, "one target per thread");
+#pragma unroll
+    for (int n = 0; n < C; ++n) {
+      const HExp& e = hexp[n];
+      double v = 0.0;
+      for (int u = 0; u < e.nterm; ++u) v = __builtin_fma(e.coef[u], lh[e.col[u] * kNTarget + tid], v);
+      out[(size_t)n * kNTarget + tid] = ldexp(v, l2 * (1 + order_of(n)));
+    }
+    return;
+  }
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     const int x = (t & 1) * 4 + xi, y = (t >> 1) * 4 + yi;
@@ -481,12 +554,14 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
   }
 }
 
-template <bool PIPE>
+template <bool PIPE, bool HARM = false>
 __global__ void __launch_bounds__(kBlThreads) m2l_fwd_bl_kernel(
     const WorkItem* __restrict__ items, int count, unsigned* __restrict__ counter,
     const DevDesc* __restrict__ desc, const double* __restrict__ M, double* __restrict__ L,
     const double* __restrict__ B2, const double* __restrict__ B3, const double* __restrict__ B4,
-    const int* __restrict__ lds_off, const uint32_t* __restrict__ touch) {
+    const int* __restrict__ lds_off, const uint32_t* __restrict__ touch,
+    const HRound* __restrict__ hr2, const HRound* __restrict__ hr3, const HRound* __restrict__ hr4,
+    const HExp* __restrict__ he2, const HExp* __restrict__ he3, const HExp* __restrict__ he4) {
   __shared__ double2 smem[kWinCells];
   __shared__ double sB[2 * kBlChunkMax];
   __shared__ int4 s_off[kQuads];
@@ -501,20 +576,24 @@ __global__ void __launch_bounds__(kBlThreads) m2l_fwd_bl_kernel(
     const int item = s_item;
     if (item >= count) break;
     const DevDesc d = desc[items[item].sub];
+    const bool full = d.mask == kFullMask;
     switch (d.p) {
       case 2:
-        if (PIPE && d.mask == kFullMask)
-          fwd_bl_subgrid<2, PIPE, true>(d, M, L, B2, lds_off, touch, smem, sB, s_off);
+        if (PIPE && full)
+          fwd_bl_subgrid<2, PIPE, true, HARM>(d, M, L, B2, lds_off, touch, smem, sB, s_off, hr2, he2);
         else
-          fwd_bl_subgrid<2, PIPE>(d, M, L, B2, lds_off, touch, smem, sB, s_off);
+          fwd_bl_subgrid<2, PIPE, false, HARM>(d, M, L, B2, lds_off, touch, smem, sB, s_off, hr2, he2);
         break;
       case 3:
-        if (PIPE && d.mask == kFullMask)
-          fwd_bl_subgrid<3, PIPE, true>(d, M, L, B3, lds_off, touch, smem, sB, s_off);
+        if (PIPE && full)
+          fwd_bl_subgrid<3, PIPE, true, HARM>(d, M, L, B3, lds_off, touch, smem, sB, s_off, hr3, he3);
         else
-          fwd_bl_subgrid<3, PIPE>(d, M, L, B3, lds_off, touch, smem, sB, s_off);
+          fwd_bl_subgrid<3, PIPE, false, HARM>(d, M, L, B3, lds_off, touch, smem, sB, s_off, hr3, he3);
         break;
-      case 4: fwd_bl_subgrid<4, false>(d, M, L, B4, lds_off, touch, smem, sB, s_off); break;
+      case 4:
+        // (the p = 4 operand sets do not fit the registers of the pipelined loop)
+        fwd_bl_subgrid<4, false, false, HARM>(d, M, L, B4, lds_off, touch, smem, sB, s_off, hr4, he4);
+        break;
       default: break;
     }
     __syncthreads();
@@ -1036,6 +1115,30 @@ __global__ void pack_fwd_kernel(const double* __restrict__ T, int p, double* __r
   lo[i] = (float)(v - (double)h);
 }
 
+// harmonic: [r][q][g][kk*4 + j][c] = T_{4q+kk}[rowk[2r + c]][colk[4g + j]] (0 where a map is -1)
+struct HPackMaps {
+  int rowk[32];   // full index of each round's folded components, or -1
+  int colk[32];   // full index of each harmonic column, or -1 past (p+1)^2
+};
+__global__ void pack_fwdh_kernel(const double* __restrict__ T, int p, HPackMaps mp, int rounds, int ng,
+                                 double* __restrict__ out) {
+  const int C = ncomp(p);
+  const int total = rounds * kQuads * ng * 32;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int c = i & 1;
+  int rest = i >> 1;
+  const int jj = rest & 15;
+  rest >>= 4;
+  const int g = rest % ng;
+  rest /= ng;
+  const int q = rest % kQuads;
+  const int r = rest / kQuads;
+  const int s = 4 * q + (jj >> 2);
+  const int k = mp.rowk[2 * r + c], n = mp.colk[4 * g + (jj & 3)];
+  out[i] = (k >= 0 && n >= 0) ? T[((size_t)s * C + k) * C + n] : 0.0;
+}
+
 // adjoint: [r][pair][kc][kk*4 + j] = T_{s_(j/2)}[2r + j%2][4kc + kk] (0 for a missing offset)
 __global__ void pack_bwd_kernel(const double* __restrict__ T, int p, const int4* __restrict__ pairs,
                                 int npairs, double* __restrict__ out) {
@@ -1139,7 +1242,7 @@ struct Config {
 constexpr Config kConfigs[] = {{2, 8, false, FMM_FP64}, {1, 8, false, FMM_FP64},
                                {0, 8, true, FMM_FP64},  {0, 8, false, FMM_FP64},
                                {0, 4, false, FMM_FP64}, {0, 4, true, FMM_FP64},
-                               {0, 8, false, FMM_SPLIT_FP32}};
+                               {0, 8, false, FMM_SPLIT_FP32}, {2, 8, false, FMM_FP64_HARMONIC}};
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
 }  // namespace
@@ -1168,6 +1271,118 @@ uint32_t plane_blocks(const std::vector<int>& st, int z, int o) {
     for (int by = (8 + dy) / 8; by <= (15 + dy) / 8; ++by) m |= 1u << (bx + 3 * by + 9 * bz);
   return m;
 }
+// ---- harmonic form: fold, round plan and expansion (host)
+
+struct MI3 {
+  int x, y, z;
+};
+
+std::vector<MI3> graded_indices(int p) {
+  std::vector<MI3> v;
+  for (int n = 0; n <= p; ++n)
+    for (int kx = n; kx >= 0; --kx)
+      for (int ky = n - kx; ky >= 0; --ky) v.push_back({kx, ky, n - kx - ky});
+  return v;
+}
+
+int index_of(const std::vector<MI3>& v, int a, int b, int c) {
+  for (size_t i = 0; i < v.size(); ++i)
+    if (v[i].x == a && v[i].y == b && v[i].z == c) return (int)i;
+  return -1;
+}
+
+// T(a,b,c) = -T(a+2,b,c-2) - T(a,b+2,c-2) for a family harmonic in its index,
+// applied until the z-index is 0 or 1: coefficients over the kz <= 1 indices
+void fold_into(const std::vector<MI3>& hs, int a, int b, int c, double coef, std::vector<double>* row) {
+  if (c <= 1) {
+    (*row)[index_of(hs, a, b, c)] += coef;
+    return;
+  }
+  fold_into(hs, a + 2, b, c - 2, -coef, row);
+  fold_into(hs, a, b + 2, c - 2, -coef, row);
+}
+
+struct HostHarmonic {
+  std::vector<HRound> rounds;
+  std::vector<HExp> exps;
+  HPackMaps maps;
+  int ng = 0;
+};
+
+// The folded components are staged two per round; pairs that share moment
+// components are formed first (largest overlap first), so each moment
+// component is read as few times as possible.
+bool build_harmonic(int p, HostHarmonic* out) {
+  const std::vector<MI3> ks = graded_indices(p);
+  std::vector<MI3> hs;
+  for (const MI3& k : ks)
+    if (k.z <= 1) hs.push_back(k);
+  const int C = (int)ks.size(), CR = (int)hs.size();
+  std::vector<std::vector<double>> F(C, std::vector<double>(CR, 0.0));   // F[k][k']
+  for (int k = 0; k < C; ++k) fold_into(hs, ks[k].x, ks[k].y, ks[k].z, 1.0, &F[k]);
+  std::vector<std::vector<int>> sup(CR);
+  for (int h = 0; h < CR; ++h)
+    for (int k = 0; k < C; ++k)
+      if (F[k][h] != 0.0) sup[h].push_back(k);
+  auto shared = [&](int a, int b) {
+    int n = 0;
+    for (int x : sup[a])
+      for (int y : sup[b]) n += x == y;
+    return n;
+  };
+  std::vector<std::pair<int, int>> pairs;
+  std::vector<bool> used(CR, false);
+  for (int best = CR; best >= 1; --best)
+    for (int a = 0; a < CR; ++a)
+      for (int b = a + 1; b < CR; ++b)
+        if (!used[a] && !used[b] && shared(a, b) == best) {
+          used[a] = used[b] = true;
+          pairs.push_back({a, b});
+        }
+  std::vector<int> rest;
+  for (int h = 0; h < CR; ++h)
+    if (!used[h]) rest.push_back(h);
+  for (size_t i = 0; i < rest.size(); i += 2)
+    pairs.push_back({rest[i], i + 1 < rest.size() ? rest[i + 1] : -1});
+  out->ng = (CR + 3) / 4;
+  if ((int)pairs.size() * 2 > 32 || out->ng * 4 > 32) return false;
+  for (int i = 0; i < 32; ++i) out->maps.rowk[i] = out->maps.colk[i] = -1;
+  for (size_t r = 0; r < pairs.size(); ++r) {
+    const int h0 = pairs[r].first, h1 = pairs[r].second;
+    std::vector<int> u = sup[h0];
+    if (h1 >= 0)
+      for (int k : sup[h1])
+        if (std::find(u.begin(), u.end(), k) == u.end()) u.push_back(k);
+    std::sort(u.begin(), u.end());
+    if ((int)u.size() > kHMaxSup) return false;
+    HRound rd{};
+    rd.nsup = (int)u.size();
+    rd.ord0 = hs[h0].x + hs[h0].y + hs[h0].z;
+    rd.ord1 = h1 >= 0 ? hs[h1].x + hs[h1].y + hs[h1].z : -1;
+    for (size_t i = 0; i < u.size(); ++i) {
+      rd.comp[i] = u[i];
+      rd.c0[i] = F[u[i]][h0];
+      rd.c1[i] = h1 >= 0 ? F[u[i]][h1] : 0.0;
+    }
+    out->rounds.push_back(rd);
+    out->maps.rowk[2 * r] = index_of(ks, hs[h0].x, hs[h0].y, hs[h0].z);
+    out->maps.rowk[2 * r + 1] = h1 >= 0 ? index_of(ks, hs[h1].x, hs[h1].y, hs[h1].z) : -1;
+  }
+  for (int h = 0; h < CR; ++h) out->maps.colk[h] = index_of(ks, hs[h].x, hs[h].y, hs[h].z);
+  for (int k = 0; k < C; ++k) {
+    HExp ex{};
+    for (int h = 0; h < CR; ++h)
+      if (F[k][h] != 0.0) {
+        if (ex.nterm == kHMaxExp) return false;
+        ex.col[ex.nterm] = h;
+        ex.coef[ex.nterm] = F[k][h];
+        ++ex.nterm;
+      }
+    out->exps.push_back(ex);
+  }
+  return true;
+}
+
 }  // namespace
 
 hipError_t mfma_tables_create(MfmaTables* t, double* const* d_T, const int* d_stencil,
@@ -1222,6 +1437,19 @@ hipError_t mfma_tables_create(MfmaTables* t, double* const* d_T, const int* d_st
     hipLaunchKernelGGL(pack_bwd_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, d_T[p], p,
                        t->pairs, t->npairs, t->bwd[p]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    HostHarmonic hh;
+    if (!build_harmonic(p, &hh)) return hipErrorInvalidValue;
+    const size_t nh = hh.rounds.size() * (size_t)kQuads * hh.ng * 32;
+    if ((e = hipMalloc(&t->fwdh[p], nh * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc(&t->hround[p], hh.rounds.size() * sizeof(HRound))) != hipSuccess) return e;
+    if ((e = hipMalloc(&t->hexp[p], hh.exps.size() * sizeof(HExp))) != hipSuccess) return e;
+    if ((e = hipMemcpy(t->hround[p], hh.rounds.data(), hh.rounds.size() * sizeof(HRound),
+                       hipMemcpyHostToDevice)) != hipSuccess) return e;
+    if ((e = hipMemcpy(t->hexp[p], hh.exps.data(), hh.exps.size() * sizeof(HExp),
+                       hipMemcpyHostToDevice)) != hipSuccess) return e;
+    hipLaunchKernelGGL(pack_fwdh_kernel, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s, d_T[p], p,
+                       hh.maps, (int)hh.rounds.size(), hh.ng, t->fwdh[p]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -1234,6 +1462,12 @@ void mfma_tables_destroy(MfmaTables* t) {
     if (t->fwd_hi[p]) (void)hipFree(t->fwd_hi[p]);
     if (t->fwd_lo[p]) (void)hipFree(t->fwd_lo[p]);
     if (t->bwd[p]) (void)hipFree(t->bwd[p]);
+    if (t->fwdh[p]) (void)hipFree(t->fwdh[p]);
+    if (t->hround[p]) (void)hipFree(t->hround[p]);
+    if (t->hexp[p]) (void)hipFree(t->hexp[p]);
+    t->fwdh[p] = nullptr;
+    t->hround[p] = nullptr;
+    t->hexp[p] = nullptr;
     t->fwd[p] = t->bwd[p] = nullptr;
     t->fwd_hi[p] = t->fwd_lo[p] = nullptr;
   }
@@ -1269,6 +1503,12 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
   const int grid = std::min(t.num_cu, w.count);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, w.counter);
   const Config& c = kConfigs[cfg];
+  if (c.prec == FMM_FP64_HARMONIC) {
+    hipLaunchKernelGGL((m2l_fwd_bl_kernel<true, true>), dim3(grid), dim3(kBlThreads), 0, s, w.items,
+                       w.count, w.counter, d_desc, M, L, t.fwdh[2], t.fwdh[3], t.fwdh[4], t.lds_off,
+                       t.touch, t.hround[2], t.hround[3], t.hround[4], t.hexp[2], t.hexp[3], t.hexp[4]);
+    return hipGetLastError();
+  }
   if (c.prec == FMM_SPLIT_FP32) {
     hipLaunchKernelGGL(m2l_fwd_split_kernel, dim3(grid), dim3(512), 0, s, w.items, w.count, w.counter,
                        d_desc, M, L, t.fwd_hi[2], t.fwd_lo[2], t.fwd_hi[3], t.fwd_lo[3], t.fwd_hi[4],
@@ -1276,12 +1516,16 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
     return hipGetLastError();
   }
   if (c.ldstab) {
+    const HRound* nr = nullptr;
+    const HExp* ne = nullptr;
     if (c.ldstab == 2)
-      hipLaunchKernelGGL(m2l_fwd_bl_kernel<true>, dim3(grid), dim3(kBlThreads), 0, s, w.items, w.count,
-                         w.counter, d_desc, M, L, t.fwdl[2], t.fwdl[3], t.fwdl[4], t.lds_off, t.touch);
+      hipLaunchKernelGGL((m2l_fwd_bl_kernel<true, false>), dim3(grid), dim3(kBlThreads), 0, s, w.items,
+                         w.count, w.counter, d_desc, M, L, t.fwdl[2], t.fwdl[3], t.fwdl[4], t.lds_off,
+                         t.touch, nr, nr, nr, ne, ne, ne);
     else
-      hipLaunchKernelGGL(m2l_fwd_bl_kernel<false>, dim3(grid), dim3(kBlThreads), 0, s, w.items, w.count,
-                         w.counter, d_desc, M, L, t.fwdl[2], t.fwdl[3], t.fwdl[4], t.lds_off, t.touch);
+      hipLaunchKernelGGL((m2l_fwd_bl_kernel<false, false>), dim3(grid), dim3(kBlThreads), 0, s, w.items,
+                         w.count, w.counter, d_desc, M, L, t.fwdl[2], t.fwdl[3], t.fwdl[4], t.lds_off,
+                         t.touch, nr, nr, nr, ne, ne, ne);
     return hipGetLastError();
   }
 #define FWD_LAUNCH(W, PFV)                                                                         \

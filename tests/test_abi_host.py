@@ -113,6 +113,22 @@ def test_host_only_context_reports_unsupported_after_checks(hctx, lib):
     assert lib.fmm_pair_count(None, 0, ctypes.byref(n)) == 0 and n.value == 0
 
 
+def test_harmonic_precision_checks(hctx):
+    desc, _, _ = fmm.make_descriptors([3], [0], [synth.FULL_MASK])
+    # accepted by the checks (a host-only context then reports unsupported)
+    with pytest.raises(fmm.FMMError) as e:
+        hctx.m2l(desc, 8, 8, precision=fmm.FMM_FP64_HARMONIC)
+    assert e.value.status == fmm.FMM_EUNSUPPORTED
+    # the reference kernel computes the dense float64 form only
+    hctx.set_option(fmm.FMM_OPT_M2L_KERNEL, 1)
+    try:
+        with pytest.raises(fmm.FMMError) as e:
+            hctx.m2l(desc, 8, 8, precision=fmm.FMM_FP64_HARMONIC)
+        assert e.value.status == fmm.FMM_EINVAL
+    finally:
+        hctx.set_option(fmm.FMM_OPT_M2L_KERNEL, 0)
+
+
 def test_null_context_and_create_errors(lib):
     assert lib.fmm_m2l(None, None, 0, None, None, 0, None) == fmm.FMM_EINVAL
     assert lib.fmm_destroy(None) == fmm.FMM_OK

@@ -326,3 +326,50 @@ def test_backward_is_deterministic(ctx, torch):
         outs.append(dM)
     assert torch.isfinite(outs[0]).all()
     assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
+# ---------------------------------------------------------------------------
+# harmonic (traceless) form, against the dense oracle
+# ---------------------------------------------------------------------------
+
+HARM = fmm.FMM_FP64_HARMONIC
+
+
+def test_harmonic_form_matches_oracle(ctx, torch):
+    # one full sub-grid; mixed p, h and masks with absent blocks poisoned; the edge set
+    w = synth.config(1)
+    desc, pos, mass, M, L = forward(ctx, torch, w, [0], MFMA, prec=HARM)
+    _, Lo, La = oracle_subgrid(w, 0, pos[0], mass[0])
+    assert_close(L.cpu().numpy().reshape(Lo.shape), Lo, La, TOL, "harmonic single")
+    w = synth.config(3, nsub=9)
+    desc, pos, mass, M, L = forward(ctx, torch, w, range(9), MFMA, prec=HARM, poison=True)
+    Lg = split_views(L.cpu().numpy(), desc, "L")
+    for b in range(9):
+        _, Lo, La = oracle_subgrid(w, b, pos[b], mass[b])
+        assert_close(Lg[b], Lo, La, TOL, "harmonic sub-grid %d (p=%d, h=%g)" % (b, w.p[b], w.h(b)))
+    w = synth.Workload("edge", 17, np.array([4, 3, 2], np.int32), np.array([2, 0, 1], np.int32),
+                       np.array([1 << 13, synth.FULL_MASK, (1 << 13) | (1 << 0) | (1 << 26)], np.uint32))
+    desc, pos, mass, M, L = forward(ctx, torch, w, [0, 1, 2], MFMA, prec=HARM, poison=True)
+    Lg = split_views(L.cpu().numpy(), desc, "L")
+    for b in range(3):
+        _, Lo, La = oracle_subgrid(w, b, pos[b], mass[b])
+        assert_close(Lg[b], Lo, La, TOL, "harmonic edge %d" % b)
+
+
+def test_harmonic_form_deterministic_graphs_and_autotune(ctx, torch):
+    w = synth.config(3, nsub=5)
+    _, _, _, M, L_plain = forward(ctx, torch, w, range(5), MFMA, prec=HARM, graph=0)
+    desc, _, _ = descriptors(w, range(5))
+    ctx.set_option(fmm.FMM_OPT_USE_GRAPH, 1)
+    for rep in range(3):
+        L = torch.full_like(L_plain, float("nan"))
+        ctx.m2l(desc, M, L, HARM)
+        x = torch.ones(1000, device="cuda").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(L, L_plain), rep
+        assert x.item() == 1000
+    chosen = ctx.autotune(desc, M, L_plain, HARM)
+    L = torch.full_like(L_plain, float("nan"))
+    ctx.m2l(desc, M, L, HARM)
+    torch.cuda.synchronize()
+    assert chosen >= 0 and torch.equal(L, L_plain)
