@@ -7,7 +7,10 @@ cell, lognormal masses, seeded synthetic inputs), expansion order p = 3
 (C = 20), the 892-offset shell stencil, float64. A step is the forward hot
 path on that batch with inputs resident in HBM: P2M (point masses -> cell
 moments) then M2L (moments -> local coefficients of the 512 targets of every
-sub-grid). `value` is cell-pair interactions per second over the whole step.
+sub-grid) in float64, computed in the harmonic (traceless) form: (p+1)^2 = 16
+folded moment components against 16 local columns, then expanded to all 20.
+`value` is cell-pair interactions per second over the whole step. The dense
+20 x 20 form of the same M2L is timed on the same moments as an extra.
 
 The same run also measures, each on its own batch: the split-precision M2L
 (float32 matrix cores, hi/lo products) on the step's moments, with its error
@@ -43,8 +46,14 @@ def log(*a):
 
 
 def flops_per_pair(p):
+    """Dense form: 2 C^2 FLOP per (target, offset) pair."""
     C = (p + 1) * (p + 2) * (p + 3) // 6
     return 2 * C * C
+
+
+def harmonic_flops_per_pair(p):
+    """Harmonic form: 2 (p+1)^4 FLOP per pair (the executed matrix-core work)."""
+    return 2 * (p + 1) ** 4
 
 
 # ---------------------------------------------------------------------------
@@ -209,13 +218,14 @@ def main():
     M = torch.empty(m_el, dtype=torch.float64, device="cuda")
     L = torch.empty(l_el, dtype=torch.float64, device="cuda")
     ctx.p2m(desc, pos, mass, 8, M)
-    tuned = ctx.autotune(desc, M, L, fmm.FMM_FP64)    # tile configuration for this batch
+    tuned = ctx.autotune(desc, M, L, fmm.FMM_FP64_HARMONIC)    # configuration for this batch
+    ctx.m2l(desc, M, L, fmm.FMM_FP64_HARMONIC)                 # graph capture, untimed
 
     def step(ev, i):
         if ev: ev[0].record()
         ctx.p2m(desc, pos, mass, 8, M)
         if ev: ev[1].record()
-        ctx.m2l(desc, M, L, fmm.FMM_FP64)
+        ctx.m2l(desc, M, L, fmm.FMM_FP64_HARMONIC)
         if ev: ev[2].record()
 
     wall, seg = timed(torch, step, K, W, marks=2)
@@ -223,21 +233,29 @@ def main():
     p2m_ms, m2l_ms = seg[:, 0].mean(), seg[:, 1].mean()
     out["value"] = pairs / (wall / K)
     out["ms_per_step"] = ms_step
+    import torch.version as tv
     out["config"] = {"workload": "uniform_4096_p3", "subgrids": w.nsub, "p": 3, "components": 20,
                      "h": 1.0, "particles_per_cell": 8, "stencil_offsets": 892,
-                     "pairs_per_step": pairs, "step": "P2M + M2L (float64)",
+                     "pairs_per_step": pairs, "step": "P2M + M2L (float64, harmonic form)",
                      "p2m_ms": float(p2m_ms), "m2l_ms": float(m2l_ms),
-                     "m2l_ms_min": float(seg[:, 1].min()), "autotune_choice": tuned}
+                     "m2l_ms_median": float(np.median(seg[:, 1])), "m2l_ms_min": float(seg[:, 1].min()),
+                     "autotune_choice": tuned, "device": torch.cuda.get_device_name(0),
+                     "hip": getattr(tv, "hip", None), "torch": torch.__version__}
     log("step %.3f ms (P2M %.3f, M2L %.3f): %.4g pairs/s" % (ms_step, p2m_ms, m2l_ms, out["value"]))
-    fl = pairs * flops_per_pair(3)
-    achieved = fl / (m2l_ms * 1e-3) / 1e12
+    fl_exec = pairs * harmonic_flops_per_pair(3)      # executed matrix-core flops
+    fl_dense = pairs * flops_per_pair(3)              # the dense 2 C^2 form
+    achieved = fl_exec / (m2l_ms * 1e-3) / 1e12
     traffic = read_traffic(pairs)
-    kname = "m2l_fwd_bl_kernel" if tuned in (0, 1) else "m2l_fwd_kernel"
-    out["roofline"] = {"bound": "mfma", "kernel": "%s (v_mfma_f64_4x4x4, tile configuration %d)" % (kname, tuned),
+    out["roofline"] = {"bound": "mfma",
+                       "kernel": "m2l_fwd_bl_kernel<PIPE, HARM> (v_mfma_f64_4x4x4, harmonic form, "
+                                 "configuration %d)" % tuned,
                        "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                       "flops_per_launch": fl, "flops_per_pair": flops_per_pair(3)}
-    log("M2L FP64: %.2f TFLOP/s (%.1f%% of %.1f)" % (achieved, 100 * achieved / FP64_PEAK_TFLOPS, FP64_PEAK_TFLOPS))
+                       "flops_per_launch": fl_exec, "flops_per_pair": harmonic_flops_per_pair(3),
+                       "fp64_dense_equivalent_tflops": fl_dense / (m2l_ms * 1e-3) / 1e12,
+                       "dense_flops_per_pair": flops_per_pair(3)}
+    log("M2L FP64 harmonic: %.2f executed TFLOP/s (%.1f%% of %.1f); %.2f TFLOP/s dense-equivalent"
+        % (achieved, 100 * achieved / FP64_PEAK_TFLOPS, FP64_PEAK_TFLOPS, fl_dense / (m2l_ms * 1e-3) / 1e12))
 
     def pos_fn2(b):
         return synth.subgrid_particles(w.seed, b)
@@ -247,6 +265,27 @@ def main():
     out["parity_fp64"] = par
     assert par["max_rel_labs"] <= 1e-12, par
     log("FP64 parity on sampled sub-grids: max |dL|/Labs %.3g" % par["max_rel_labs"])
+
+    # ---------------- the dense form of the same M2L, on the same moments
+    Ld = torch.empty_like(L)
+    tuned_d = ctx.autotune(desc, M, Ld, fmm.FMM_FP64)
+
+    def step_dense(ev, i):
+        if ev: ev[0].record()
+        ctx.m2l(desc, M, Ld, fmm.FMM_FP64)
+        if ev: ev[1].record()
+
+    _, seg_d = timed(torch, step_dense, K, W, marks=1)
+    ms_d = seg_d[:, 0].mean()
+    par_d = sampled_parity(fmm, w, desc, Ld, [0, 4095], lambda b: synth.subgrid_particles(w.seed, b))
+    assert par_d["max_rel_labs"] <= 1e-12, par_d
+    out["dense_fp64"] = {"m2l_ms": float(ms_d), "pairs_per_s": pairs / (ms_d * 1e-3),
+                         "tflops": fl_dense / (ms_d * 1e-3) / 1e12,
+                         "frac_of_fp64_peak": fl_dense / (ms_d * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                         "autotune_choice": tuned_d, "parity": par_d,
+                         "harmonic_speedup": float(ms_d / m2l_ms)}
+    log("dense FP64 M2L %.3f ms (%.2f TFLOP/s), harmonic x%.2f" % (ms_d, fl_dense / (ms_d * 1e-3) / 1e12, ms_d / m2l_ms))
+    del Ld
 
     if not args.no_extras:
         # ---------------- split precision on the same moments
@@ -286,7 +325,7 @@ def main():
         def step_fb(ev, i):
             if ev: ev[0].record()
             ctx.p2m(desc=d5, pos=pos5, mass=mass5, ppc=8, M=M5)
-            ctx.m2l(d5, M5, L5)
+            ctx.m2l(d5, M5, L5, fmm.FMM_FP64_HARMONIC)
             if ev: ev[1].record()
             ctx.m2l_backward(d5, wt, dM5)      # dLoss/dL = w for loss = sum w . L
             ctx.p2m_backward(d5, pos5, 8, dM5, dm5)
@@ -295,6 +334,7 @@ def main():
         wall_fb, seg_fb = timed(torch, step_fb, max(3, K // 2), W, marks=2)
         fwd_ms, bwd_ms = seg_fb[:, 0].mean(), seg_fb[:, 1].mean()
         out["fwd_bwd"] = {"workload": "grad_2048_p3", "subgrids": w5.nsub, "pairs": pairs5,
+                          "forward": "P2M + M2L (harmonic form)", "backward": "M2L adjoint + P2M adjoint",
                           "fwd_ms": float(fwd_ms), "bwd_ms": float(bwd_ms),
                           "fwd_bwd_ms_per_batch": float(fwd_ms + bwd_ms),
                           "bwd_over_fwd": float(bwd_ms / fwd_ms)}
@@ -313,9 +353,17 @@ def main():
         ctx.p2m(d3, pos3, mass3, 8, M3)
         chosen = ctx.autotune(d3, M3, L3, fmm.FMM_FP64)
 
-        def step_u(ev, i):
+        def step_ud(ev, i):
             if ev: ev[0].record()
             ctx.m2l(d3, M3, L3)
+            if ev: ev[1].record()
+
+        _, seg_ud = timed(torch, step_ud, K, W, marks=1)
+        ms_ud = seg_ud[:, 0].mean()
+
+        def step_u(ev, i):
+            if ev: ev[0].record()
+            ctx.m2l(d3, M3, L3, fmm.FMM_FP64_HARMONIC)
             if ev: ev[1].record()
 
         wall_u, seg_u = timed(torch, step_u, K, W, marks=1)
@@ -327,10 +375,11 @@ def main():
         par3 = sampled_parity(fmm, w3, d3, L3, [0, 2999, 5999], pos_fn3)
         assert par3["max_rel_labs"] <= 1e-12, par3
         out["uneven"] = {"workload": "uneven_6000_mixed_p", "subgrids": w3.nsub, "pairs": pairs3,
-                         "m2l_ms": float(ms_u), "pairs_per_s": pairs3 / (ms_u * 1e-3),
-                         "useful_tflops": fl3 / (ms_u * 1e-3) / 1e12, "autotune_choice": chosen,
-                         "parity": par3}
-        log("uneven 6000: %.3f ms, %.4g pairs/s, %.2f TFLOP/s useful" % (ms_u, pairs3 / (ms_u * 1e-3), fl3 / (ms_u * 1e-3) / 1e12))
+                         "form": "harmonic", "m2l_ms": float(ms_u), "pairs_per_s": pairs3 / (ms_u * 1e-3),
+                         "dense_equivalent_tflops": fl3 / (ms_u * 1e-3) / 1e12,
+                         "dense_m2l_ms": float(ms_ud), "dense_tflops": fl3 / (ms_ud * 1e-3) / 1e12,
+                         "dense_autotune_choice": chosen, "parity": par3}
+        log("uneven 6000: harmonic %.3f ms (%.4g pairs/s), dense %.3f ms" % (ms_u, pairs3 / (ms_u * 1e-3), ms_ud))
         del pos3, mass3, M3, L3
         torch.cuda.empty_cache()
 
