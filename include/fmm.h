@@ -90,6 +90,10 @@ typedef struct {
 #define FMM_OPT_M2L_KERNEL  1  /* 0 auto (default), 1 reference VALU kernel, 2 MFMA kernel */
 #define FMM_OPT_USE_GRAPH   2  /* 1 (default): replay cached hipGraphs for M2L; 0: plain launches */
 #define FMM_OPT_TILE_CONFIG 3  /* -1 (default): autotuned/built-in choice; >= 0 forces a table entry */
+#define FMM_OPT_ADJOINT_FORM 4 /* fmm_m2l_backward: 0 (default) dense form; 1 harmonic form (the
+                                  transpose of the FMM_FP64_HARMONIC operator: dL folded to the
+                                  (p+1)^2 harmonic columns, dM expanded from the folded components;
+                                  equal to the dense adjoint up to rounding; MFMA kernel only) */
 
 /* Create a context on HIP device `device`, or a host-only context with
  * device = -1 (argument checking and host queries only; compute calls then

@@ -118,6 +118,7 @@ struct fmm_ctx {
   int m2l_kernel = 0;                         // 0 auto, 1 reference, 2 matrix core
   int use_graph = 1;
   int tile_config = -1;
+  int adjoint_form = 0;     // FMM_OPT_ADJOINT_FORM
 };
 
 namespace {
@@ -417,6 +418,10 @@ fmm_status fmm_set_option(fmm_ctx* ctx, int32_t option, int64_t value) {
       if (value != 0 && value != 1) return set_err(ctx, FMM_EINVAL, "FMM_OPT_USE_GRAPH value not 0/1");
       ctx->use_graph = (int)value;
       return FMM_OK;
+    case FMM_OPT_ADJOINT_FORM:
+      if (value != 0 && value != 1) return set_err(ctx, FMM_EINVAL, "FMM_OPT_ADJOINT_FORM value not 0/1");
+      ctx->adjoint_form = (int)value;
+      return FMM_OK;
     case FMM_OPT_TILE_CONFIG:
       if (value < -1 || value >= mfma_num_configs()) return set_err(ctx, FMM_EINVAL, "FMM_OPT_TILE_CONFIG out of range");
       ctx->tile_config = (int)value;
@@ -547,6 +552,8 @@ fmm_status fmm_m2l_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
   CHECK_OK(check_desc(ctx, desc, nsub));
   CHECK_OK(check_ptr(ctx, dL, "dL", nsub));
   CHECK_OK(check_ptr(ctx, dM, "dM", nsub));
+  if (ctx->adjoint_form == 1 && ctx->m2l_kernel == 1)
+    return set_err(ctx, FMM_EINVAL, "the reference kernel computes the dense adjoint only");
   if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
   if (nsub == 0) return FMM_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -557,7 +564,7 @@ fmm_status fmm_m2l_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
   if (ctx->m2l_kernel == 1) {
     CHECK_OK(run_ref(ctx, e, true, dL, dM, s));
   } else {
-    HIP_TRY(ctx, launch_m2l_mfma_backward(ctx->mfma, e->work, e->d_desc, dL, dM, s));
+    HIP_TRY(ctx, launch_m2l_mfma_backward(ctx->mfma, e->work, e->d_desc, dL, dM, ctx->adjoint_form == 1, s));
   }
   return mark_used(ctx, e, s);
 }

@@ -47,6 +47,25 @@ struct HExp {
   double coef[kHMaxExp];
 };
 
+// Harmonic adjoint. dL folds to the harmonic columns like M (Wh_n' = sum over n
+// of F[n][n'] W_n, one entry per n'); each round's two accumulators hold folded
+// output components Gh_k', and dM_k = sum_k' F[k][k'] Gh_k' is written from
+// them: a component whose folded terms span rounds is added to in each later
+// round by the thread that wrote it.
+struct HFold {
+  int32_t nterm;
+  int32_t comp[kHMaxSup];
+  double coef[kHMaxSup];
+};
+constexpr int kHMaxOut = 6;
+struct HOut {
+  int32_t nout;
+  int32_t comp[kHMaxOut];    // output component k
+  int32_t add[kHMaxOut];     // 1: add to the value written in an earlier round
+  double c0[kHMaxOut];       // coefficient of the round's first folded accumulator
+  double c1[kHMaxOut];       // and of its second
+};
+
 struct MfmaTables {
   // forward, per order p: [rounds][quad][comp of pair][n-group][kk*4 + j] float64
   double* fwd[kMaxP + 1] = {};
@@ -70,6 +89,11 @@ struct MfmaTables {
   double* fwdh[kMaxP + 1] = {};
   HRound* hround[kMaxP + 1] = {};
   HExp* hexp[kMaxP + 1] = {};
+  // harmonic adjoint, per order p: tables [rounds][offset pair][n' chunk][kk*4 + j], the
+  // fold of dL per harmonic column and the output plan per round
+  double* bwdh[kMaxP + 1] = {};
+  HFold* hfold[kMaxP + 1] = {};
+  HOut* hout[kMaxP + 1] = {};
   int num_cu = 0;
 };
 
@@ -84,7 +108,8 @@ int mfma_default_config(fmm_precision prec);
 hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc* d_desc,
                            const double* M, double* L, fmm_precision prec, int cfg,
                            hipStream_t s);
+// harmonic: the harmonic form of the adjoint (equal to the dense one up to rounding)
 hipError_t launch_m2l_mfma_backward(const MfmaTables& t, const WorkList& w, const DevDesc* d_desc,
-                                    const double* dL, double* dM, hipStream_t s);
+                                    const double* dL, double* dM, bool harmonic, hipStream_t s);
 
 }  // namespace fmm

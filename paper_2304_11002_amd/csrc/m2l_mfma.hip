@@ -883,15 +883,19 @@ constexpr int kMaxPairs = 512;
 
 // FULL: every neighbour block is present, so no pair is skipped and the pair
 // loop carries no branches.
-template <int P, bool FULL>
+// HARM: the harmonic form; dL is folded to the (p+1)^2 harmonic columns, the
+// rounds accumulate folded output components and the write-out expands them.
+template <int P, bool FULL, bool HARM = false>
 __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __restrict__ dL,
                                             double* __restrict__ dM, const double* __restrict__ Bp,
                                             int npairs, const int* s_gs,
                                             const uint32_t* __restrict__ ptouch, double* smem,
-                                            const int* s_po) {
+                                            const int* s_po, const HFold* __restrict__ hfold = nullptr,
+                                            const HOut* __restrict__ hout = nullptr) {
   constexpr int C = ncomp(P);
-  constexpr int KC = (C + 3) / 4;     // dL component chunks of 4 (the reduction)
-  constexpr int ROUNDS = (C + 1) / 2;
+  constexpr int CR = HARM ? (P + 1) * (P + 1) : C;   // reduced components
+  constexpr int KC = (CR + 3) / 4;    // dL component chunks of 4 (the reduction)
+  constexpr int ROUNDS = (CR + 1) / 2;
   constexpr int TPW = 4;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // target plane
@@ -910,7 +914,19 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
       const int n = 4 * kc + kk;
-      a[t][kc] = n < C ? ldexp(src[(size_t)n * kNTarget + tcell], l2 * (1 + order_of(n))) : 0.0;
+      if constexpr (HARM) {
+        // folded dL: the components that fold onto column n' (all of one order)
+        double v = 0.0;
+        if (n < CR) {
+          const HFold& f = hfold[n];
+          for (int u = 0; u < f.nterm; ++u)
+            v = __builtin_fma(f.coef[u], src[(size_t)f.comp[u] * kNTarget + tcell], v);
+          v = ldexp(v, l2 * (1 + order_of(f.comp[0])));
+        }
+        a[t][kc] = v;
+      } else {
+        a[t][kc] = n < C ? ldexp(src[(size_t)n * kNTarget + tcell], l2 * (1 + order_of(n))) : 0.0;
+      }
     }
     // D layout: lane holds target cell (x = lane/16, y = (lane%16)/4) of the tile
     obase[t] = (x0 + (lane >> 4) + 6) + kWin * (y0 + ((lane & 15) >> 2) + 6) + kWin * kWin * (wave + 6) +
@@ -1020,7 +1036,32 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
 #undef BW_INTERLEAVE
 #undef BW_STEP
 #undef BW_GROUP_END
-    // write the round's two components of dM (whole frame) and clear the accumulators
+    // write the round's components of dM (whole frame) and clear the accumulators
+    if constexpr (HARM) {
+      const HOut& ho = hout[r];
+      for (int c = tid; c < kNCell; c += kBwdThreads) {
+        const int jx = c % kFrame, jy = (c / kFrame) % kFrame, jz = c / (kFrame * kFrame);
+        const bool win = jx >= kWin0 && jx < kWin0 + kWin && jy >= kWin0 && jy < kWin0 + kWin &&
+                         jz >= kWin0 && jz < kWin0 + kWin;
+        const bool pres = win && block_present(d.mask, jx, jy, jz);
+        const int wc = (jx - kWin0) + kWin * (jy - kWin0) + kWin * kWin * (jz - kWin0);
+        double g0 = 0.0, g1 = 0.0;
+        if (win) {
+          g0 = smem[wc];
+          g1 = smem[kAccStride + wc];
+          smem[wc] = 0.0;
+          smem[kAccStride + wc] = 0.0;
+        }
+        for (int e = 0; e < ho.nout; ++e) {
+          const int k = ho.comp[e];
+          double* o = out + (size_t)k * kNCell + c;
+          double v = __builtin_fma(ho.c1[e], g1, ho.c0[e] * g0);
+          v = pres ? ldexp(v, l2 * order_of(k)) : 0.0;
+          *o = ho.add[e] ? *o + v : v;
+        }
+      }
+      continue;
+    }
     const double sc0 = ldexp(1.0, l2 * order_of(2 * r));
     const double sc1 = ldexp(1.0, l2 * order_of(2 * r + 1));
     for (int c = tid; c < kNCell; c += kBwdThreads) {
@@ -1043,12 +1084,15 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
   }
 }
 
+template <bool HARM>
 __global__ void __launch_bounds__(kBwdThreads) m2l_bwd_kernel(
     const WorkItem* __restrict__ items, int count, unsigned* __restrict__ counter,
     const DevDesc* __restrict__ desc, const double* __restrict__ dL, double* __restrict__ dM,
     const double* __restrict__ B2, const double* __restrict__ B3, const double* __restrict__ B4,
     const int4* __restrict__ pairs, int npairs, const int* __restrict__ gstart,
-    const uint32_t* __restrict__ ptouch) {
+    const uint32_t* __restrict__ ptouch, const HFold* __restrict__ hf2, const HFold* __restrict__ hf3,
+    const HFold* __restrict__ hf4, const HOut* __restrict__ ho2, const HOut* __restrict__ ho3,
+    const HOut* __restrict__ ho4) {
   __shared__ double smem[2 * kAccStride];
   __shared__ int s_po[2 * kMaxPairs];     // output offsets of each pair's two offsets
   __shared__ int s_gs[16];                // first pair of each dz group, and the end
@@ -1070,16 +1114,16 @@ __global__ void __launch_bounds__(kBwdThreads) m2l_bwd_kernel(
     const bool full = d.mask == kFullMask;
     switch (d.p) {
       case 2:
-        if (full) bwd_subgrid<2, true>(d, dL, dM, B2, npairs, s_gs, ptouch, smem, s_po);
-        else bwd_subgrid<2, false>(d, dL, dM, B2, npairs, s_gs, ptouch, smem, s_po);
+        if (full) bwd_subgrid<2, true, HARM>(d, dL, dM, B2, npairs, s_gs, ptouch, smem, s_po, hf2, ho2);
+        else bwd_subgrid<2, false, HARM>(d, dL, dM, B2, npairs, s_gs, ptouch, smem, s_po, hf2, ho2);
         break;
       case 3:
-        if (full) bwd_subgrid<3, true>(d, dL, dM, B3, npairs, s_gs, ptouch, smem, s_po);
-        else bwd_subgrid<3, false>(d, dL, dM, B3, npairs, s_gs, ptouch, smem, s_po);
+        if (full) bwd_subgrid<3, true, HARM>(d, dL, dM, B3, npairs, s_gs, ptouch, smem, s_po, hf3, ho3);
+        else bwd_subgrid<3, false, HARM>(d, dL, dM, B3, npairs, s_gs, ptouch, smem, s_po, hf3, ho3);
         break;
       case 4:
-        if (full) bwd_subgrid<4, true>(d, dL, dM, B4, npairs, s_gs, ptouch, smem, s_po);
-        else bwd_subgrid<4, false>(d, dL, dM, B4, npairs, s_gs, ptouch, smem, s_po);
+        if (full) bwd_subgrid<4, true, HARM>(d, dL, dM, B4, npairs, s_gs, ptouch, smem, s_po, hf4, ho4);
+        else bwd_subgrid<4, false, HARM>(d, dL, dM, B4, npairs, s_gs, ptouch, smem, s_po, hf4, ho4);
         break;
       default: break;
     }
@@ -1137,6 +1181,25 @@ __global__ void pack_fwdh_kernel(const double* __restrict__ T, int p, HPackMaps 
   const int s = 4 * q + (jj >> 2);
   const int k = mp.rowk[2 * r + c], n = mp.colk[4 * g + (jj & 3)];
   out[i] = (k >= 0 && n >= 0) ? T[((size_t)s * C + k) * C + n] : 0.0;
+}
+
+// harmonic adjoint: [r][pair][kc][kk*4 + j] = T_{s_(j/2)}[rowk[2r + j%2]][colk[4kc + kk]]
+__global__ void pack_bwdh_kernel(const double* __restrict__ T, int p, const int4* __restrict__ pairs,
+                                 int npairs, HPackMaps mp, int rounds, int kcn, double* __restrict__ out) {
+  const int C = ncomp(p);
+  const int total = rounds * npairs * kcn * 16;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int j = i & 3, kk = (i >> 2) & 3;
+  int rest = i >> 4;
+  const int kc = rest % kcn;
+  rest /= kcn;
+  const int q = rest % npairs;
+  const int r = rest / npairs;
+  const int4 pr = pairs[q];
+  const int so = (j >> 1) ? pr.w : pr.z;
+  const int k = mp.rowk[2 * r + (j & 1)], n = mp.colk[4 * kc + kk];
+  out[i] = (so >= 0 && k >= 0 && n >= 0) ? T[((size_t)so * C + k) * C + n] : 0.0;
 }
 
 // adjoint: [r][pair][kc][kk*4 + j] = T_{s_(j/2)}[2r + j%2][4kc + kk] (0 for a missing offset)
@@ -1305,6 +1368,8 @@ void fold_into(const std::vector<MI3>& hs, int a, int b, int c, double coef, std
 struct HostHarmonic {
   std::vector<HRound> rounds;
   std::vector<HExp> exps;
+  std::vector<HFold> folds;   // per harmonic column: the components folding onto it
+  std::vector<HOut> outs;     // per round: the output components written from it
   HPackMaps maps;
   int ng = 0;
 };
@@ -1369,6 +1434,37 @@ bool build_harmonic(int p, HostHarmonic* out) {
     out->maps.rowk[2 * r + 1] = h1 >= 0 ? index_of(ks, hs[h1].x, hs[h1].y, hs[h1].z) : -1;
   }
   for (int h = 0; h < CR; ++h) out->maps.colk[h] = index_of(ks, hs[h].x, hs[h].y, hs[h].z);
+  // adjoint: the fold of dL onto each harmonic column
+  for (int h = 0; h < CR; ++h) {
+    if ((int)sup[h].size() > kHMaxSup) return false;
+    HFold f{};
+    f.nterm = (int)sup[h].size();
+    for (size_t i = 0; i < sup[h].size(); ++i) {
+      f.comp[i] = sup[h][i];
+      f.coef[i] = F[sup[h][i]][h];
+    }
+    out->folds.push_back(f);
+  }
+  // adjoint: dM_k = sum_k' F[k][k'] Gh_k', written from each round holding some k'
+  std::vector<bool> written(C, false);
+  out->outs.assign(pairs.size(), HOut{});
+  for (size_t r = 0; r < pairs.size(); ++r) {
+    const int h0 = pairs[r].first, h1 = pairs[r].second;
+    HOut& o = out->outs[r];
+    for (int k = 0; k < C; ++k) {
+      const double c0 = F[k][h0], c1 = h1 >= 0 ? F[k][h1] : 0.0;
+      if (c0 == 0.0 && c1 == 0.0) continue;
+      if (o.nout == kHMaxOut) return false;
+      o.comp[o.nout] = k;
+      o.add[o.nout] = written[k] ? 1 : 0;
+      o.c0[o.nout] = c0;
+      o.c1[o.nout] = c1;
+      ++o.nout;
+      written[k] = true;
+    }
+  }
+  for (int k = 0; k < C; ++k)
+    if (!written[k]) return false;
   for (int k = 0; k < C; ++k) {
     HExp ex{};
     for (int h = 0; h < CR; ++h)
@@ -1450,6 +1546,17 @@ hipError_t mfma_tables_create(MfmaTables* t, double* const* d_T, const int* d_st
     hipLaunchKernelGGL(pack_fwdh_kernel, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s, d_T[p], p,
                        hh.maps, (int)hh.rounds.size(), hh.ng, t->fwdh[p]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t nbh = hh.rounds.size() * (size_t)t->npairs * hh.ng * 16;   // ng = n'-chunks of 4
+    if ((e = hipMalloc(&t->bwdh[p], nbh * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc(&t->hfold[p], hh.folds.size() * sizeof(HFold))) != hipSuccess) return e;
+    if ((e = hipMalloc(&t->hout[p], hh.outs.size() * sizeof(HOut))) != hipSuccess) return e;
+    if ((e = hipMemcpy(t->hfold[p], hh.folds.data(), hh.folds.size() * sizeof(HFold),
+                       hipMemcpyHostToDevice)) != hipSuccess) return e;
+    if ((e = hipMemcpy(t->hout[p], hh.outs.data(), hh.outs.size() * sizeof(HOut),
+                       hipMemcpyHostToDevice)) != hipSuccess) return e;
+    hipLaunchKernelGGL(pack_bwdh_kernel, dim3((unsigned)((nbh + 255) / 256)), dim3(256), 0, s, d_T[p], p,
+                       t->pairs, t->npairs, hh.maps, (int)hh.rounds.size(), hh.ng, t->bwdh[p]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -1465,6 +1572,12 @@ void mfma_tables_destroy(MfmaTables* t) {
     if (t->fwdh[p]) (void)hipFree(t->fwdh[p]);
     if (t->hround[p]) (void)hipFree(t->hround[p]);
     if (t->hexp[p]) (void)hipFree(t->hexp[p]);
+    if (t->bwdh[p]) (void)hipFree(t->bwdh[p]);
+    if (t->hfold[p]) (void)hipFree(t->hfold[p]);
+    if (t->hout[p]) (void)hipFree(t->hout[p]);
+    t->bwdh[p] = nullptr;
+    t->hfold[p] = nullptr;
+    t->hout[p] = nullptr;
     t->fwdh[p] = nullptr;
     t->hround[p] = nullptr;
     t->hexp[p] = nullptr;
@@ -1541,13 +1654,22 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
 }
 
 hipError_t launch_m2l_mfma_backward(const MfmaTables& t, const WorkList& w, const DevDesc* d_desc,
-                                    const double* dL, double* dM, hipStream_t s) {
+                                    const double* dL, double* dM, bool harmonic, hipStream_t s) {
   if (w.count == 0) return hipSuccess;
   const int grid = std::min(t.num_cu, w.count);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, w.counter);
-  hipLaunchKernelGGL(m2l_bwd_kernel, dim3(grid), dim3(kBwdThreads), 0, s, w.items, w.count, w.counter,
-                     d_desc, dL, dM, t.bwd[2], t.bwd[3], t.bwd[4], t.pairs, t.npairs, t.gstart,
-                     t.ptouch);
+  if (harmonic) {
+    hipLaunchKernelGGL(m2l_bwd_kernel<true>, dim3(grid), dim3(kBwdThreads), 0, s, w.items, w.count,
+                       w.counter, d_desc, dL, dM, t.bwdh[2], t.bwdh[3], t.bwdh[4], t.pairs, t.npairs,
+                       t.gstart, t.ptouch, t.hfold[2], t.hfold[3], t.hfold[4], t.hout[2], t.hout[3],
+                       t.hout[4]);
+  } else {
+    const HFold* nf = nullptr;
+    const HOut* no = nullptr;
+    hipLaunchKernelGGL(m2l_bwd_kernel<false>, dim3(grid), dim3(kBwdThreads), 0, s, w.items, w.count,
+                       w.counter, d_desc, dL, dM, t.bwd[2], t.bwd[3], t.bwd[4], t.pairs, t.npairs,
+                       t.gstart, t.ptouch, nf, nf, nf, no, no, no);
+  }
   return hipGetLastError();
 }
 

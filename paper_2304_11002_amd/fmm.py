@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libfmm.so")
 
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_EUNSUPPORTED = 0, -1, -2, -3, -4
 FMM_FP64, FMM_SPLIT_FP32, FMM_FP64_HARMONIC = 0, 1, 2
-FMM_OPT_M2L_KERNEL, FMM_OPT_USE_GRAPH, FMM_OPT_TILE_CONFIG = 1, 2, 3
+FMM_OPT_M2L_KERNEL, FMM_OPT_USE_GRAPH, FMM_OPT_TILE_CONFIG, FMM_OPT_ADJOINT_FORM = 1, 2, 3, 4
 
 FRAME, NCELL, NTARGET = 24, 24 ** 3, 512
 FULL_MASK = (1 << 27) - 1

@@ -121,12 +121,19 @@ def test_harmonic_precision_checks(hctx):
     assert e.value.status == fmm.FMM_EUNSUPPORTED
     # the reference kernel computes the dense float64 form only
     hctx.set_option(fmm.FMM_OPT_M2L_KERNEL, 1)
+    hctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 1)
     try:
-        with pytest.raises(fmm.FMMError) as e:
-            hctx.m2l(desc, 8, 8, precision=fmm.FMM_FP64_HARMONIC)
-        assert e.value.status == fmm.FMM_EINVAL
+        for call in (lambda: hctx.m2l(desc, 8, 8, precision=fmm.FMM_FP64_HARMONIC),
+                     lambda: hctx.m2l_backward(desc, 8, 8)):
+            with pytest.raises(fmm.FMMError) as e:
+                call()
+            assert e.value.status == fmm.FMM_EINVAL
     finally:
         hctx.set_option(fmm.FMM_OPT_M2L_KERNEL, 0)
+        hctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 0)
+    with pytest.raises(fmm.FMMError) as e:
+        hctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 2)
+    assert e.value.status == fmm.FMM_EINVAL
 
 
 def test_null_context_and_create_errors(lib):

@@ -373,3 +373,48 @@ def test_harmonic_form_deterministic_graphs_and_autotune(ctx, torch):
     ctx.m2l(desc, M, L, HARM)
     torch.cuda.synchronize()
     assert chosen >= 0 and torch.equal(L, L_plain)
+
+
+def test_harmonic_adjoint_matches_oracle_and_is_deterministic(ctx, torch):
+    # the harmonic adjoint against the dense oracle adjoint; mixed p, h and masks
+    w = synth.config(3, nsub=9)
+    idx = list(range(9))
+    desc, m_el, l_el = descriptors(w, idx)
+    W = np.random.default_rng(78).standard_normal(l_el)
+    dW = to_dev(W)
+    ctx.set_option(fmm.FMM_OPT_M2L_KERNEL, MFMA)
+    ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 1)
+    try:
+        dM = torch.full((m_el,), float("nan"), dtype=torch.float64, device="cuda")
+        ctx.m2l_backward(desc, dW, dM)
+        dM2 = torch.full_like(dM, float("nan"))
+        ctx.m2l_backward(desc, dW, dM2)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 0)
+    assert torch.equal(dM, dM2)
+    Gg = split_views(dM.cpu().numpy(), desc, "M")
+    Wv = split_views(W, desc, "L")
+    assert sorted(set(w.p.tolist())) == [2, 3, 4]
+    for b in idx:
+        p, h, mask = int(w.p[b]), w.h(b), int(w.mask[b])
+        Go = O.m2l_adjoint(Wv[b], p, h, mask)
+        Ga = O.m2l_adjoint_abs(Wv[b], p, h, mask)
+        assert_close(Gg[b], Go, Ga, TOL, "harmonic dM sub-grid %d (p=%d)" % (b, p))
+
+
+def test_harmonic_adjoint_dot_product(ctx, torch):
+    # <W, L(M)> = <dM(W), M> between the harmonic forward and the harmonic adjoint
+    w = synth.config(3, nsub=4)
+    desc, pos, mass, M, L = forward(ctx, torch, w, range(4), MFMA, prec=HARM)
+    W = np.random.default_rng(4).standard_normal(L.numel())
+    dM = torch.empty_like(M)
+    ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 1)
+    try:
+        ctx.m2l_backward(desc, to_dev(W), dM)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 0)
+    lhs = float(np.dot(W, L.cpu().numpy()))
+    rhs = float(np.dot(dM.cpu().numpy(), M.cpu().numpy()))
+    assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + abs(rhs))
