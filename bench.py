@@ -332,10 +332,16 @@ def main():
             ctx.p2m_backward(d5, pos5, 8, dM5, dm5)
             if ev: ev[2].record()
 
+        ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 1)      # harmonic adjoint with the harmonic forward
         wall_fb, seg_fb = timed(torch, step_fb, max(3, K // 2), W, marks=2)
         fwd_ms, bwd_ms = seg_fb[:, 0].mean(), seg_fb[:, 1].mean()
+        ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 0)
+        _, seg_fbd = timed(torch, step_fb, max(3, K // 2), 1, marks=2)
+        bwd_dense_ms = seg_fbd[:, 1].mean()
         out["fwd_bwd"] = {"workload": "grad_2048_p3", "subgrids": w5.nsub, "pairs": pairs5,
-                          "forward": "P2M + M2L (harmonic form)", "backward": "M2L adjoint + P2M adjoint",
+                          "forward": "P2M + M2L (harmonic form)",
+                          "backward": "M2L adjoint (harmonic form) + P2M adjoint",
+                          "bwd_ms_dense_adjoint": float(bwd_dense_ms),
                           "fwd_ms": float(fwd_ms), "bwd_ms": float(bwd_ms),
                           "fwd_bwd_ms_per_batch": float(fwd_ms + bwd_ms),
                           "bwd_over_fwd": float(bwd_ms / fwd_ms)}

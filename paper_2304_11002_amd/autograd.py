@@ -4,8 +4,10 @@
 
 Forward runs fmm_p2m and fmm_m2l; backward runs fmm_m2l_backward (adjoint
 M2L, dL -> dM) and fmm_p2m_backward (dM -> d mass). Positions are held
-fixed (no gradient). Every step runs in the library's HIP kernels; torch
-supplies device memory and the stream.
+fixed (no gradient). harmonic=True computes M2L and its adjoint in the
+harmonic (traceless) form, equal to the dense form up to rounding. Every
+step runs in the library's HIP kernels; torch supplies device memory and
+the stream.
 """
 import torch
 
@@ -14,14 +16,15 @@ from . import fmm
 
 class FMMGravity(torch.autograd.Function):
     @staticmethod
-    def forward(actx, mass, pos, handle, desc, ppc, m_elems, l_elems):
+    def forward(actx, mass, pos, handle, desc, ppc, m_elems, l_elems, harmonic):
         M = torch.empty(m_elems, dtype=torch.float64, device=mass.device)
         L = torch.empty(l_elems, dtype=torch.float64, device=mass.device)
         mass_c = mass.contiguous()
         handle.p2m(desc, pos, mass_c, ppc, M)
-        handle.m2l(desc, M, L, fmm.FMM_FP64)
+        handle.m2l(desc, M, L, fmm.FMM_FP64_HARMONIC if harmonic else fmm.FMM_FP64)
         actx.save_for_backward(pos)
         actx.handle, actx.desc, actx.ppc, actx.m_elems = handle, desc, ppc, m_elems
+        actx.harmonic = harmonic
         actx.mass_shape = mass.shape
         return L
 
@@ -30,13 +33,17 @@ class FMMGravity(torch.autograd.Function):
         (pos,) = actx.saved_tensors
         gL = gL.contiguous()
         dM = torch.empty(actx.m_elems, dtype=torch.float64, device=gL.device)
-        actx.handle.m2l_backward(actx.desc, gL, dM)
+        actx.handle.set_option(fmm.FMM_OPT_ADJOINT_FORM, 1 if actx.harmonic else 0)
+        try:
+            actx.handle.m2l_backward(actx.desc, gL, dM)
+        finally:
+            actx.handle.set_option(fmm.FMM_OPT_ADJOINT_FORM, 0)
         dmass = torch.empty(actx.mass_shape, dtype=torch.float64, device=gL.device)
         actx.handle.p2m_backward(actx.desc, pos, actx.ppc, dM, dmass)
-        return dmass, None, None, None, None, None, None
+        return dmass, None, None, None, None, None, None, None
 
 
-def gravity_local_expansion(handle, desc, pos, mass, ppc=8):
+def gravity_local_expansion(handle, desc, pos, mass, ppc=8, harmonic=False):
     """L of every sub-grid (flat, ragged by order), differentiable in `mass`."""
     if pos.dtype != torch.float64 or mass.dtype != torch.float64:
         raise TypeError("pos and mass must be float64")
@@ -46,4 +53,4 @@ def gravity_local_expansion(handle, desc, pos, mass, ppc=8):
     C = (p + 1) * (p + 2) * (p + 3) // 6
     m_elems = int((C * fmm.NCELL).sum())
     l_elems = int((C * fmm.NTARGET).sum())
-    return FMMGravity.apply(mass, pos.contiguous(), handle, desc, ppc, m_elems, l_elems)
+    return FMMGravity.apply(mass, pos.contiguous(), handle, desc, ppc, m_elems, l_elems, harmonic)

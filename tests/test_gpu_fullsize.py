@@ -163,7 +163,8 @@ def test_gradient_2048_fd_and_oracle(ctx, torch):
         assert np.all(np.abs(gb - go) <= TOL * scale)
 
 
-def test_gradcheck_fast_mode_one_subgrid(ctx, torch):
+@pytest.mark.parametrize("harmonic", [False, True])
+def test_gradcheck_fast_mode_one_subgrid(ctx, torch, harmonic):
     from paper_2304_11002_amd.autograd import gravity_local_expansion
     w = synth.config(3, nsub=2)
     desc, _, _ = fmm.make_descriptors(w.p, w.log2_inv_h, w.mask)
@@ -178,5 +179,6 @@ def test_gradcheck_fast_mode_one_subgrid(ctx, torch):
     # up to rounding; with |L_0| ~ 3e3 the rounding of L(m +- eps u) limits the
     # numerical side to ~1e-5 relative, hence the tolerances (the exact gradient is
     # checked against the oracle above)
-    assert torch.autograd.gradcheck(lambda m: gravity_local_expansion(ctx, desc, pos, m), (mass,),
+    assert torch.autograd.gradcheck(lambda m: gravity_local_expansion(ctx, desc, pos, m, harmonic=harmonic),
+                                    (mass,),
                                     eps=1e-6, atol=1e-4, rtol=1e-4, fast_mode=True)
