@@ -38,6 +38,12 @@ from .fmm import (  # noqa: F401
     m2l,
     m2l_abs,
     m2l_adjoint,
+    near_stencil,
+    l2p,
+    l2p_abs,
+    near_field,
+    near_field_abs,
+    evaluate,
     harmonic_indices,
     harmonic_fold,
     m2l_harmonic,

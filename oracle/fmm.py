@@ -320,6 +320,112 @@ def direct_sum(pos, mass, h, order, mask=FULL_MASK, offsets=None, targets=None):
 
 
 # ---------------------------------------------------------------------------
+# evaluation at the target particles: near field and L2P
+# ---------------------------------------------------------------------------
+
+def near_stencil():
+    """N = {d in Z^3 : |d|^2 <= 4}, 33 offsets including d = 0: the cells whose
+    particles are summed directly. With the M2L shell S (5 <= |d|^2 <= 36) it
+    covers every same-level cell with |d| <= 6."""
+    return stencil(0, 4)
+
+
+def _target_cells():
+    """Frame indices j of the 512 target cells, in target order (x fastest)."""
+    return [(x + BLOCK, y + BLOCK, z + BLOCK)
+            for z in range(BLOCK) for y in range(BLOCK) for x in range(BLOCK)]
+
+
+def l2p(L, pos, p, h):
+    """Far-field potential and gradient at the target block's particles.
+
+    phi(y) = sum_n L_n(t) b^n / n! and d phi / d y_i = sum_{|m| <= p-1} L_{m + e_i}(t) b^m / m!,
+    b = y - c_t (the Taylor polynomial of the local expansion and its gradient).
+    L [C, 8, 8, 8]; pos [13824, ppc, 3]. Returns [4, 512, ppc]: phi, gx, gy, gz.
+    """
+    ks = multi_indices(p)
+    pos = np.asarray(pos, dtype=np.float64)
+    Lf = np.asarray(L, dtype=np.float64).reshape(len(ks), -1)
+    ppc = pos.shape[1]
+    out = np.zeros((4, BLOCK ** 3, ppc))
+    for t, j in enumerate(_target_cells()):
+        cell = j[0] + FRAME * j[1] + FRAME * FRAME * j[2]
+        c = (np.array(j) + 0.5) * h
+        b = pos[cell] - c[None, :]                      # [ppc, 3]
+        mono = _monomials(b, p)                         # [C, ppc], b^n / n!
+        out[0, t] = Lf[:, t] @ mono
+        for ax in range(3):
+            e = [0, 0, 0]
+            e[ax] = 1
+            for c_m, m in enumerate(ks):
+                if sum(m) > p - 1:
+                    continue
+                n = (m[0] + e[0], m[1] + e[1], m[2] + e[2])
+                out[1 + ax, t] += Lf[ks.index(n), t] * mono[c_m]
+    return out
+
+
+def _near_pairs(pos, mass, h, mask, fn):
+    pos = np.asarray(pos, dtype=np.float64)
+    mass = np.asarray(mass, dtype=np.float64)
+    pres = present_cells(mask)
+    ppc = pos.shape[1]
+    out = np.zeros((4, BLOCK ** 3, ppc))
+    for t, j in enumerate(_target_cells()):
+        ct = j[0] + FRAME * j[1] + FRAME * FRAME * j[2]
+        yi = pos[ct]                                    # [ppc, 3]
+        for d in near_stencil():
+            js = (j[0] + d[0], j[1] + d[1], j[2] + d[2])
+            if not pres[js[2], js[1], js[0]]:
+                continue
+            cs = js[0] + FRAME * js[1] + FRAME * FRAME * js[2]
+            dy = yi[:, None, :] - pos[cs][None, :, :]    # [ppc, ppc_src, 3], y_i - y_j
+            r = np.sqrt(np.sum(dy * dy, axis=-1))
+            mj = np.broadcast_to(mass[cs][None, :], r.shape).copy()
+            if d == (0, 0, 0):
+                np.fill_diagonal(mj, 0.0)               # no self-interaction
+                np.fill_diagonal(r, 1.0)
+            fn(out, t, mj, r, dy)
+    return out
+
+
+def near_field(pos, mass, h, mask=FULL_MASK):
+    """Direct sums over the near cells for the target block's particles:
+    phi_i = sum_{j != i} m_j / |y_i - y_j| and grad_i = -sum_{j != i} m_j (y_i - y_j) / |y_i - y_j|^3,
+    over the particles j of the cells cell(i) + d, d in N, in present blocks.
+    Returns [4, 512, ppc]: phi, gx, gy, gz."""
+    def acc(out, t, mj, r, dy):
+        out[0, t] += np.sum(mj / r, axis=1)
+        out[1:, t] -= np.einsum("ij,ijk->ki", mj / r ** 3, dy)
+    return _near_pairs(pos, mass, h, mask, acc)
+
+
+def near_field_abs(pos, mass, h, mask=FULL_MASK):
+    """Scales of the rounding of near_field: sum m/r for phi and sum m/r^2 for
+    every gradient component (masses are positive)."""
+    def acc(out, t, mj, r, dy):
+        out[0, t] += np.sum(mj / r, axis=1)
+        out[1:, t] += np.sum(mj / r ** 2, axis=1)[None, :]
+    return _near_pairs(pos, mass, h, mask, acc)
+
+
+def l2p_abs(L, pos, p, h):
+    """Scales of the rounding of l2p: l2p with |L| and |b|."""
+    cs = cell_centres(h).reshape(FRAME ** 3, 1, 3)
+    posa = cs + np.abs(np.asarray(pos, dtype=np.float64) - cs)
+    return np.abs(l2p(np.abs(L), posa, p, h))
+
+
+def evaluate(pos, mass, p, h, mask=FULL_MASK, L=None):
+    """Same-level potential and gradient at the target block's particles: the
+    far part from the local expansion L (computed with m2l when not given)
+    plus the near field. Returns [4, 512, ppc]."""
+    if L is None:
+        L = m2l(p2m(pos, mass, p, h, mask), p, h, mask)
+    return l2p(L, pos, p, h) + near_field(pos, mass, h, mask)
+
+
+# ---------------------------------------------------------------------------
 # harmonic (traceless) form of M2L
 # ---------------------------------------------------------------------------
 

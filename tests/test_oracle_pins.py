@@ -494,3 +494,147 @@ def test_harmonic_m2l_equals_dense(p, h, seed, masked):
     Lh = O.m2l_harmonic(M, p, h, mask)
     La = O.m2l_abs(M, p, h, mask)
     assert np.max(np.abs(Lh - Ld) / La) <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# evaluation at the particles: near field and L2P
+# ---------------------------------------------------------------------------
+
+def _exact_same_level(pos, mass, h, tcells, mask=O.FULL_MASK):
+    """Brute force: potential and gradient at the particles of the given target
+    cells from every particle of the cells with |d|^2 <= 36 (present blocks),
+    excluding the particle itself; explicit loops over particles."""
+    pres = O.present_cells(mask)
+    out = []
+    for (tx, ty, tz) in tcells:
+        j = (tx + 8, ty + 8, tz + 8)
+        ct = j[0] + 24 * j[1] + 576 * j[2]
+        phis, grads = [], []
+        for i in range(pos.shape[1]):
+            y = pos[ct, i]
+            phi, g = 0.0, np.zeros(3)
+            for dz in range(-6, 7):
+                for dy in range(-6, 7):
+                    for dx in range(-6, 7):
+                        if dx * dx + dy * dy + dz * dz > 36:
+                            continue
+                        js = (j[0] + dx, j[1] + dy, j[2] + dz)
+                        if not pres[js[2], js[1], js[0]]:
+                            continue
+                        cs = js[0] + 24 * js[1] + 576 * js[2]
+                        for k in range(pos.shape[1]):
+                            if cs == ct and k == i:
+                                continue
+                            v = y - pos[cs, k]
+                            r = np.sqrt(v @ v)
+                            phi += mass[cs, k] / r
+                            g -= mass[cs, k] * v / r ** 3
+            phis.append(phi)
+            grads.append(g)
+        out.append((np.array(phis), np.array(grads)))
+    return out
+
+
+def test_near_stencil_complements_the_shell():
+    N, S = set(O.near_stencil()), set(O.stencil())
+    assert len(N) == 33 and (0, 0, 0) in N and not (N & S)
+    assert N | S == set(O.stencil(0, 36))
+
+
+def test_near_field_against_pair_loop():
+    # independent explicit loops over particle pairs, ppc = 2, absent blocks
+    pos, mass = synth.subgrid_particles(21, ppc=2)
+    mask = O.FULL_MASK & ~(1 << 4) & ~(1 << 14)     # blocks next to the centre removed
+    nf = O.near_field(pos, mass, 1.0, mask)
+    pres = O.present_cells(mask)
+    for (tx, ty, tz) in [(0, 0, 0), (7, 3, 0), (2, 7, 7), (4, 4, 4)]:
+        t = tx + 8 * ty + 64 * tz
+        j = (tx + 8, ty + 8, tz + 8)
+        ct = j[0] + 24 * j[1] + 576 * j[2]
+        for i in range(2):
+            phi, g = 0.0, np.zeros(3)
+            for z in range(j[2] - 2, j[2] + 3):
+                for y in range(j[1] - 2, j[1] + 3):
+                    for x in range(j[0] - 2, j[0] + 3):
+                        if (x - j[0]) ** 2 + (y - j[1]) ** 2 + (z - j[2]) ** 2 > 4 or not pres[z, y, x]:
+                            continue
+                        cs = x + 24 * y + 576 * z
+                        for k in range(2):
+                            if cs == ct and k == i:
+                                continue
+                            v = pos[ct, i] - pos[cs, k]
+                            r = np.sqrt(v @ v)
+                            phi += mass[cs, k] / r
+                            g -= mass[cs, k] * v / r ** 3
+            assert abs(nf[0, t, i] - phi) <= 1e-13 * phi
+            assert np.max(np.abs(nf[1:, t, i] - g)) <= 1e-12 * np.abs(g).max()
+
+
+def test_l2p_is_the_taylor_polynomial_of_far_sources():
+    # L from exact derivatives of a far shell of sources: L2P at the particles must
+    # approach the sources' exact potential and field as p grows (|b| / R <= 0.2)
+    h = 1.0
+    pos, mass = synth.subgrid_particles(22)
+    far = O.stencil(25, 36)
+    targets = [(0, 0, 0), (5, 2, 7)]
+    errs = []
+    for p in (2, 4):
+        Lx = O.direct_sum(pos, mass, h, p, offsets=far, targets=targets)     # [2, C]
+        L = np.zeros((O.ncomp(p), 512))
+        for it, (x, y, z) in enumerate(targets):
+            L[:, x + 8 * y + 64 * z] = Lx[it]
+        ev = O.l2p(L.reshape(-1, 8, 8, 8), pos, p, h)
+        worst = 0.0
+        for (x, y, z) in targets:
+            t = x + 8 * y + 64 * z
+            ct = (x + 8) + 24 * (y + 8) + 576 * (z + 8)
+            for i in range(8):
+                yv = pos[ct, i]
+                phi, g = 0.0, np.zeros(3)
+                for d in far:
+                    cs = (x + 8 + d[0]) + 24 * (y + 8 + d[1]) + 576 * (z + 8 + d[2])
+                    v = yv[None, :] - pos[cs]
+                    r = np.sqrt(np.sum(v * v, axis=1))
+                    phi += np.sum(mass[cs] / r)
+                    g -= np.sum((mass[cs] / r ** 3)[:, None] * v, axis=0)
+                worst = max(worst, abs(ev[0, t, i] - phi) / phi,
+                            np.max(np.abs(ev[1:, t, i] - g)) / np.abs(g).max())
+        errs.append(worst)
+    assert errs[1] < 2e-3 and errs[1] < errs[0] / 5, errs
+
+
+def test_l2p_gradient_is_the_derivative_of_the_potential():
+    # central differences of phi in each coordinate of one particle (phi is a
+    # polynomial in the position for fixed L)
+    rng = np.random.default_rng(9)
+    pos, _ = synth.subgrid_particles(23)
+    L = rng.standard_normal((20, 8, 8, 8))
+    ev = O.l2p(L, pos, 3, 1.0)
+    cell = 9 + 24 * 10 + 576 * 11
+    t = 1 + 8 * 2 + 64 * 3
+    eps = 1e-5
+    for ax in range(3):
+        pp, pm = pos.copy(), pos.copy()
+        pp[cell, 0, ax] += eps
+        pm[cell, 0, ax] -= eps
+        fd = (O.l2p(L, pp, 3, 1.0)[0, t, 0] - O.l2p(L, pm, 3, 1.0)[0, t, 0]) / (2 * eps)
+        assert abs(fd - ev[1 + ax, t, 0]) <= 1e-7 * (abs(ev[1 + ax, t, 0]) + 1.0)
+
+
+def test_evaluation_converges_to_the_direct_sum():
+    # near field + L2P of the M2L local expansion against brute force over every
+    # particle with |d| <= 6: the error falls with p
+    pos, mass = synth.subgrid_particles(0)
+    tcells = [(0, 0, 0), (3, 4, 5), (7, 7, 7)]
+    ex = _exact_same_level(pos, mass, 1.0, tcells)
+    worst = {}
+    for p in (2, 4):
+        E = O.evaluate(pos, mass, p, 1.0)
+        ep, eg = 0.0, 0.0
+        for k, (x, y, z) in enumerate(tcells):
+            t = x + 8 * y + 64 * z
+            ep = max(ep, np.max(np.abs(E[0, t] - ex[k][0]) / ex[k][0]))
+            eg = max(eg, np.max(np.abs(E[1:, t].T - ex[k][1]).max(axis=1) / np.abs(ex[k][1]).max(axis=1)))
+        worst[p] = (ep, eg)
+    assert worst[4][0] < 3e-5 and worst[4][0] < worst[2][0] / 5, worst
+    assert worst[4][1] < 0.05 and worst[4][1] < worst[2][1] / 3, worst
