@@ -147,6 +147,25 @@ fmm_status fmm_p2m_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
                             const double* pos, int32_t ppc, const double* dM,
                             double* dmass, void* stream);
 
+/* Evaluation at the particles (row "near field and L2P"; the leaf cells of
+ * the paper's Sec. IV-C interact as point masses): for every particle i of
+ * the 512 target cells t of each sub-grid, with b = y_i - c_t,
+ *   phi_i  = sum_n L_n(t) b^n / n!  +  sum_{j != i} m_j / |y_i - y_j|
+ *   grad_i = sum_{|m| <= p-1} L_{m+e}(t) b^m / m!
+ *            - sum_{j != i} m_j (y_i - y_j) / |y_i - y_j|^3        (e = e_x, e_y, e_z)
+ * where j runs over the particles of the 33 near cells t + d, |d|^2 <= 4
+ * (the cells the shell S leaves out), in present blocks; grad_i is the
+ * gradient of phi at y_i. L is laid out as fmm_m2l writes it (any
+ * precision); pos/mass/ppc as for fmm_p2m (particles of absent blocks are
+ * not read). out is dense in descriptor order, float64
+ * [nsub][4][512][ppc]: phi, then the x, y and z components of grad, each
+ * [512 target cells][ppc], fully written. Two different particles of the
+ * near cells at one position make that target's result inf or NaN.
+ * nsub <= 2^21 per call. */
+fmm_status fmm_evaluate(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
+                        const double* pos, const double* mass, int32_t ppc,
+                        const double* L, double* out, void* stream);
+
 /* Copy the float64 stencil tables T_d[k][n] at unit spacing for order p to
  * device memory `out` ([892][C][C], offsets in fmm_stencil order). */
 fmm_status fmm_stencil_tables(fmm_ctx* ctx, int32_t p, double* out, void* stream);

@@ -1,0 +1,235 @@
+// Evaluation at the particles of the target block: the far part from the
+// local expansion (L2P) plus the direct sums over the near cells, the leaf
+// (point-mass) interactions that the M2L shell leaves out (paper Sec. IV-C:
+// leaf cells interact as monopoles). For a particle y_i of target cell t:
+//
+//   phi_i  = sum_n L_n(t) b^n / n!  +  sum_{j != i} m_j / |y_i - y_j|
+//   grad_i = sum_{|m| <= p-1} L_{m+e}(t) b^m / m!  -  sum_{j != i} m_j (y_i - y_j) / |y_i - y_j|^3
+//
+// with b = y_i - c_t and j over the particles of the 33 cells t + d,
+// |d|^2 <= 4, in present blocks. The near sums dominate (263 pairs per
+// particle at 8 per cell) and are bound by FP64 VALU issue.
+//
+// Work decomposition: one workgroup per (sub-grid, target z-plane): 64 target
+// cells, each thread owning R particles of one cell. The source planes
+// z-2 .. z+2 pass through LDS one at a time (only the cells the plane's
+// offsets reach: 12^2, 10^2 or 8^2), in chunks of 8 particles per cell.
+// Absent blocks and particle slots beyond ppc are staged as zero mass far
+// away, which adds exact zeros, so the inner loop has no tests. The eight
+// planes of one sub-grid run on one XCD (workgroups are dealt round-robin
+// over the 8 XCDs), so overlapping source planes are re-read from that
+// XCD's L2.
+#include "kernels.h"
+
+namespace fmm {
+
+constexpr int kEvThreads = 256;
+constexpr int kEvKC = 8;                 // source particles per cell per staged chunk
+constexpr int kEvW = 12;                 // staged plane width: frame cells [6, 18) per axis
+constexpr int kEvPlane = kEvW * kEvW;
+constexpr int kEvR = 2;                  // target particles per thread (one cell)
+constexpr double kEvFar = 1e100;         // coordinate of padding sources (zero mass)
+
+// 1/sqrt(x) to float64 accuracy: the hardware estimate y0 refined with the
+// second-order step y = y0 (1 + e/2 + 3 e^2 / 8), e = 1 - x y0^2, whose
+// error is of order e^3 (Newton-Raphson on x^{-1/2} with the next term of
+// the binomial series of (1 - e)^{-1/2}).
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  const double y0 = __builtin_amdgcn_rsq(x);
+  const double e = __builtin_fma(-(x * y0), y0, 1.0);
+  return __builtin_fma(y0 * e, __builtin_fma(0.375, e, 0.5), y0);
+}
+
+// Adds the local expansion's value and gradient at the thread's R targets
+// (b relative to the cell centre) to acc. L of the target cell through a
+// buffer resource: lane offset vo (the cell), component c at the scalar
+// offset c * 512 doubles, so no per-load address registers; each component
+// is read once for all R targets.
+template <int P>
+__device__ __forceinline__ void l2p_add(__amdgpu_buffer_rsrc_t Lr, int vo,
+                                        const double (&b)[kEvR][3], double (&acc)[kEvR][4]) {
+  constexpr int C = ncomp(P);
+  double pw[kEvR][3][P + 1];                    // b_axis^i / i!
+#pragma unroll
+  for (int r = 0; r < kEvR; ++r)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      pw[r][a][0] = 1.0;
+#pragma unroll
+      for (int i = 1; i <= P; ++i) pw[r][a][i] = pw[r][a][i - 1] * b[r][a] * (1.0 / i);
+    }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const MI k = mi_of(c);
+    const double l = __builtin_bit_cast(
+        double, __builtin_amdgcn_raw_buffer_load_b64(Lr, vo, c * kNTarget * (int)sizeof(double), 0));
+#pragma unroll
+    for (int r = 0; r < kEvR; ++r) {
+      const double(&x)[P + 1] = pw[r][0];
+      const double(&y)[P + 1] = pw[r][1];
+      const double(&z)[P + 1] = pw[r][2];
+      // d/db_x (b^k / k!) = b^(k - e_x) / (k - e_x)!
+      acc[r][0] = __builtin_fma(l, x[k.x] * y[k.y] * z[k.z], acc[r][0]);
+      if (k.x > 0) acc[r][1] = __builtin_fma(l, x[k.x - 1] * y[k.y] * z[k.z], acc[r][1]);
+      if (k.y > 0) acc[r][2] = __builtin_fma(l, x[k.x] * y[k.y - 1] * z[k.z], acc[r][2]);
+      if (k.z > 0) acc[r][3] = __builtin_fma(l, x[k.x] * y[k.y] * z[k.z - 1], acc[r][3]);
+    }
+  }
+}
+
+// One source particle against the thread's R targets.
+template <bool SELF>
+__device__ __forceinline__ void near_pair(const double (&ty)[kEvR][3], double (&acc)[kEvR][4],
+                                          const int (&tk)[kEvR], double sx, double sy, double sz,
+                                          double sm, int k) {
+#pragma unroll
+  for (int r = 0; r < kEvR; ++r) {
+    const double dx = ty[r][0] - sx, dy = ty[r][1] - sy, dz = ty[r][2] - sz;
+    double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+    double m = sm;
+    if (SELF) {                       // the particle itself: no term
+      const bool self = k == tk[r];
+      r2 = self ? 1.0 : r2;
+      m = self ? 0.0 : m;
+    }
+    const double ri = rsqrt_f64(r2);
+    const double mr = m * ri;
+    const double mr3 = mr * (ri * ri);
+    acc[r][0] += mr;
+    acc[r][1] = __builtin_fma(-mr3, dx, acc[r][1]);
+    acc[r][2] = __builtin_fma(-mr3, dy, acc[r][2]);
+    acc[r][3] = __builtin_fma(-mr3, dz, acc[r][3]);
+  }
+}
+
+__global__ void __launch_bounds__(kEvThreads) __attribute__((amdgpu_waves_per_eu(4))) evaluate_kernel(
+    const DevDesc* __restrict__ desc, int nsub, const double* __restrict__ pos,
+    const double* __restrict__ mass, int ppc, const double* __restrict__ L,
+    double* __restrict__ out) {
+  __shared__ double s_x[kEvKC * kEvPlane], s_y[kEvKC * kEvPlane], s_z[kEvKC * kEvPlane],
+      s_m[kEvKC * kEvPlane];
+  // block i -> XCD i % 8; the 8 planes of sub-grid b are blocks 8 apart
+  const int i = blockIdx.x;
+  const int b = (i / 64) * 8 + (i % 8);
+  const int tz = (i / 8) % 8;
+  if (b >= nsub) return;                       // whole workgroup: no barrier is skipped by part of it
+  const DevDesc d = desc[b];
+  const double h = ldexp(1.0, -d.log2_inv_h);
+  const int64_t p0 = d.part_off;
+  const int G = (ppc + kEvR - 1) / kEvR;       // threads per target cell
+  const int nslot = 64 * G;
+  const int nch = (ppc + kEvKC - 1) / kEvKC;
+
+  for (int slot0 = 0; slot0 < nslot; slot0 += kEvThreads) {
+    const int slot = slot0 + (int)threadIdx.x;
+    const int q = slot / G;                    // target cell within the plane (>= 64: idle)
+    const int g = slot - q * G;
+    const bool active = q < 64;
+    const int cx = q & 7, cy = (q >> 3) & 7;
+    const int tcell = (8 + cx) + kFrame * (8 + cy) + kFrame * kFrame * (8 + tz);
+    double ty[kEvR][3], acc[kEvR][4];
+    int tk[kEvR];
+#pragma unroll
+    for (int r = 0; r < kEvR; ++r) {
+      tk[r] = g + r * G;
+      // idle slots take a point outside the frame (their results are not written)
+      ty[r][0] = ty[r][1] = ty[r][2] = -1.0;
+      if (active && tk[r] < ppc) {
+        const double* y = pos + 3 * (p0 + (int64_t)tcell * ppc + tk[r]);
+        ty[r][0] = y[0];
+        ty[r][1] = y[1];
+        ty[r][2] = y[2];
+      }
+      acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
+    }
+
+    for (int dz = -2; dz <= 2; ++dz) {
+      const int rr = dz == 0 ? 2 : (dz == 1 || dz == -1 ? 1 : 0);   // in-plane reach
+      const int wr = 8 + 2 * rr;
+      const int fz = 8 + tz + dz;
+      const int nitems = wr * wr * kEvKC;
+      for (int ch = 0; ch < nch; ++ch) {
+        __syncthreads();                       // the previous chunk is consumed
+        for (int it = threadIdx.x; it < nitems; it += kEvThreads) {
+          const int kk = it % kEvKC;
+          const int c = it / kEvKC;
+          const int fx = 8 - rr + c % wr, fy = 8 - rr + c / wr;
+          const int k = ch * kEvKC + kk;
+          double x = kEvFar, y = kEvFar, z = kEvFar, m = 0.0;
+          if (k < ppc && block_present(d.mask, fx, fy, fz)) {
+            const int64_t pi = p0 + (int64_t)(fx + kFrame * fy + kFrame * kFrame * fz) * ppc + k;
+            x = pos[3 * pi];
+            y = pos[3 * pi + 1];
+            z = pos[3 * pi + 2];
+            m = mass[pi];
+          }
+          const int li = kk * kEvPlane + (fx - 6) + kEvW * (fy - 6);
+          s_x[li] = x;
+          s_y[li] = y;
+          s_z[li] = z;
+          s_m[li] = m;
+        }
+        __syncthreads();
+        for (int oy = -rr; oy <= rr; ++oy) {
+          for (int ox = -rr; ox <= rr; ++ox) {
+            if (ox * ox + oy * oy + dz * dz > 4) continue;
+            const int li0 = (cx + 2 + ox) + kEvW * (cy + 2 + oy);
+            if (dz == 0 && ox == 0 && oy == 0) {
+#pragma unroll
+              for (int kk = 0; kk < kEvKC; ++kk) {
+                const int li = kk * kEvPlane + li0;
+                near_pair<true>(ty, acc, tk, s_x[li], s_y[li], s_z[li], s_m[li], ch * kEvKC + kk);
+              }
+            } else {
+#pragma unroll
+              for (int kk = 0; kk < kEvKC; ++kk) {
+                const int li = kk * kEvPlane + li0;
+                near_pair<false>(ty, acc, tk, s_x[li], s_y[li], s_z[li], s_m[li], 0);
+              }
+            }
+          }
+        }
+      }
+    }
+
+    if (active) {
+      const int t = cx + 8 * cy + 64 * tz;
+      const __amdgpu_buffer_rsrc_t Lr = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<double*>(L + d.l_off), (short)0, ncomp(d.p) * kNTarget * (int)sizeof(double),
+          0x00020000);
+      const int vo = t * (int)sizeof(double);
+      const double ccx = (8 + cx + 0.5) * h, ccy = (8 + cy + 0.5) * h, ccz = (8 + tz + 0.5) * h;
+      double* o = out + (int64_t)b * 4 * kNTarget * ppc + (int64_t)t * ppc;
+      double bb[kEvR][3];
+#pragma unroll
+      for (int r = 0; r < kEvR; ++r) {
+        bb[r][0] = ty[r][0] - ccx;
+        bb[r][1] = ty[r][1] - ccy;
+        bb[r][2] = ty[r][2] - ccz;
+      }
+      switch (d.p) {
+        case 2: l2p_add<2>(Lr, vo, bb, acc); break;
+        case 3: l2p_add<3>(Lr, vo, bb, acc); break;
+        case 4: l2p_add<4>(Lr, vo, bb, acc); break;
+        default: break;
+      }
+#pragma unroll
+      for (int r = 0; r < kEvR; ++r) {
+        if (tk[r] >= ppc) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o[(int64_t)c * kNTarget * ppc + tk[r]] = acc[r][c];
+      }
+    }
+  }
+}
+
+hipError_t launch_evaluate(const DevDesc* d_desc, int64_t nsub, const double* pos,
+                           const double* mass, int ppc, const double* L, double* out,
+                           hipStream_t s) {
+  const int64_t groups = (nsub + 7) / 8 * 64;
+  hipLaunchKernelGGL(evaluate_kernel, dim3((unsigned)groups), dim3(kEvThreads), 0, s, d_desc,
+                     (int)nsub, pos, mass, ppc, L, out);
+  return hipGetLastError();
+}
+
+}  // namespace fmm

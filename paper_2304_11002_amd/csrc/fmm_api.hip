@@ -469,6 +469,29 @@ fmm_status fmm_p2m_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
   return mark_used(ctx, e, s);
 }
 
+fmm_status fmm_evaluate(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const double* pos,
+                        const double* mass, int32_t ppc, const double* L, double* out,
+                        void* stream) {
+  CHECK_OK(check_ctx(ctx));
+  CHECK_OK(check_desc(ctx, desc, nsub));
+  CHECK_OK(check_ppc(ctx, ppc));
+  CHECK_OK(check_ptr(ctx, pos, "pos", nsub));
+  CHECK_OK(check_ptr(ctx, mass, "mass", nsub));
+  CHECK_OK(check_ptr(ctx, L, "L", nsub));
+  CHECK_OK(check_ptr(ctx, out, "out", nsub));
+  // one workgroup of 256 threads per target z-plane: the grid's thread count fits 32 bits
+  if (nsub > (int64_t)1 << 21) return set_err(ctx, FMM_EINVAL, "nsub exceeds 2^21 for fmm_evaluate");
+  if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
+  if (nsub == 0) return FMM_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  DescEntry* e = nullptr;
+  CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
+  HIP_TRY(ctx, launch_evaluate(e->d_desc, nsub, pos, mass, ppc, L, out, s));
+  return mark_used(ctx, e, s);
+}
+
 static fmm_status run_ref(fmm_ctx* ctx, DescEntry* e, bool backward, const double* src, double* out,
                           hipStream_t s) {
   for (int p = 2; p <= kMaxP; ++p)

@@ -19,6 +19,12 @@ hipError_t launch_p2m_backward(const DevDesc* d_desc, int64_t nsub, const int* c
                                const int* counts, const double* pos, int ppc, const double* dM,
                                double* dmass, bool all_aligned, hipStream_t s);
 
+// evaluate.hip: near field + L2P at the particles of every target block;
+// out [nsub][4][512][ppc]
+hipError_t launch_evaluate(const DevDesc* d_desc, int64_t nsub, const double* pos,
+                           const double* mass, int ppc, const double* L, double* out,
+                           hipStream_t s);
+
 // m2l_ref.hip: sub-grids listed in d_ids (all of order p)
 hipError_t launch_m2l_ref(int p, bool backward, const DevDesc* d_desc, const int* d_ids, int count,
                           const int* d_stencil, const double* d_T, const double* src, double* out,

@@ -22,7 +22,7 @@ FULL_MASK = (1 << 27) - 1
 EXPORTS = [
     "fmm_create", "fmm_destroy", "fmm_status_string", "fmm_last_error", "fmm_set_option",
     "fmm_stencil", "fmm_pair_count", "fmm_p2m", "fmm_m2l", "fmm_m2l_backward",
-    "fmm_p2m_backward", "fmm_stencil_tables", "fmm_autotune",
+    "fmm_p2m_backward", "fmm_stencil_tables", "fmm_autotune", "fmm_evaluate",
 ]
 
 DESC_DTYPE = np.dtype([("p", "<i4"), ("log2_inv_h", "<i4"), ("mask", "<u4"), ("reserved", "<i4"),
@@ -63,6 +63,7 @@ def load_library(path=LIB_PATH):
         "fmm_p2m_backward": ([vp, vp, i64, vp, i32, vp, vp, vp], i32),
         "fmm_stencil_tables": ([vp, i32, vp, vp], i32),
         "fmm_autotune": ([vp, vp, i64, vp, vp, i32, vp, ctypes.POINTER(i32)], i32),
+        "fmm_evaluate": ([vp, vp, i64, vp, vp, i32, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -212,6 +213,12 @@ class Context:
         pd, n = _desc_ptr(desc)
         self._run(self.lib.fmm_p2m_backward(self.handle, pd, n, _ptr(pos), int(ppc), _ptr(dM),
                                             _ptr(dmass), self._s(stream, n)))
+
+    def evaluate(self, desc, pos, mass, ppc, L, out, stream=None):
+        """Near field + L2P: out [nsub, 4, 512, ppc] (phi, grad x, y, z)."""
+        pd, n = _desc_ptr(desc)
+        self._run(self.lib.fmm_evaluate(self.handle, pd, n, _ptr(pos), _ptr(mass), int(ppc),
+                                        _ptr(L), _ptr(out), self._s(stream, n)))
 
     def stencil_tables(self, p, out, stream=None):
         self._run(self.lib.fmm_stencil_tables(self.handle, int(p), _ptr(out), self._s(stream, 1)))

@@ -95,7 +95,11 @@ def test_pointer_and_option_validation(hctx):
                  lambda: hctx.set_option(fmm.FMM_OPT_M2L_KERNEL, 3),
                  lambda: hctx.set_option(fmm.FMM_OPT_USE_GRAPH, 2),
                  lambda: hctx.set_option(99, 0),
-                 lambda: hctx.stencil_tables(5, 8)):
+                 lambda: hctx.stencil_tables(5, 8),
+                 lambda: hctx.evaluate(desc, 8, 8, 0, 8, 8),
+                 lambda: hctx.evaluate(desc, 8, 8, 65, 8, 8),
+                 lambda: hctx.evaluate(desc, 8, 8, 8, 8, None),
+                 lambda: hctx.evaluate(desc, 8, 8, 8, 12, 8)):
         with pytest.raises(fmm.FMMError) as e:
             call()
         assert e.value.status == fmm.FMM_EINVAL
@@ -107,6 +111,9 @@ def test_host_only_context_reports_unsupported_after_checks(hctx, lib):
         hctx.m2l(desc, 8, 8)
     assert e.value.status == fmm.FMM_EUNSUPPORTED
     # empty batches are valid no-ops only after the host-only check
+    with pytest.raises(fmm.FMMError) as e:
+        hctx.evaluate(desc, 8, 8, 8, 8, 8)
+    assert e.value.status == fmm.FMM_EUNSUPPORTED
     n = ctypes.c_int64(0)
     assert lib.fmm_m2l(hctx.handle, None, 0, None, None, 0, None) == fmm.FMM_EUNSUPPORTED
     assert lib.fmm_m2l(hctx.handle, None, -1, None, None, 0, None) == fmm.FMM_EINVAL

@@ -90,6 +90,38 @@ def test_uniform_4096_fp64_and_split(ctx, torch):
     assert rel.max() < 1e-6 and np.median(rel) < 5e-8
 
 
+def test_uniform_4096_evaluate(ctx, torch):
+    # P2M -> harmonic M2L -> evaluation at all 16.8M target particles, as timed;
+    # sampled sub-grids against the oracle's own chain; the whole output is finite,
+    # deterministic, and the potential is positive everywhere (positive masses)
+    w = synth.config(2)
+    desc, m_el, l_el = fmm.make_descriptors(w.p, w.log2_inv_h, w.mask)
+    pos, mass = device_batch(torch, w)
+    M = torch.empty(m_el, dtype=torch.float64, device="cuda")
+    L = torch.empty(l_el, dtype=torch.float64, device="cuda")
+    ctx.p2m(desc, pos, mass, 8, M)
+    ctx.m2l(desc, M, L, fmm.FMM_FP64_HARMONIC)
+    del M
+    n = w.nsub * 4 * 512 * 8
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.evaluate(desc, pos, mass, 8, L, out)
+    out2 = torch.empty_like(out)
+    ctx.evaluate(desc, pos, mass, 8, L, out2)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all() and torch.equal(out, out2)
+    got = out.view(w.nsub, 4, 512, 8)
+    assert (got[:, 0] > 0).all()
+    for b in (0, 2049, 4095):
+        pos_b, mass_b = host_subgrid(w, b)
+        Mo = O.p2m(pos_b, mass_b, 3, 1.0)
+        Lo, La = O.m2l(Mo, 3, 1.0), O.m2l_abs(Mo, 3, 1.0)
+        want = O.l2p(Lo, pos_b, 3, 1.0) + O.near_field(pos_b, mass_b, 1.0)
+        scale = (O.l2p_abs(Lo, pos_b, 3, 1.0) + O.near_field_abs(pos_b, mass_b, 1.0)
+                 + O.l2p_abs(La, pos_b, 3, 1.0))
+        err = np.abs(got[b].cpu().numpy() - want)
+        assert np.all(err <= TOL * scale), (b, float(np.max(err / scale)))
+
+
 def test_uneven_6000(ctx, torch):
     w = synth.config(3)
     desc, m_el, l_el = fmm.make_descriptors(w.p, w.log2_inv_h, w.mask)
