@@ -15,7 +15,8 @@ folded moment components against 16 local columns, then expanded to all 20.
 The same run also measures, each on its own batch: the split-precision M2L
 (float32 matrix cores, hi/lo products) on the step's moments, with its error
 against the oracle; forward + backward (P2M, M2L, adjoint M2L, adjoint P2M)
-on 2048 sub-grids; the uneven batch (6000 sub-grids, p in {2,3,4} as 1:2:1,
+on 2048 sub-grids; the evaluation at the particles (near field over the 33
+cells with |d|^2 <= 4 plus L2P of the step's L); the uneven batch (6000 sub-grids, p in {2,3,4} as 1:2:1,
 h in {1,1/2,1/4}, random boundary masks) in one persistent launch; and the
 CPU oracle on a bounded sample of the step's workload on the host cores.
 """
@@ -109,6 +110,61 @@ def sampled_parity(fmm, w, desc, L_dev, sample, pos_fn):
     return {"max_rel_labs": float(rl.max()), "median_rel_labs": float(np.median(rl)),
             "max_rel_abs_L": float(rL.max()), "median_rel_abs_L": float(np.median(rL)),
             "sampled_subgrids": len(sample)}
+
+
+# FP64 operations of one near-field pair as executed: 3 differences, r^2 (1 mul,
+# 2 fma), the float estimate of 1/r refined by one second-order step (1 mul,
+# 3 fma, 1 mul), m/r, 1/r^2, m/r^3, the potential add and 3 gradient fma:
+# 19 operations, 8 of them fused multiply-adds, 27 FLOP (the float estimate and
+# its two conversions are not counted).
+NEAR_FLOPS_PER_PAIR = 27
+
+
+def l2p_flops(p):
+    """Contraction flops of L2P per particle: C fma for the potential and
+    3 C(p-1) for the gradient."""
+    C = (p + 1) * (p + 2) * (p + 3) // 6
+    Cm = p * (p + 1) * (p + 2) // 6
+    return 2 * (C + 3 * Cm)
+
+
+def near_pair_count(desc, ppc):
+    """Particle pairs of the near field over the batch: for every target
+    particle, the particles of the present cells among the 33 with |d|^2 <= 4,
+    less itself."""
+    offs = [(dx, dy, dz) for dz in range(-2, 3) for dy in range(-2, 3) for dx in range(-2, 3)
+            if dx * dx + dy * dy + dz * dz <= 4]
+    cache, total = {}, 0
+    for m in desc["mask"]:
+        m = int(m)
+        if m not in cache:
+            bits = np.array([(m >> b) & 1 for b in range(27)], bool).reshape(3, 3, 3)   # [bz][by][bx]
+            pres = np.repeat(np.repeat(np.repeat(bits, 8, 0), 8, 1), 8, 2)             # [z][y][x]
+            cells = 0
+            for dx, dy, dz in offs:
+                cells += int(pres[8 + dz:16 + dz, 8 + dy:16 + dy, 8 + dx:16 + dx].sum())
+            cache[m] = cells * ppc * ppc - 512 * ppc
+        total += cache[m]
+    return total
+
+
+def evaluate_parity(w, E_dev, sample):
+    """max |dE| / E_abs over sampled sub-grids: the oracle's own chain (P2M, M2L,
+    L2P, near field) against the device result."""
+    import oracle as O
+    worst = 0.0
+    Eh = E_dev.view(w.nsub, 4, 512, w.ppc)
+    for b in sample:
+        p, h, mask = int(w.p[b]), w.h(b), int(w.mask[b])
+        pos, mass = synth.subgrid_particles(w.seed, b, h, w.ppc)
+        M = O.p2m(pos, mass, p, h, mask)
+        Lo, La = O.m2l(M, p, h, mask), O.m2l_abs(M, p, h, mask)
+        want = O.l2p(Lo, pos, p, h) + O.near_field(pos, mass, h, mask)
+        scale = (O.l2p_abs(Lo, pos, p, h) + O.near_field_abs(pos, mass, h, mask)
+                 + O.l2p_abs(La, pos, p, h))
+        worst = max(worst, float(np.max(np.abs(Eh[b].cpu().numpy() - want) / scale)))
+    return {"max_rel_abs": worst, "sampled_subgrids": len(sample),
+            "scale": "l2p_abs(L) + near_field_abs + l2p_abs(Labs)"}
 
 
 # ---------------------------------------------------------------------------
@@ -309,7 +365,39 @@ def main():
             del Ls
         except fmm.FMMError as e:
             out["split_fp32"] = {"error": str(e)}
-        del pos, mass, M, L
+        # ---------------- evaluation at the particles (near field + L2P) from the step's L
+        del M
+        torch.cuda.empty_cache()
+        n_part = w.nsub * 512 * 8
+        npairs = near_pair_count(desc, 8)
+        E = torch.empty(n_part * 4, dtype=torch.float64, device="cuda")
+
+        def step_ev(ev, i):
+            if ev: ev[0].record()
+            ctx.evaluate(desc, pos, mass, 8, L, E)
+            if ev: ev[1].record()
+
+        _, seg_e = timed(torch, step_ev, K, W, marks=1)
+        ms_e = seg_e[:, 0].mean()
+        par_e = evaluate_parity(w, E, [0, 4095])
+        assert par_e["max_rel_abs"] <= 1e-12, par_e
+        fl_e = npairs * NEAR_FLOPS_PER_PAIR + n_part * l2p_flops(3)
+        ach_e = fl_e / (ms_e * 1e-3) / 1e12
+        out["evaluate"] = {
+            "what": "potential and gradient at all 16.8M particles of the step: near field "
+                    "(33 cells, |d|^2 <= 4, direct sums) + L2P of the step's L",
+            "ms": float(ms_e), "particles_per_s": n_part / (ms_e * 1e-3),
+            "near_pairs": npairs, "near_pairs_per_s": npairs / (ms_e * 1e-3),
+            "same_level_solve_ms": float(ms_step + ms_e),
+            "roofline": {"bound": "alu", "kernel": "evaluate_kernel (FP64 VALU)",
+                         "achieved": ach_e, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": ach_e / FP64_PEAK_TFLOPS, "traffic": None,
+                         "flops_per_near_pair": NEAR_FLOPS_PER_PAIR,
+                         "l2p_flops_per_particle": l2p_flops(3)},
+            "parity": par_e}
+        log("evaluate %.3f ms: %.4g particles/s, %.4g near pairs/s, %.1f TFLOP/s executed"
+            % (ms_e, n_part / (ms_e * 1e-3), npairs / (ms_e * 1e-3), ach_e))
+        del pos, mass, L, E
         torch.cuda.empty_cache()
 
         # ---------------- forward + backward on 2048 sub-grids

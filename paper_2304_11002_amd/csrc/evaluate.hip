@@ -26,16 +26,19 @@ namespace fmm {
 constexpr int kEvThreads = 256;
 constexpr int kEvKC = 8;                 // source particles per cell per staged chunk
 constexpr int kEvW = 12;                 // staged plane width: frame cells [6, 18) per axis
-constexpr int kEvPlane = kEvW * kEvW;
 constexpr int kEvR = 2;                  // target particles per thread (one cell)
 constexpr double kEvFar = 1e100;         // coordinate of padding sources (zero mass)
 
-// 1/sqrt(x) to float64 accuracy: the hardware estimate y0 refined with the
-// second-order step y = y0 (1 + e/2 + 3 e^2 / 8), e = 1 - x y0^2, whose
-// error is of order e^3 (Newton-Raphson on x^{-1/2} with the next term of
-// the binomial series of (1 - e)^{-1/2}).
+// 1/sqrt(x) to float64 accuracy: the single-precision hardware estimate
+// y0 (relative error below 2^-22 including the rounding of x to float)
+// refined with the second-order step y = y0 (1 + e/2 + 3 e^2 / 8),
+// e = 1 - x y0^2, whose error is of order e^3 (the binomial series of
+// (1 - e)^{-1/2}). The float estimate costs half the issue slots of the
+// double one. x beyond the float range (the far padding sources, x ~ 1e200)
+// gives y0 = 0 and so y = 0; x below it (two particles closer than 1e-19)
+// is not refined correctly.
 __device__ __forceinline__ double rsqrt_f64(double x) {
-  const double y0 = __builtin_amdgcn_rsq(x);
+  const double y0 = (double)__builtin_amdgcn_rsqf((float)x);
   const double e = __builtin_fma(-(x * y0), y0, 1.0);
   return __builtin_fma(y0 * e, __builtin_fma(0.375, e, 0.5), y0);
 }
@@ -102,12 +105,49 @@ __device__ __forceinline__ void near_pair(const double (&ty)[kEvR][3], double (&
   }
 }
 
+// Staged source plane in LDS: per particle slot kk (0..7) and cell (fx, fy)
+// of the frame window [6, 18)^2 the four doubles x, y, z, m, at double index
+// kk * kEvSlot + (fy - 6) * kEvRow + (fx - 6) * 4. Rows are padded by two
+// doubles so that the two rows of cells one wave reads fall on disjoint LDS
+// banks, and every read of a slot is a 16-byte (x, y) and (z, m) pair at a
+// fixed immediate offset from one base address.
+constexpr int kEvRow = kEvW * 4 + 2;           // 50 doubles
+constexpr int kEvSlot = kEvW * kEvRow;         // 600 doubles
+constexpr int kEvLds = kEvKC * kEvSlot;        // 4800 doubles = 38400 bytes
+
+// Stages particle slots ch*8 .. ch*8+7 of the cells of frame plane fz that
+// the offsets of reach RR (|dx|, |dy| <= RR) touch: (8 + 2 RR)^2 cells.
+template <int RR>
+__device__ __forceinline__ void stage_plane(double* __restrict__ s, const DevDesc& d,
+                                            const double* __restrict__ pos,
+                                            const double* __restrict__ mass, int ppc, int fz,
+                                            int ch) {
+  constexpr int WR = 8 + 2 * RR;
+  constexpr int NITEMS = WR * WR * kEvKC;
+  for (int it = threadIdx.x; it < NITEMS; it += kEvThreads) {
+    const int kk = it % kEvKC;
+    const int c = it / kEvKC;
+    const int fx = 8 - RR + c % WR, fy = 8 - RR + c / WR;
+    const int k = ch * kEvKC + kk;
+    double2 xy = make_double2(kEvFar, kEvFar), zm = make_double2(kEvFar, 0.0);
+    if (k < ppc && block_present(d.mask, fx, fy, fz)) {
+      const int64_t pi = d.part_off + (int64_t)(fx + kFrame * fy + kFrame * kFrame * fz) * ppc + k;
+      xy.x = pos[3 * pi];
+      xy.y = pos[3 * pi + 1];
+      zm.x = pos[3 * pi + 2];
+      zm.y = mass[pi];
+    }
+    double* o = s + kk * kEvSlot + (fy - 6) * kEvRow + (fx - 6) * 4;
+    *reinterpret_cast<double2*>(o) = xy;
+    *reinterpret_cast<double2*>(o + 2) = zm;
+  }
+}
+
 __global__ void __launch_bounds__(kEvThreads) __attribute__((amdgpu_waves_per_eu(4))) evaluate_kernel(
     const DevDesc* __restrict__ desc, int nsub, const double* __restrict__ pos,
     const double* __restrict__ mass, int ppc, const double* __restrict__ L,
     double* __restrict__ out) {
-  __shared__ double s_x[kEvKC * kEvPlane], s_y[kEvKC * kEvPlane], s_z[kEvKC * kEvPlane],
-      s_m[kEvKC * kEvPlane];
+  __shared__ __attribute__((aligned(16))) double s_src[kEvLds];
   // block i -> XCD i % 8; the 8 planes of sub-grid b are blocks 8 apart
   const int i = blockIdx.x;
   const int b = (i / 64) * 8 + (i % 8);
@@ -142,49 +182,35 @@ __global__ void __launch_bounds__(kEvThreads) __attribute__((amdgpu_waves_per_eu
       }
       acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
     }
+    // this thread's cell in the staged window, offsets added per source cell
+    const double* sbase = s_src + (cy + 2) * kEvRow + (cx + 2) * 4;
 
     for (int dz = -2; dz <= 2; ++dz) {
       const int rr = dz == 0 ? 2 : (dz == 1 || dz == -1 ? 1 : 0);   // in-plane reach
-      const int wr = 8 + 2 * rr;
       const int fz = 8 + tz + dz;
-      const int nitems = wr * wr * kEvKC;
       for (int ch = 0; ch < nch; ++ch) {
         __syncthreads();                       // the previous chunk is consumed
-        for (int it = threadIdx.x; it < nitems; it += kEvThreads) {
-          const int kk = it % kEvKC;
-          const int c = it / kEvKC;
-          const int fx = 8 - rr + c % wr, fy = 8 - rr + c / wr;
-          const int k = ch * kEvKC + kk;
-          double x = kEvFar, y = kEvFar, z = kEvFar, m = 0.0;
-          if (k < ppc && block_present(d.mask, fx, fy, fz)) {
-            const int64_t pi = p0 + (int64_t)(fx + kFrame * fy + kFrame * kFrame * fz) * ppc + k;
-            x = pos[3 * pi];
-            y = pos[3 * pi + 1];
-            z = pos[3 * pi + 2];
-            m = mass[pi];
-          }
-          const int li = kk * kEvPlane + (fx - 6) + kEvW * (fy - 6);
-          s_x[li] = x;
-          s_y[li] = y;
-          s_z[li] = z;
-          s_m[li] = m;
-        }
+        if (rr == 2) stage_plane<2>(s_src, d, pos, mass, ppc, fz, ch);
+        else if (rr == 1) stage_plane<1>(s_src, d, pos, mass, ppc, fz, ch);
+        else stage_plane<0>(s_src, d, pos, mass, ppc, fz, ch);
         __syncthreads();
         for (int oy = -rr; oy <= rr; ++oy) {
           for (int ox = -rr; ox <= rr; ++ox) {
             if (ox * ox + oy * oy + dz * dz > 4) continue;
-            const int li0 = (cx + 2 + ox) + kEvW * (cy + 2 + oy);
+            const double* sc = sbase + oy * kEvRow + ox * 4;
             if (dz == 0 && ox == 0 && oy == 0) {
 #pragma unroll
               for (int kk = 0; kk < kEvKC; ++kk) {
-                const int li = kk * kEvPlane + li0;
-                near_pair<true>(ty, acc, tk, s_x[li], s_y[li], s_z[li], s_m[li], ch * kEvKC + kk);
+                const double2 xy = *reinterpret_cast<const double2*>(sc + kk * kEvSlot);
+                const double2 zm = *reinterpret_cast<const double2*>(sc + kk * kEvSlot + 2);
+                near_pair<true>(ty, acc, tk, xy.x, xy.y, zm.x, zm.y, ch * kEvKC + kk);
               }
             } else {
 #pragma unroll
               for (int kk = 0; kk < kEvKC; ++kk) {
-                const int li = kk * kEvPlane + li0;
-                near_pair<false>(ty, acc, tk, s_x[li], s_y[li], s_z[li], s_m[li], 0);
+                const double2 xy = *reinterpret_cast<const double2*>(sc + kk * kEvSlot);
+                const double2 zm = *reinterpret_cast<const double2*>(sc + kk * kEvSlot + 2);
+                near_pair<false>(ty, acc, tk, xy.x, xy.y, zm.x, zm.y, 0);
               }
             }
           }
