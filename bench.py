@@ -237,6 +237,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="oracle seconds per host core for cpu_baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the step (for profiling)")
+    ap.add_argument("--evaluate-only", action="store_true",
+                    help="only the step and the evaluation at the particles (for profiling)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of this many GiB three times (counter calibration)")
     args = ap.parse_args()
@@ -322,28 +324,29 @@ def main():
     assert par["max_rel_labs"] <= 1e-12, par
     log("FP64 parity on sampled sub-grids: max |dL|/Labs %.3g" % par["max_rel_labs"])
 
-    # ---------------- the dense form of the same M2L, on the same moments
-    Ld = torch.empty_like(L)
-    tuned_d = ctx.autotune(desc, M, Ld, fmm.FMM_FP64)
+    if not args.evaluate_only:
+        # ---------------- the dense form of the same M2L, on the same moments
+        Ld = torch.empty_like(L)
+        tuned_d = ctx.autotune(desc, M, Ld, fmm.FMM_FP64)
 
-    def step_dense(ev, i):
-        if ev: ev[0].record()
-        ctx.m2l(desc, M, Ld, fmm.FMM_FP64)
-        if ev: ev[1].record()
+        def step_dense(ev, i):
+            if ev: ev[0].record()
+            ctx.m2l(desc, M, Ld, fmm.FMM_FP64)
+            if ev: ev[1].record()
 
-    _, seg_d = timed(torch, step_dense, K, W, marks=1)
-    ms_d = seg_d[:, 0].mean()
-    par_d = sampled_parity(fmm, w, desc, Ld, [0, 4095], lambda b: synth.subgrid_particles(w.seed, b))
-    assert par_d["max_rel_labs"] <= 1e-12, par_d
-    out["dense_fp64"] = {"m2l_ms": float(ms_d), "pairs_per_s": pairs / (ms_d * 1e-3),
-                         "tflops": fl_dense / (ms_d * 1e-3) / 1e12,
-                         "frac_of_fp64_peak": fl_dense / (ms_d * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-                         "autotune_choice": tuned_d, "parity": par_d,
-                         "harmonic_speedup": float(ms_d / m2l_ms)}
-    log("dense FP64 M2L %.3f ms (%.2f TFLOP/s), harmonic x%.2f" % (ms_d, fl_dense / (ms_d * 1e-3) / 1e12, ms_d / m2l_ms))
-    del Ld
+        _, seg_d = timed(torch, step_dense, K, W, marks=1)
+        ms_d = seg_d[:, 0].mean()
+        par_d = sampled_parity(fmm, w, desc, Ld, [0, 4095], lambda b: synth.subgrid_particles(w.seed, b))
+        assert par_d["max_rel_labs"] <= 1e-12, par_d
+        out["dense_fp64"] = {"m2l_ms": float(ms_d), "pairs_per_s": pairs / (ms_d * 1e-3),
+                             "tflops": fl_dense / (ms_d * 1e-3) / 1e12,
+                             "frac_of_fp64_peak": fl_dense / (ms_d * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                             "autotune_choice": tuned_d, "parity": par_d,
+                             "harmonic_speedup": float(ms_d / m2l_ms)}
+        log("dense FP64 M2L %.3f ms (%.2f TFLOP/s), harmonic x%.2f" % (ms_d, fl_dense / (ms_d * 1e-3) / 1e12, ms_d / m2l_ms))
+        del Ld
 
-    if not args.no_extras:
+    if not args.no_extras and not args.evaluate_only:
         # ---------------- split precision on the same moments
         try:
             Ls = torch.empty_like(L)
@@ -365,6 +368,7 @@ def main():
             del Ls
         except fmm.FMMError as e:
             out["split_fp32"] = {"error": str(e)}
+    if not args.no_extras:
         # ---------------- evaluation at the particles (near field + L2P) from the step's L
         del M
         torch.cuda.empty_cache()
@@ -400,6 +404,7 @@ def main():
         del pos, mass, L, E
         torch.cuda.empty_cache()
 
+    if not args.no_extras and not args.evaluate_only:
         # ---------------- forward + backward on 2048 sub-grids
         w5 = synth.config(5)
         d5, m5, l5 = fmm.make_descriptors(w5.p, w5.log2_inv_h, w5.mask)
