@@ -15,6 +15,10 @@ multiple HPX tasks per Kokkos kernel invocation"). The paper gives no
 formulas; the definitions written out here are textbook Cartesian FMM, and
 each function states the reading it takes where the paper is silent.
 
+``oracle.tree`` extends the same definitions to the whole three-step iteration
+on a uniform octree (P2M, M2M, interaction-list M2L on every level, L2L, and
+the near field plus L2P at the finest level).
+
 Every floating-point step is plain NumPy float64 (float32 only in the
 split-precision emulation, which is an expectation model, not a reference).
 """

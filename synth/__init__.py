@@ -49,6 +49,19 @@ def subgrid_particles(seed, b=None, h=1.0, ppc=8):
     return pos.reshape(NCELL, ppc, 3), mass.reshape(NCELL, ppc)
 
 
+def grid_particles(seed, n, h=1.0, ppc=8):
+    """Positions [n^3, ppc, 3] and masses [n^3, ppc] of a uniform n^3-cell domain
+    (cell index x + n y + n^2 z), drawn like subgrid_particles: u uniform in the
+    cell, lognormal(0, 1) masses, rng = default_rng([seed, 2**30 + n])."""
+    rng = np.random.default_rng([seed, 2 ** 30 + n])
+    u = rng.random((n, n, n, ppc, 3))
+    mass = rng.lognormal(0.0, 1.0, (n, n, n, ppc))
+    g = np.arange(n, dtype=np.float64)
+    j = np.stack(np.meshgrid(g, g, g, indexing="ij")[::-1], axis=-1)
+    pos = (j[:, :, :, None, :] + u) * h
+    return pos.reshape(n ** 3, ppc, 3), mass.reshape(n ** 3, ppc)
+
+
 @dataclass
 class Workload:
     """A batch description: per-sub-grid order, spacing exponent and mask."""
