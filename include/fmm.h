@@ -166,6 +166,59 @@ fmm_status fmm_evaluate(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
                         const double* pos, const double* mass, int32_t ppc,
                         const double* L, double* out, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Multi-level iteration on a uniform octree (row "multi-level"; the paper's
+ * three-step gravity iteration, Sec. VII-C: bottom-up traversal, the
+ * cell-to-cell interactions on every level, top-down traversal; Sec. IV-C:
+ * octree cells carry multipole moments, leaves act as point masses).
+ *
+ *   domain   n^3 finest cells of spacing h = 2^log2_h, cell j spans
+ *            [j h, (j+1) h) per axis; particles pos [n^3][ppc][3] and mass
+ *            [n^3][ppc], cell index x + n y + n^2 z (every particle inside its
+ *            cell).
+ *   levels   l = 0 (finest, n per axis) ... J (4 per axis); level l has n/2^l
+ *            cells per axis of spacing 2^l h; parent of cell j is j/2.
+ *   M, L     workspaces holding every level, finest first, each level
+ *            [C][n_l][n_l][n_l] (x fastest): fmm_tree_size gives the total.
+ *   P2M      level 0: M_k(j) = sum_i m_i (y_i - c_j)^k / k!.
+ *   M2M      M_k(J) = sum_{children j} sum_{q <= k} M_q(j) s^(k-q)/(k-q)!,
+ *            s = c_j - c_J.
+ *   M2L      every level: L_n(t) = sum_{d in IL(t)} sum_k M_k(t+d) T_d[k][n]
+ *            at the level's spacing, IL(t) = {d : |d|^2 > 4 and
+ *            |floor((t mod 2 + d)/2)|^2 <= 4} (not near, parents near;
+ *            231 offsets per parity of t); sources outside the domain absent.
+ *   L2L      L_n(j) += sum_{m >= n} L_m(J) s^(m-n)/(m-n)!, coarsest first.
+ *   evaluate the finest level's L2P plus the near field over |d|^2 <= 4, as
+ *            fmm_evaluate; out [4][n^3][ppc] (phi, grad x, y, z).
+ * Every pair of particles is then accounted for once (directly when their
+ * cells are near, else on the one level where the cells' ancestors are not
+ * near but the ancestors' parents are).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t p;        /* expansion order, 2, 3 or 4 */
+    int32_t n;        /* finest cells per axis: 8, 16, 32, 64 or 128 */
+    int32_t ppc;      /* particles per finest cell, 1..64 */
+    int32_t log2_h;   /* finest spacing h = 2^log2_h, -4 <= log2_h <= 4 */
+} fmm_tree;
+
+/* Host query: number of levels (J + 1) and the float64 elements of one M or
+ * L workspace (C * sum_l n_l^3). Either output may be NULL. */
+fmm_status fmm_tree_size(const fmm_tree* tree, int32_t* levels, int64_t* elems);
+/* P2M on level 0, then M2M up to the coarsest level: writes all of M. */
+fmm_status fmm_tree_upward(fmm_ctx* ctx, const fmm_tree* tree, const double* pos,
+                           const double* mass, double* M, void* stream);
+/* The interaction-list M2L of every level: overwrites all of L. */
+fmm_status fmm_tree_m2l(fmm_ctx* ctx, const fmm_tree* tree, const double* M, double* L,
+                        void* stream);
+/* L2L from the coarsest level down, in place: L_l += L2L(L_{l+1}). */
+fmm_status fmm_tree_downward(fmm_ctx* ctx, const fmm_tree* tree, double* L, void* stream);
+/* L2P of level 0 of L plus the near field; out [4][n^3][ppc], fully written. */
+fmm_status fmm_tree_evaluate(fmm_ctx* ctx, const fmm_tree* tree, const double* pos,
+                             const double* mass, const double* L, double* out, void* stream);
+/* The whole iteration: upward, m2l, downward, evaluate (M and L are workspaces). */
+fmm_status fmm_tree_solve(fmm_ctx* ctx, const fmm_tree* tree, const double* pos,
+                          const double* mass, double* M, double* L, double* out, void* stream);
+
 /* Copy the float64 stencil tables T_d[k][n] at unit spacing for order p to
  * device memory `out` ([892][C][C], offsets in fmm_stencil order). */
 fmm_status fmm_stencil_tables(fmm_ctx* ctx, int32_t p, double* out, void* stream);

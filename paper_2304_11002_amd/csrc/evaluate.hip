@@ -46,10 +46,10 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
 // Adds the local expansion's value and gradient at the thread's R targets
 // (b relative to the cell centre) to acc. L of the target cell through a
 // buffer resource: lane offset vo (the cell), component c at the scalar
-// offset c * 512 doubles, so no per-load address registers; each component
+// offset c * cstride bytes, so no per-load address registers; each component
 // is read once for all R targets.
 template <int P>
-__device__ __forceinline__ void l2p_add(__amdgpu_buffer_rsrc_t Lr, int vo,
+__device__ __forceinline__ void l2p_add(__amdgpu_buffer_rsrc_t Lr, int vo, int cstride,
                                         const double (&b)[kEvR][3], double (&acc)[kEvR][4]) {
   constexpr int C = ncomp(P);
   double pw[kEvR][3][P + 1];                    // b_axis^i / i!
@@ -65,7 +65,7 @@ __device__ __forceinline__ void l2p_add(__amdgpu_buffer_rsrc_t Lr, int vo,
   for (int c = 0; c < C; ++c) {
     const MI k = mi_of(c);
     const double l = __builtin_bit_cast(
-        double, __builtin_amdgcn_raw_buffer_load_b64(Lr, vo, c * kNTarget * (int)sizeof(double), 0));
+        double, __builtin_amdgcn_raw_buffer_load_b64(Lr, vo, c * cstride, 0));
 #pragma unroll
     for (int r = 0; r < kEvR; ++r) {
       const double(&x)[P + 1] = pw[r][0];
@@ -115,10 +115,41 @@ constexpr int kEvRow = kEvW * 4 + 2;           // 50 doubles
 constexpr int kEvSlot = kEvW * kEvRow;         // 600 doubles
 constexpr int kEvLds = kEvKC * kEvSlot;        // 4800 doubles = 38400 bytes
 
+// Where the cells of one workgroup's neighbourhood live. Cells are named by
+// frame coordinates f in [6, 18)^3 around the 8^3 target block [8, 16)^3.
+//   FrameGeom: one sub-grid's 24^3 frame (descriptor: particle offset, mask,
+//              L block of 512 targets, output [4][512][ppc] per sub-grid).
+//   GridGeom:  an 8^3 block of a uniform n^3 domain (cell index x + n y + n^2 z,
+//              L [C][n^3], output [4][n^3][ppc]); cells outside the domain are absent.
+struct FrameGeom {
+  DevDesc d;
+  __device__ bool present(int fx, int fy, int fz) const { return block_present(d.mask, fx, fy, fz); }
+  __device__ int64_t cell(int fx, int fy, int fz) const { return fx + kFrame * fy + kFrame * kFrame * fz; }
+  __device__ int64_t part0() const { return d.part_off; }
+  __device__ double coord(int f, int) const { return f; }
+  __device__ int64_t lcell(int fx, int fy, int fz) const { return (fx - 8) + 8 * (fy - 8) + 64 * (fz - 8); }
+  __device__ int64_t ncells_out() const { return kNTarget; }
+};
+
+struct GridGeom {
+  int n, ox, oy, oz;     // frame coordinate f is global f + o (o = block origin - 8)
+  __device__ bool present(int fx, int fy, int fz) const {
+    const unsigned gx = fx + ox, gy = fy + oy, gz = fz + oz;
+    return gx < (unsigned)n && gy < (unsigned)n && gz < (unsigned)n;
+  }
+  __device__ int64_t cell(int fx, int fy, int fz) const {
+    return (fx + ox) + (int64_t)n * (fy + oy) + (int64_t)n * n * (fz + oz);
+  }
+  __device__ int64_t part0() const { return 0; }
+  __device__ double coord(int f, int axis) const { return f + (axis == 0 ? ox : axis == 1 ? oy : oz); }
+  __device__ int64_t lcell(int fx, int fy, int fz) const { return cell(fx, fy, fz); }
+  __device__ int64_t ncells_out() const { return (int64_t)n * n * n; }
+};
+
 // Stages particle slots ch*8 .. ch*8+7 of the cells of frame plane fz that
 // the offsets of reach RR (|dx|, |dy| <= RR) touch: (8 + 2 RR)^2 cells.
-template <int RR>
-__device__ __forceinline__ void stage_plane(double* __restrict__ s, const DevDesc& d,
+template <int RR, class Geom>
+__device__ __forceinline__ void stage_plane(double* __restrict__ s, const Geom& geo,
                                             const double* __restrict__ pos,
                                             const double* __restrict__ mass, int ppc, int fz,
                                             int ch) {
@@ -130,8 +161,8 @@ __device__ __forceinline__ void stage_plane(double* __restrict__ s, const DevDes
     const int fx = 8 - RR + c % WR, fy = 8 - RR + c / WR;
     const int k = ch * kEvKC + kk;
     double2 xy = make_double2(kEvFar, kEvFar), zm = make_double2(kEvFar, 0.0);
-    if (k < ppc && block_present(d.mask, fx, fy, fz)) {
-      const int64_t pi = d.part_off + (int64_t)(fx + kFrame * fy + kFrame * kFrame * fz) * ppc + k;
+    if (k < ppc && geo.present(fx, fy, fz)) {
+      const int64_t pi = geo.part0() + geo.cell(fx, fy, fz) * ppc + k;
       xy.x = pos[3 * pi];
       xy.y = pos[3 * pi + 1];
       zm.x = pos[3 * pi + 2];
@@ -143,22 +174,18 @@ __device__ __forceinline__ void stage_plane(double* __restrict__ s, const DevDes
   }
 }
 
-__global__ void __launch_bounds__(kEvThreads) __attribute__((amdgpu_waves_per_eu(4))) evaluate_kernel(
-    const DevDesc* __restrict__ desc, int nsub, const double* __restrict__ pos,
-    const double* __restrict__ mass, int ppc, const double* __restrict__ L,
-    double* __restrict__ out) {
-  __shared__ __attribute__((aligned(16))) double s_src[kEvLds];
-  // block i -> XCD i % 8; the 8 planes of sub-grid b are blocks 8 apart
-  const int i = blockIdx.x;
-  const int b = (i / 64) * 8 + (i % 8);
-  const int tz = (i / 8) % 8;
-  if (b >= nsub) return;                       // whole workgroup: no barrier is skipped by part of it
-  const DevDesc d = desc[b];
-  const double h = ldexp(1.0, -d.log2_inv_h);
-  const int64_t p0 = d.part_off;
+// One target z-plane tz of one block: near sums over the staged source planes,
+// then L2P, written for the block's 64 x ppc particles.
+template <class Geom>
+__device__ __forceinline__ void evaluate_plane(double* __restrict__ s_src, const Geom& geo, int p,
+                                               double h, int tz, const double* __restrict__ pos,
+                                               const double* __restrict__ mass, int ppc,
+                                               const double* __restrict__ L, double* __restrict__ out) {
+  const int64_t p0 = geo.part0();
   const int G = (ppc + kEvR - 1) / kEvR;       // threads per target cell
   const int nslot = 64 * G;
   const int nch = (ppc + kEvKC - 1) / kEvKC;
+  const int64_t ncell = geo.ncells_out();
 
   for (int slot0 = 0; slot0 < nslot; slot0 += kEvThreads) {
     const int slot = slot0 + (int)threadIdx.x;
@@ -166,16 +193,16 @@ __global__ void __launch_bounds__(kEvThreads) __attribute__((amdgpu_waves_per_eu
     const int g = slot - q * G;
     const bool active = q < 64;
     const int cx = q & 7, cy = (q >> 3) & 7;
-    const int tcell = (8 + cx) + kFrame * (8 + cy) + kFrame * kFrame * (8 + tz);
+    const int64_t tcell = geo.cell(8 + cx, 8 + cy, 8 + tz);
     double ty[kEvR][3], acc[kEvR][4];
     int tk[kEvR];
 #pragma unroll
     for (int r = 0; r < kEvR; ++r) {
       tk[r] = g + r * G;
-      // idle slots take a point outside the frame (their results are not written)
-      ty[r][0] = ty[r][1] = ty[r][2] = -1.0;
+      // idle slots take a point outside the domain (their results are not written)
+      ty[r][0] = ty[r][1] = ty[r][2] = -1e30;
       if (active && tk[r] < ppc) {
-        const double* y = pos + 3 * (p0 + (int64_t)tcell * ppc + tk[r]);
+        const double* y = pos + 3 * (p0 + tcell * ppc + tk[r]);
         ty[r][0] = y[0];
         ty[r][1] = y[1];
         ty[r][2] = y[2];
@@ -190,9 +217,9 @@ __global__ void __launch_bounds__(kEvThreads) __attribute__((amdgpu_waves_per_eu
       const int fz = 8 + tz + dz;
       for (int ch = 0; ch < nch; ++ch) {
         __syncthreads();                       // the previous chunk is consumed
-        if (rr == 2) stage_plane<2>(s_src, d, pos, mass, ppc, fz, ch);
-        else if (rr == 1) stage_plane<1>(s_src, d, pos, mass, ppc, fz, ch);
-        else stage_plane<0>(s_src, d, pos, mass, ppc, fz, ch);
+        if (rr == 2) stage_plane<2>(s_src, geo, pos, mass, ppc, fz, ch);
+        else if (rr == 1) stage_plane<1>(s_src, geo, pos, mass, ppc, fz, ch);
+        else stage_plane<0>(s_src, geo, pos, mass, ppc, fz, ch);
         __syncthreads();
         for (int oy = -rr; oy <= rr; ++oy) {
           for (int ox = -rr; ox <= rr; ++ox) {
@@ -219,13 +246,14 @@ __global__ void __launch_bounds__(kEvThreads) __attribute__((amdgpu_waves_per_eu
     }
 
     if (active) {
-      const int t = cx + 8 * cy + 64 * tz;
+      const int64_t t = geo.lcell(8 + cx, 8 + cy, 8 + tz);
+      const int cstride = (int)(ncell * (int64_t)sizeof(double));
       const __amdgpu_buffer_rsrc_t Lr = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<double*>(L + d.l_off), (short)0, ncomp(d.p) * kNTarget * (int)sizeof(double),
-          0x00020000);
-      const int vo = t * (int)sizeof(double);
-      const double ccx = (8 + cx + 0.5) * h, ccy = (8 + cy + 0.5) * h, ccz = (8 + tz + 0.5) * h;
-      double* o = out + (int64_t)b * 4 * kNTarget * ppc + (int64_t)t * ppc;
+          const_cast<double*>(L), (short)0, ncomp(p) * cstride, 0x00020000);
+      const int vo = (int)(t * (int64_t)sizeof(double));
+      const double ccx = (geo.coord(8 + cx, 0) + 0.5) * h, ccy = (geo.coord(8 + cy, 1) + 0.5) * h,
+                   ccz = (geo.coord(8 + tz, 2) + 0.5) * h;
+      double* o = out + t * ppc;
       double bb[kEvR][3];
 #pragma unroll
       for (int r = 0; r < kEvR; ++r) {
@@ -233,20 +261,56 @@ __global__ void __launch_bounds__(kEvThreads) __attribute__((amdgpu_waves_per_eu
         bb[r][1] = ty[r][1] - ccy;
         bb[r][2] = ty[r][2] - ccz;
       }
-      switch (d.p) {
-        case 2: l2p_add<2>(Lr, vo, bb, acc); break;
-        case 3: l2p_add<3>(Lr, vo, bb, acc); break;
-        case 4: l2p_add<4>(Lr, vo, bb, acc); break;
+      switch (p) {
+        case 2: l2p_add<2>(Lr, vo, cstride, bb, acc); break;
+        case 3: l2p_add<3>(Lr, vo, cstride, bb, acc); break;
+        case 4: l2p_add<4>(Lr, vo, cstride, bb, acc); break;
         default: break;
       }
 #pragma unroll
       for (int r = 0; r < kEvR; ++r) {
         if (tk[r] >= ppc) continue;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) o[(int64_t)c * kNTarget * ppc + tk[r]] = acc[r][c];
+        for (int c = 0; c < 4; ++c) o[(int64_t)c * ncell * ppc + tk[r]] = acc[r][c];
       }
     }
   }
+}
+
+__global__ void __launch_bounds__(kEvThreads) __attribute__((amdgpu_waves_per_eu(4))) evaluate_kernel(
+    const DevDesc* __restrict__ desc, int nsub, const double* __restrict__ pos,
+    const double* __restrict__ mass, int ppc, const double* __restrict__ L,
+    double* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) double s_src[kEvLds];
+  // block i -> XCD i % 8; the 8 planes of sub-grid b are blocks 8 apart
+  const int i = blockIdx.x;
+  const int b = (i / 64) * 8 + (i % 8);
+  const int tz = (i / 8) % 8;
+  if (b >= nsub) return;                       // whole workgroup: no barrier is skipped by part of it
+  FrameGeom geo;
+  geo.d = desc[b];
+  evaluate_plane(s_src, geo, geo.d.p, ldexp(1.0, -geo.d.log2_inv_h), tz, pos, mass, ppc,
+                 L + geo.d.l_off, out + (int64_t)b * 4 * kNTarget * ppc);
+}
+
+// The finest level of a uniform n^3 domain: (n/8)^3 blocks x 8 planes, the
+// planes of one block dealt to one XCD as above.
+__global__ void __launch_bounds__(kEvThreads) __attribute__((amdgpu_waves_per_eu(4))) evaluate_grid_kernel(
+    int p, int n, double h, const double* __restrict__ pos, const double* __restrict__ mass, int ppc,
+    const double* __restrict__ L, double* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) double s_src[kEvLds];
+  const int nb = n / 8;
+  const int nblk = nb * nb * nb;
+  const int i = blockIdx.x;
+  const int b = (i / 64) * 8 + (i % 8);
+  const int tz = (i / 8) % 8;
+  if (b >= nblk) return;
+  GridGeom geo;
+  geo.n = n;
+  geo.ox = 8 * (b % nb) - 8;
+  geo.oy = 8 * ((b / nb) % nb) - 8;
+  geo.oz = 8 * (b / (nb * nb)) - 8;
+  evaluate_plane(s_src, geo, p, h, tz, pos, mass, ppc, L, out);
 }
 
 hipError_t launch_evaluate(const DevDesc* d_desc, int64_t nsub, const double* pos,
@@ -255,6 +319,15 @@ hipError_t launch_evaluate(const DevDesc* d_desc, int64_t nsub, const double* po
   const int64_t groups = (nsub + 7) / 8 * 64;
   hipLaunchKernelGGL(evaluate_kernel, dim3((unsigned)groups), dim3(kEvThreads), 0, s, d_desc,
                      (int)nsub, pos, mass, ppc, L, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_evaluate_grid(int p, int n, double h, const double* pos, const double* mass,
+                                int ppc, const double* L, double* out, hipStream_t s) {
+  const int64_t nblk = (int64_t)(n / 8) * (n / 8) * (n / 8);
+  const int64_t groups = (nblk + 7) / 8 * 64;
+  hipLaunchKernelGGL(evaluate_grid_kernel, dim3((unsigned)groups), dim3(kEvThreads), 0, s, p, n, h,
+                     pos, mass, ppc, L, out);
   return hipGetLastError();
 }
 

@@ -112,6 +112,7 @@ struct fmm_ctx {
   double* d_D = nullptr;                      // [892][165] derivatives up to order 8
   double* d_T[kMaxP + 1] = {};                // canonical [892][C][C] per order
   MfmaTables mfma;                            // packed tables for the matrix-core kernels
+  TreeTables tree;                            // interaction-list tables of the multi-level M2L
   std::vector<std::unique_ptr<DescEntry>> descs;
   std::unordered_map<uint64_t, GraphEntry> graphs;
   uint64_t clock = 0;
@@ -380,6 +381,7 @@ fmm_status fmm_create(fmm_ctx** out, int32_t device) {
     CREATE_TRY(launch_build_tensors(c->d_D, kMaxOrderD, p, c->d_T[p], c->internal));
   }
   CREATE_TRY(mfma_tables_create(&c->mfma, c->d_T, c->d_stencil, c->internal));
+  CREATE_TRY(tree_tables_create(&c->tree, c->d_T, st.data(), (int)(st.size() / 3), c->internal));
   CREATE_TRY(hipStreamSynchronize(c->internal));
 #undef CREATE_TRY
   *out = ctx.release();
@@ -397,6 +399,7 @@ fmm_status fmm_destroy(fmm_ctx* ctx) {
     }
     for (auto& e : ctx->descs) free_entry(e.get());
     mfma_tables_destroy(&ctx->mfma);
+    tree_tables_destroy(&ctx->tree);
     for (int p = 0; p <= kMaxP; ++p)
       if (ctx->d_T[p]) (void)hipFree(ctx->d_T[p]);
     if (ctx->d_D) (void)hipFree(ctx->d_D);
@@ -490,6 +493,144 @@ fmm_status fmm_evaluate(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, con
   CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
   HIP_TRY(ctx, launch_evaluate(e->d_desc, nsub, pos, mass, ppc, L, out, s));
   return mark_used(ctx, e, s);
+}
+
+// ---------------------------------------------------------------------------
+// multi-level iteration on a uniform octree
+
+static fmm_status check_tree(fmm_ctx* ctx, const fmm_tree* t) {
+  if (!t) return set_err(ctx, FMM_EINVAL, "tree is NULL");
+  if (t->p < 2 || t->p > kMaxP) return set_err(ctx, FMM_EINVAL, "tree.p not in {2,3,4}");
+  if (t->n < 8 || t->n > 128 || (t->n & (t->n - 1)))
+    return set_err(ctx, FMM_EINVAL, "tree.n must be 8, 16, 32, 64 or 128");
+  if (t->ppc < 1 || t->ppc > 64) return set_err(ctx, FMM_EINVAL, "tree.ppc not in [1, 64]");
+  if (t->log2_h < -4 || t->log2_h > 4) return set_err(ctx, FMM_EINVAL, "tree.log2_h not in [-4, 4]");
+  return FMM_OK;
+}
+
+static int tree_nlevels(int n) {
+  int l = 1;
+  for (int m = n; m > 4; m /= 2) ++l;
+  return l;
+}
+
+// element offset of level l in a workspace
+static int64_t tree_level_off(const fmm_tree* t, int l) {
+  const int64_t C = ncomp(t->p);
+  int64_t off = 0;
+  for (int i = 0, m = t->n; i < l; ++i, m /= 2) off += C * m * m * m;
+  return off;
+}
+
+static fmm_status tree_begin(fmm_ctx* ctx, const fmm_tree* t) {
+  CHECK_OK(check_ctx(ctx));
+  CHECK_OK(check_tree(ctx, t));
+  return FMM_OK;
+}
+
+static fmm_status tree_device(fmm_ctx* ctx) {
+  if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
+  return FMM_OK;
+}
+
+fmm_status fmm_tree_size(const fmm_tree* tree, int32_t* levels, int64_t* elems) {
+  CHECK_OK(check_tree(nullptr, tree));
+  const int nl = tree_nlevels(tree->n);
+  if (levels) *levels = nl;
+  if (elems) *elems = tree_level_off(tree, nl);
+  return FMM_OK;
+}
+
+static fmm_status tree_upward(fmm_ctx* ctx, const fmm_tree* t, const double* pos, const double* mass,
+                              double* M, hipStream_t s) {
+  HIP_TRY(ctx, launch_tree_p2m(t->p, pos, mass, t->ppc, t->n, ldexp(1.0, t->log2_h), M, s));
+  const int nl = tree_nlevels(t->n);
+  for (int l = 0, m = t->n; l + 1 < nl; ++l, m /= 2)
+    HIP_TRY(ctx, launch_tree_m2m(t->p, M + tree_level_off(t, l), M + tree_level_off(t, l + 1), m,
+                                 ldexp(1.0, t->log2_h + l), s));
+  return FMM_OK;
+}
+
+static fmm_status tree_m2l(fmm_ctx* ctx, const fmm_tree* t, const double* M, double* L, hipStream_t s) {
+  const int nl = tree_nlevels(t->n);
+  for (int l = 0, m = t->n; l < nl; ++l, m /= 2)
+    HIP_TRY(ctx, launch_tree_m2l(t->p, ctx->tree, M + tree_level_off(t, l), L + tree_level_off(t, l), m,
+                                 t->log2_h + l, s));
+  return FMM_OK;
+}
+
+static fmm_status tree_downward(fmm_ctx* ctx, const fmm_tree* t, double* L, hipStream_t s) {
+  const int nl = tree_nlevels(t->n);
+  for (int l = nl - 2; l >= 0; --l)
+    HIP_TRY(ctx, launch_tree_l2l(t->p, L + tree_level_off(t, l + 1), L + tree_level_off(t, l),
+                                 t->n >> l, ldexp(1.0, t->log2_h + l), s));
+  return FMM_OK;
+}
+
+fmm_status fmm_tree_upward(fmm_ctx* ctx, const fmm_tree* tree, const double* pos, const double* mass,
+                           double* M, void* stream) {
+  CHECK_OK(tree_begin(ctx, tree));
+  CHECK_OK(check_ptr(ctx, pos, "pos", 1));
+  CHECK_OK(check_ptr(ctx, mass, "mass", 1));
+  CHECK_OK(check_ptr(ctx, M, "M", 1));
+  CHECK_OK(tree_device(ctx));
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  return tree_upward(ctx, tree, pos, mass, M, static_cast<hipStream_t>(stream));
+}
+
+fmm_status fmm_tree_m2l(fmm_ctx* ctx, const fmm_tree* tree, const double* M, double* L, void* stream) {
+  CHECK_OK(tree_begin(ctx, tree));
+  CHECK_OK(check_ptr(ctx, M, "M", 1));
+  CHECK_OK(check_ptr(ctx, L, "L", 1));
+  CHECK_OK(tree_device(ctx));
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  return tree_m2l(ctx, tree, M, L, static_cast<hipStream_t>(stream));
+}
+
+fmm_status fmm_tree_downward(fmm_ctx* ctx, const fmm_tree* tree, double* L, void* stream) {
+  CHECK_OK(tree_begin(ctx, tree));
+  CHECK_OK(check_ptr(ctx, L, "L", 1));
+  CHECK_OK(tree_device(ctx));
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  return tree_downward(ctx, tree, L, static_cast<hipStream_t>(stream));
+}
+
+fmm_status fmm_tree_evaluate(fmm_ctx* ctx, const fmm_tree* tree, const double* pos, const double* mass,
+                             const double* L, double* out, void* stream) {
+  CHECK_OK(tree_begin(ctx, tree));
+  CHECK_OK(check_ptr(ctx, pos, "pos", 1));
+  CHECK_OK(check_ptr(ctx, mass, "mass", 1));
+  CHECK_OK(check_ptr(ctx, L, "L", 1));
+  CHECK_OK(check_ptr(ctx, out, "out", 1));
+  CHECK_OK(tree_device(ctx));
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  HIP_TRY(ctx, launch_evaluate_grid(tree->p, tree->n, ldexp(1.0, tree->log2_h), pos, mass, tree->ppc, L,
+                                    out, static_cast<hipStream_t>(stream)));
+  return FMM_OK;
+}
+
+fmm_status fmm_tree_solve(fmm_ctx* ctx, const fmm_tree* tree, const double* pos, const double* mass,
+                          double* M, double* L, double* out, void* stream) {
+  CHECK_OK(tree_begin(ctx, tree));
+  CHECK_OK(check_ptr(ctx, pos, "pos", 1));
+  CHECK_OK(check_ptr(ctx, mass, "mass", 1));
+  CHECK_OK(check_ptr(ctx, M, "M", 1));
+  CHECK_OK(check_ptr(ctx, L, "L", 1));
+  CHECK_OK(check_ptr(ctx, out, "out", 1));
+  CHECK_OK(tree_device(ctx));
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CHECK_OK(tree_upward(ctx, tree, pos, mass, M, s));
+  CHECK_OK(tree_m2l(ctx, tree, M, L, s));
+  CHECK_OK(tree_downward(ctx, tree, L, s));
+  HIP_TRY(ctx, launch_evaluate_grid(tree->p, tree->n, ldexp(1.0, tree->log2_h), pos, mass, tree->ppc, L,
+                                    out, s));
+  return FMM_OK;
 }
 
 static fmm_status run_ref(fmm_ctx* ctx, DescEntry* e, bool backward, const double* src, double* out,

@@ -1,0 +1,418 @@
+// The multi-level gravity iteration on a uniform octree (the paper's
+// three-step iteration, Sec. VII-C: bottom-up traversal, cell-to-cell
+// interactions on every level, top-down traversal; Sec. IV-C: the octree's
+// cells carry multipole moments).
+//
+// Domain: n^3 finest cells of spacing h; level l has n / 2^l cells per axis of
+// spacing 2^l h, down to 4 per axis. Level arrays are [C][n_l][n_l][n_l]
+// (x fastest), finest level first, back to back.
+//
+//   P2M  finest level: M_k(j) = sum_i m_i (y_i - c_j)^k / k!
+//   M2M  M_k(J) = sum_{children j} sum_{q <= k} M_q(j) s^(k-q) / (k-q)!,  s = c_j - c_J
+//   M2L  every level: L_n(t) = sum_{d in IL(t)} sum_k M_k(t + d) T_d[k][n] at the
+//        level's spacing, IL(t) = {d : |d|^2 > 4, |floor((t mod 2 + d) / 2)|^2 <= 4}
+//        (sources not near the target whose parents are near the target's
+//        parent); on the 4-per-axis level every parent is near every other, so
+//        the same lists give all non-near sources there. Sources outside the
+//        domain are absent.
+//   L2L  L_n(j) += sum_{m >= n} L_m(J) s^(m-n) / (m-n)!, coarsest level first.
+//
+// IL(t) depends only on the parity sigma of t: 231 offsets per parity, all
+// inside the shell 5 <= |d|^2 <= 36 with |d_i| <= 5. The level M2L kernel
+// gives each of its 8 waves one parity class of an 8^3 target block, so a
+// wave's 64 targets (four 16-cell tiles, one per plane of that z parity) share
+// one offset list and one table stream: v_mfma_f64_4x4x4_4b over
+// [16 cells x 4 offsets] x [4 offsets x 4 columns] as in the single-level
+// kernels, with the 18^3 source window of two moment components per round in
+// LDS.
+#include <vector>
+
+#include "kernels.h"
+
+namespace fmm {
+
+namespace {
+
+constexpr int kTreeW = 18;                         // window: block cells -5 .. 12 per axis
+constexpr int kTreeWCells = kTreeW * kTreeW * kTreeW;
+constexpr int kTreeList = 231;                     // interaction-list length per parity
+constexpr int kTreeQuads = (kTreeList + 3) / 4;    // 58 (the last quad has one empty slot)
+constexpr int kTreeThreads = 512;
+constexpr int kTreeStage = (kTreeWCells + kTreeThreads - 1) / kTreeThreads;
+
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+// b^i / i! per axis for i <= P
+template <int P>
+__device__ __forceinline__ void powers(double bx, double by, double bz, double (&px)[P + 1],
+                                       double (&py)[P + 1], double (&pz)[P + 1]) {
+  px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+  for (int i = 1; i <= P; ++i) {
+    px[i] = px[i - 1] * bx * (1.0 / i);
+    py[i] = py[i - 1] * by * (1.0 / i);
+    pz[i] = pz[i - 1] * bz * (1.0 / i);
+  }
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) p2m_grid_kernel(const double* __restrict__ pos,
+                                                       const double* __restrict__ mass, int ppc,
+                                                       int n, double h, double* __restrict__ M) {
+  constexpr int C = ncomp(P);
+  const int64_t n3 = (int64_t)n * n * n;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n3) return;
+  const int x = (int)(j % n), y = (int)((j / n) % n), z = (int)(j / ((int64_t)n * n));
+  const double cx = (x + 0.5) * h, cy = (y + 0.5) * h, cz = (z + 0.5) * h;
+  double acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = 0.0;
+  for (int i = 0; i < ppc; ++i) {
+    const int64_t pi = j * ppc + i;
+    double px[P + 1], py[P + 1], pz[P + 1];
+    powers<P>(pos[3 * pi] - cx, pos[3 * pi + 1] - cy, pos[3 * pi + 2] - cz, px, py, pz);
+    const double m = mass[pi];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const MI k = mi_of(c);
+      acc[c] = __builtin_fma(m, px[k.x] * py[k.y] * pz[k.z], acc[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) M[c * n3 + j] = acc[c];
+}
+
+// One parent cell per thread; its 8 children's moments shifted to its centre.
+template <int P>
+__global__ void __launch_bounds__(256) m2m_kernel(const double* __restrict__ Mc,
+                                                  double* __restrict__ Mp, int nc, double hc) {
+  constexpr int C = ncomp(P);
+  const int np = nc / 2;
+  const int64_t np3 = (int64_t)np * np * np, nc3 = (int64_t)nc * nc * nc;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= np3) return;
+  const int X = (int)(i % np), Y = (int)((i / np) % np), Z = (int)(i / ((int64_t)np * np));
+  double acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = 0.0;
+#pragma unroll 1
+  for (int o = 0; o < 8; ++o) {
+    const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+    const int64_t g = (2 * X + ox) + (int64_t)nc * (2 * Y + oy) + (int64_t)nc * nc * (2 * Z + oz);
+    double mc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) mc[c] = Mc[c * nc3 + g];
+    double px[P + 1], py[P + 1], pz[P + 1];
+    powers<P>((ox - 0.5) * hc, (oy - 0.5) * hc, (oz - 0.5) * hc, px, py, pz);
+#pragma unroll
+    for (int ck = 0; ck < C; ++ck) {
+      const MI k = mi_of(ck);
+#pragma unroll
+      for (int cq = 0; cq < C; ++cq) {
+        const MI q = mi_of(cq);
+        if (q.x <= k.x && q.y <= k.y && q.z <= k.z)
+          acc[ck] = __builtin_fma(mc[cq], px[k.x - q.x] * py[k.y - q.y] * pz[k.z - q.z], acc[ck]);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) Mp[c * np3 + i] = acc[c];
+}
+
+// One child cell per thread: adds its parent's local polynomial re-expanded
+// about the child centre.
+template <int P>
+__global__ void __launch_bounds__(256) l2l_kernel(const double* __restrict__ Lp,
+                                                  double* __restrict__ Lc, int nc, double hc) {
+  constexpr int C = ncomp(P);
+  const int np = nc / 2;
+  const int64_t np3 = (int64_t)np * np * np, nc3 = (int64_t)nc * nc * nc;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= nc3) return;
+  const int x = (int)(j % nc), y = (int)((j / nc) % nc), z = (int)(j / ((int64_t)nc * nc));
+  const int64_t G = (x >> 1) + (int64_t)np * (y >> 1) + (int64_t)np * np * (z >> 1);
+  double lp[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) lp[c] = Lp[c * np3 + G];
+  double px[P + 1], py[P + 1], pz[P + 1];
+  powers<P>(((x & 1) - 0.5) * hc, ((y & 1) - 0.5) * hc, ((z & 1) - 0.5) * hc, px, py, pz);
+#pragma unroll
+  for (int cn = 0; cn < C; ++cn) {
+    const MI nn = mi_of(cn);
+    double s = 0.0;
+#pragma unroll
+    for (int cm = 0; cm < C; ++cm) {
+      const MI m = mi_of(cm);
+      if (nn.x <= m.x && nn.y <= m.y && nn.z <= m.z)
+        s = __builtin_fma(lp[cm], px[m.x - nn.x] * py[m.y - nn.y] * pz[m.z - nn.z], s);
+    }
+    Lc[cn * nc3 + j] += s;
+  }
+}
+
+// Tables of the level kernel, per order p:
+//   B[sigma][round][quad][c2][group][kk * 4 + j] = T_d[2 round + c2][4 group + j]
+// at unit spacing, d = the kk-th offset of the quad in sigma's list (zero for
+// the empty slot, k >= C or n >= C). Built from the canonical [892][C][C]
+// tables with the map sidx[sigma][quad][kk] (stencil index or -1).
+__global__ void pack_tree_kernel(const double* __restrict__ T, int C, const int* __restrict__ sidx,
+                                 double* __restrict__ B) {
+  const int NG = (C + 3) / 4, R = (C + 1) / 2;
+  const int64_t total = (int64_t)8 * R * kTreeQuads * 2 * NG * 16;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r_ = e;
+    const int v = (int)(r_ % 16); r_ /= 16;
+    const int g = (int)(r_ % NG); r_ /= NG;
+    const int c2 = (int)(r_ % 2); r_ /= 2;
+    const int q = (int)(r_ % kTreeQuads); r_ /= kTreeQuads;
+    const int r = (int)(r_ % R);
+    const int sigma = (int)(r_ / R);
+    const int kk = v >> 2, j = v & 3;
+    const int k = 2 * r + c2, nn = 4 * g + j;
+    const int s = sidx[(sigma * kTreeQuads + q) * 4 + kk];
+    B[e] = (s >= 0 && k < C && nn < C) ? T[((int64_t)s * C + k) * C + nn] : 0.0;
+  }
+}
+
+template <int P>
+__global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
+    const double* __restrict__ M, double* __restrict__ L, int n, int lg,
+    const double* __restrict__ B, const int* __restrict__ doff) {
+  constexpr int C = ncomp(P);
+  constexpr int NG = (C + 3) / 4;
+  constexpr int ROUNDS = (C + 1) / 2;
+  __shared__ double2 smem[kTreeWCells];
+  __shared__ int s_doff[8 * kTreeQuads * 4];
+  const int nb = n >= 8 ? n / 8 : 1;
+  const int blk = blockIdx.x;
+  const int B0x = 8 * (blk % nb), B0y = 8 * ((blk / nb) % nb), B0z = 8 * (blk / (nb * nb));
+  const int64_t n3 = (int64_t)n * n * n;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // parity class of this wave
+  const int sx = wave & 1, sy = (wave >> 1) & 1, sz = wave >> 2;
+  const int kk = lane >> 4, ci = lane & 15;
+  for (int i = tid; i < 8 * kTreeQuads * 4; i += kTreeThreads) s_doff[i] = doff[i];
+
+  // tile t: plane z = 2 t + sz, cells (2 (ci & 3) + sx, 2 (ci >> 2) + sy)
+  int abase[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int z = 2 * t + sz, x = 2 * (ci & 3) + sx, y = 2 * (ci >> 2) + sy;
+    abase[t] = (x + 5) + kTreeW * (y + 5) + kTreeW * kTreeW * (z + 5);
+  }
+  double acc[4][NG];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) acc[t][g] = 0.0;
+
+  const int* dq = s_doff + wave * kTreeQuads * 4 + kk;
+  for (int r = 0; r < ROUNDS; ++r) {
+    const int k0 = 2 * r, k1 = 2 * r + 1;
+    const double s0 = ldexp(1.0, -lg * order_of(k0));
+    const double s1 = k1 < C ? ldexp(1.0, -lg * order_of(k1)) : 0.0;
+    const double* src0 = M + (int64_t)k0 * n3;
+    const double* src1 = M + (int64_t)(k1 < C ? k1 : k0) * n3;
+    double2 v[kTreeStage];
+#pragma unroll
+    for (int i = 0; i < kTreeStage; ++i) {
+      const int c = tid + i * kTreeThreads;
+      v[i] = make_double2(0.0, 0.0);
+      if (c < kTreeWCells) {
+        const int gx = B0x - 5 + c % kTreeW, gy = B0y - 5 + (c / kTreeW) % kTreeW,
+                  gz = B0z - 5 + c / (kTreeW * kTreeW);
+        if (gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n) {
+          const int64_t g = gx + (int64_t)n * gy + (int64_t)n * n * gz;
+          v[i].x = src0[g];
+          v[i].y = src1[g];
+        }
+      }
+    }
+    __syncthreads();   // the previous round's window reads are done
+#pragma unroll
+    for (int i = 0; i < kTreeStage; ++i) {
+      const int c = tid + i * kTreeThreads;
+      if (c < kTreeWCells) smem[c] = make_double2(v[i].x * s0, v[i].y * s1);
+    }
+    __syncthreads();
+    const double* Br = B + ((int64_t)(wave * ROUNDS + r) * kTreeQuads) * 2 * NG * 16 + kk * 4 + (lane & 3);
+    double nb0[NG], nb1[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      nb0[g] = Br[g * 16];
+      nb1[g] = Br[(NG + g) * 16];
+    }
+    for (int q = 0; q < kTreeQuads; ++q) {
+      double b0[NG], b1[NG];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        b0[g] = nb0[g];
+        b1[g] = nb1[g];
+      }
+      if (q + 1 < kTreeQuads) {
+        const double* Bn = Br + (int64_t)(q + 1) * 2 * NG * 16;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          nb0[g] = Bn[g * 16];
+          nb1[g] = Bn[(NG + g) * 16];
+        }
+      }
+      const int dl = dq[q * 4];
+      double2 a[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a[t] = smem[abase[t] + dl];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a[t].x, b0[g], acc[t][g]);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a[t].y, b1[g], acc[t][g]);
+      }
+    }
+  }
+
+  // D layout: this lane holds cell (2 xi + sx, 2 yi + sy) of each tile, column j
+  const int xi = lane >> 4, yi = (lane & 15) >> 2, j = lane & 3;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int gx = B0x + 2 * xi + sx, gy = B0y + 2 * yi + sy, gz = B0z + 2 * t + sz;
+    if (gx >= n || gy >= n || gz >= n) continue;
+    const int64_t g = gx + (int64_t)n * gy + (int64_t)n * n * gz;
+#pragma unroll
+    for (int gg = 0; gg < NG; ++gg) {
+      const int nn = 4 * gg + j;
+      if (nn < C) L[nn * n3 + g] = ldexp(acc[t][gg], -lg * (1 + order_of(nn)));
+    }
+  }
+}
+
+unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+// Interaction lists on the host: for each parity sigma (x + 2 y + 4 z bits),
+// the offsets d (dz slowest, then dy, dx, ascending) with |d|^2 > 4 whose
+// parents' offset floor((sigma + d) / 2) has squared length <= 4.
+static std::vector<int> tree_lists() {
+  std::vector<int> out;
+  auto fl2 = [](int a) { return a >= 0 ? a / 2 : -((1 - a) / 2); };   // floor(a / 2)
+  for (int sigma = 0; sigma < 8; ++sigma) {
+    const int sg[3] = {sigma & 1, (sigma >> 1) & 1, sigma >> 2};
+    int count = 0;
+    for (int dz = -6; dz <= 6; ++dz)
+      for (int dy = -6; dy <= 6; ++dy)
+        for (int dx = -6; dx <= 6; ++dx) {
+          if (dx * dx + dy * dy + dz * dz <= 4) continue;
+          const int Dx = fl2(sg[0] + dx), Dy = fl2(sg[1] + dy), Dz = fl2(sg[2] + dz);
+          if (Dx * Dx + Dy * Dy + Dz * Dz > 4) continue;
+          out.push_back(dx);
+          out.push_back(dy);
+          out.push_back(dz);
+          ++count;
+        }
+    if (count != kTreeList) return {};
+  }
+  return out;
+}
+
+hipError_t tree_tables_create(TreeTables* tt, const double* const* d_T, const int* stencil_xyz,
+                              int nstencil, hipStream_t s) {
+  const std::vector<int> lists = tree_lists();
+  if (lists.empty()) return hipErrorInvalidValue;
+  std::vector<int> sidx(8 * kTreeQuads * 4, -1), doff(8 * kTreeQuads * 4, 0);
+  for (int sigma = 0; sigma < 8; ++sigma)
+    for (int e = 0; e < kTreeList; ++e) {
+      const int* d = &lists[3 * (sigma * kTreeList + e)];
+      int found = -1;
+      for (int i = 0; i < nstencil; ++i)
+        if (stencil_xyz[3 * i] == d[0] && stencil_xyz[3 * i + 1] == d[1] && stencil_xyz[3 * i + 2] == d[2]) {
+          found = i;
+          break;
+        }
+      if (found < 0) return hipErrorInvalidValue;
+      sidx[sigma * kTreeQuads * 4 + e] = found;
+      doff[sigma * kTreeQuads * 4 + e] = d[0] + kTreeW * d[1] + kTreeW * kTreeW * d[2];
+    }
+  hipError_t e;
+  int* d_sidx = nullptr;
+  if ((e = hipMalloc(&tt->doff, sizeof(int) * doff.size())) != hipSuccess) return e;
+  if ((e = hipMemcpy(tt->doff, doff.data(), sizeof(int) * doff.size(), hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMalloc(&d_sidx, sizeof(int) * sidx.size())) != hipSuccess) return e;
+  if ((e = hipMemcpy(d_sidx, sidx.data(), sizeof(int) * sidx.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+    (void)hipFree(d_sidx);
+    return e;
+  }
+  for (int p = 2; p <= kMaxP; ++p) {
+    const int C = ncomp(p), NG = (C + 3) / 4, R = (C + 1) / 2;
+    const size_t count = (size_t)8 * R * kTreeQuads * 2 * NG * 16;
+    if ((e = hipMalloc(&tt->B[p], sizeof(double) * count)) != hipSuccess) break;
+    hipLaunchKernelGGL(pack_tree_kernel, dim3(1024), dim3(256), 0, s, d_T[p], C, d_sidx, tt->B[p]);
+    if ((e = hipGetLastError()) != hipSuccess) break;
+  }
+  hipError_t e2 = hipStreamSynchronize(s);
+  (void)hipFree(d_sidx);
+  return e != hipSuccess ? e : e2;
+}
+
+void tree_tables_destroy(TreeTables* tt) {
+  for (int p = 0; p <= kMaxP; ++p)
+    if (tt->B[p]) (void)hipFree(tt->B[p]);
+  if (tt->doff) (void)hipFree(tt->doff);
+  *tt = TreeTables{};
+}
+
+hipError_t launch_tree_p2m(int p, const double* pos, const double* mass, int ppc, int n, double h,
+                           double* M, hipStream_t s) {
+  const int64_t n3 = (int64_t)n * n * n;
+  const dim3 grid(blocks_for(n3, 256)), block(256);
+  switch (p) {
+    case 2: hipLaunchKernelGGL(p2m_grid_kernel<2>, grid, block, 0, s, pos, mass, ppc, n, h, M); break;
+    case 3: hipLaunchKernelGGL(p2m_grid_kernel<3>, grid, block, 0, s, pos, mass, ppc, n, h, M); break;
+    case 4: hipLaunchKernelGGL(p2m_grid_kernel<4>, grid, block, 0, s, pos, mass, ppc, n, h, M); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tree_m2m(int p, const double* Mc, double* Mp, int nc, double hc, hipStream_t s) {
+  const int64_t np3 = (int64_t)(nc / 2) * (nc / 2) * (nc / 2);
+  const dim3 grid(blocks_for(np3, 256)), block(256);
+  switch (p) {
+    case 2: hipLaunchKernelGGL(m2m_kernel<2>, grid, block, 0, s, Mc, Mp, nc, hc); break;
+    case 3: hipLaunchKernelGGL(m2m_kernel<3>, grid, block, 0, s, Mc, Mp, nc, hc); break;
+    case 4: hipLaunchKernelGGL(m2m_kernel<4>, grid, block, 0, s, Mc, Mp, nc, hc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tree_l2l(int p, const double* Lp, double* Lc, int nc, double hc, hipStream_t s) {
+  const int64_t nc3 = (int64_t)nc * nc * nc;
+  const dim3 grid(blocks_for(nc3, 256)), block(256);
+  switch (p) {
+    case 2: hipLaunchKernelGGL(l2l_kernel<2>, grid, block, 0, s, Lp, Lc, nc, hc); break;
+    case 3: hipLaunchKernelGGL(l2l_kernel<3>, grid, block, 0, s, Lp, Lc, nc, hc); break;
+    case 4: hipLaunchKernelGGL(l2l_kernel<4>, grid, block, 0, s, Lp, Lc, nc, hc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tree_m2l(int p, const TreeTables& tt, const double* M, double* L, int n, int lg,
+                           hipStream_t s) {
+  const int nb = n >= 8 ? n / 8 : 1;
+  const dim3 grid((unsigned)(nb * nb * nb)), block(kTreeThreads);
+  switch (p) {
+    case 2: hipLaunchKernelGGL(m2l_level_kernel<2>, grid, block, 0, s, M, L, n, lg, tt.B[2], tt.doff); break;
+    case 3: hipLaunchKernelGGL(m2l_level_kernel<3>, grid, block, 0, s, M, L, n, lg, tt.B[3], tt.doff); break;
+    case 4: hipLaunchKernelGGL(m2l_level_kernel<4>, grid, block, 0, s, M, L, n, lg, tt.B[4], tt.doff); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fmm

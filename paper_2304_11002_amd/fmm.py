@@ -23,11 +23,20 @@ EXPORTS = [
     "fmm_create", "fmm_destroy", "fmm_status_string", "fmm_last_error", "fmm_set_option",
     "fmm_stencil", "fmm_pair_count", "fmm_p2m", "fmm_m2l", "fmm_m2l_backward",
     "fmm_p2m_backward", "fmm_stencil_tables", "fmm_autotune", "fmm_evaluate",
+    "fmm_tree_size", "fmm_tree_upward", "fmm_tree_m2l", "fmm_tree_downward", "fmm_tree_evaluate",
+    "fmm_tree_solve",
 ]
 
 DESC_DTYPE = np.dtype([("p", "<i4"), ("log2_inv_h", "<i4"), ("mask", "<u4"), ("reserved", "<i4"),
                        ("m_off", "<i8"), ("l_off", "<i8"), ("part_off", "<i8")])
 assert DESC_DTYPE.itemsize == 40
+
+
+class Tree(ctypes.Structure):
+    """fmm_tree: a uniform n^3 domain of finest spacing 2^log2_h, order p, ppc
+    particles per finest cell."""
+    _fields_ = [("p", ctypes.c_int32), ("n", ctypes.c_int32), ("ppc", ctypes.c_int32),
+                ("log2_h", ctypes.c_int32)]
 
 
 class FMMError(RuntimeError):
@@ -64,6 +73,12 @@ def load_library(path=LIB_PATH):
         "fmm_stencil_tables": ([vp, i32, vp, vp], i32),
         "fmm_autotune": ([vp, vp, i64, vp, vp, i32, vp, ctypes.POINTER(i32)], i32),
         "fmm_evaluate": ([vp, vp, i64, vp, vp, i32, vp, vp, vp], i32),
+        "fmm_tree_size": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i64)], i32),
+        "fmm_tree_upward": ([vp, vp, vp, vp, vp, vp], i32),
+        "fmm_tree_m2l": ([vp, vp, vp, vp, vp], i32),
+        "fmm_tree_downward": ([vp, vp, vp, vp], i32),
+        "fmm_tree_evaluate": ([vp, vp, vp, vp, vp, vp, vp], i32),
+        "fmm_tree_solve": ([vp, vp, vp, vp, vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -119,6 +134,14 @@ def pair_count(desc):
     out = ctypes.c_int64()
     _check(lib.fmm_pair_count(pd, n, ctypes.byref(out)), None)
     return out.value
+
+
+def tree_size(tree):
+    """(levels, float64 elements of one M or L workspace) of a Tree."""
+    lib = load_library()
+    nl, ne = ctypes.c_int32(), ctypes.c_int64()
+    _check(lib.fmm_tree_size(ctypes.byref(tree), ctypes.byref(nl), ctypes.byref(ne)), None)
+    return nl.value, ne.value
 
 
 def _check(status, ctx_handle):
@@ -219,6 +242,26 @@ class Context:
         pd, n = _desc_ptr(desc)
         self._run(self.lib.fmm_evaluate(self.handle, pd, n, _ptr(pos), _ptr(mass), int(ppc),
                                         _ptr(L), _ptr(out), self._s(stream, n)))
+
+    # multi-level iteration on a uniform octree (tree: a Tree)
+    def tree_upward(self, tree, pos, mass, M, stream=None):
+        self._run(self.lib.fmm_tree_upward(self.handle, ctypes.byref(tree), _ptr(pos), _ptr(mass),
+                                           _ptr(M), self._s(stream, 1)))
+
+    def tree_m2l(self, tree, M, L, stream=None):
+        self._run(self.lib.fmm_tree_m2l(self.handle, ctypes.byref(tree), _ptr(M), _ptr(L),
+                                        self._s(stream, 1)))
+
+    def tree_downward(self, tree, L, stream=None):
+        self._run(self.lib.fmm_tree_downward(self.handle, ctypes.byref(tree), _ptr(L), self._s(stream, 1)))
+
+    def tree_evaluate(self, tree, pos, mass, L, out, stream=None):
+        self._run(self.lib.fmm_tree_evaluate(self.handle, ctypes.byref(tree), _ptr(pos), _ptr(mass),
+                                             _ptr(L), _ptr(out), self._s(stream, 1)))
+
+    def tree_solve(self, tree, pos, mass, M, L, out, stream=None):
+        self._run(self.lib.fmm_tree_solve(self.handle, ctypes.byref(tree), _ptr(pos), _ptr(mass),
+                                          _ptr(M), _ptr(L), _ptr(out), self._s(stream, 1)))
 
     def stencil_tables(self, p, out, stream=None):
         self._run(self.lib.fmm_stencil_tables(self.handle, int(p), _ptr(out), self._s(stream, 1)))

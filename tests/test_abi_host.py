@@ -157,3 +157,32 @@ def test_descriptor_layout():
     assert list(desc["l_off"]) == [0, 10 * 512, 30 * 512]
     assert m_el == 65 * 13824 and l_el == 65 * 512
     assert list(desc["part_off"]) == [0, 13824 * 8, 2 * 13824 * 8]
+
+
+def test_tree_argument_checks(hctx, lib):
+    ok = fmm.Tree(3, 16, 8, 0)
+    assert fmm.tree_size(ok) == (3, 20 * (16 ** 3 + 8 ** 3 + 4 ** 3))
+    assert fmm.tree_size(fmm.Tree(2, 128, 1, -4)) == (6, 10 * sum(m ** 3 for m in (128, 64, 32, 16, 8, 4)))
+    for bad in (fmm.Tree(1, 16, 8, 0), fmm.Tree(5, 16, 8, 0), fmm.Tree(3, 12, 8, 0), fmm.Tree(3, 4, 8, 0),
+                fmm.Tree(3, 256, 8, 0), fmm.Tree(3, 16, 0, 0), fmm.Tree(3, 16, 65, 0), fmm.Tree(3, 16, 8, 5),
+                fmm.Tree(3, 16, 8, -5)):
+        with pytest.raises(fmm.FMMError) as e:
+            fmm.tree_size(bad)
+        assert e.value.status == fmm.FMM_EINVAL
+        with pytest.raises(fmm.FMMError) as e:
+            hctx.tree_solve(bad, 8, 8, 8, 8, 8)
+        assert e.value.status == fmm.FMM_EINVAL
+    for call in (lambda: hctx.tree_upward(ok, 0, 8, 8), lambda: hctx.tree_m2l(ok, 8, 12),
+                 lambda: hctx.tree_downward(ok, 0), lambda: hctx.tree_evaluate(ok, 8, 8, 8, 0),
+                 lambda: hctx.tree_solve(ok, 8, 8, 8, 8, None)):
+        with pytest.raises(fmm.FMMError) as e:
+            call()
+        assert e.value.status == fmm.FMM_EINVAL
+    for call in (lambda: hctx.tree_upward(ok, 8, 8, 8), lambda: hctx.tree_m2l(ok, 8, 8),
+                 lambda: hctx.tree_downward(ok, 8), lambda: hctx.tree_evaluate(ok, 8, 8, 8, 8),
+                 lambda: hctx.tree_solve(ok, 8, 8, 8, 8, 8)):
+        with pytest.raises(fmm.FMMError) as e:
+            call()
+        assert e.value.status == fmm.FMM_EUNSUPPORTED
+    assert lib.fmm_tree_size(None, None, None) == fmm.FMM_EINVAL
+
