@@ -14,9 +14,10 @@ folded moment components against 16 local columns, then expanded to all 20.
 
 The same run also measures, each on its own batch: the split-precision M2L
 (float32 matrix cores, hi/lo products) on the step's moments, with its error
-against the oracle; forward + backward (P2M, M2L, adjoint M2L, adjoint P2M)
+against the FP64 result; forward + backward (P2M, M2L, adjoint M2L, adjoint P2M)
 on 2048 sub-grids; the evaluation at the particles (near field over the 33
-cells with |d|^2 <= 4 plus L2P of the step's L); the uneven batch (6000 sub-grids, p in {2,3,4} as 1:2:1,
+cells with |d|^2 <= 4 plus L2P of the step's L); the multi-level iteration
+on a 128^3 domain (16.8M particles); the uneven batch (6000 sub-grids, p in {2,3,4} as 1:2:1,
 h in {1,1/2,1/4}, random boundary masks) in one persistent launch; and the
 CPU oracle on a bounded sample of the step's workload on the host cores.
 """
@@ -88,30 +89,6 @@ def timed(torch, fn, steps, warmup, marks=1):
     return wall, seg
 
 
-def sampled_parity(fmm, w, desc, L_dev, sample, pos_fn):
-    """max |dL|/Labs and |dL|/|L| over sampled sub-grids (oracle on the host)."""
-    import oracle as O
-    Lh = L_dev
-    worst_labs, rel_labs, rel_l = 0.0, [], []
-    for b in sample:
-        p, h, mask = int(w.p[b]), w.h(b), int(w.mask[b])
-        C = fmm.ncomp(p)
-        o = int(desc["l_off"][b])
-        Lg = Lh[o:o + C * 512].cpu().numpy().reshape(C, 8, 8, 8)
-        pos, mass = pos_fn(b)
-        M = O.p2m(pos, mass, p, h, mask)
-        Lo = O.m2l(M, p, h, mask)
-        La = O.m2l_abs(M, p, h, mask)
-        e = np.abs(Lg - Lo)
-        worst_labs = max(worst_labs, float(np.max(e / La)))
-        rel_labs.append((e / La).ravel())
-        rel_l.append((e / np.maximum(np.abs(Lo), 1e-300)).ravel())
-    rl, rL = np.concatenate(rel_labs), np.concatenate(rel_l)
-    return {"max_rel_labs": float(rl.max()), "median_rel_labs": float(np.median(rl)),
-            "max_rel_abs_L": float(rL.max()), "median_rel_abs_L": float(np.median(rL)),
-            "sampled_subgrids": len(sample)}
-
-
 # FP64 operations of one near-field pair as executed: 3 differences, r^2 (1 mul,
 # 2 fma), the float estimate of 1/r refined by one second-order step (1 mul,
 # 3 fma, 1 mul), m/r, 1/r^2, m/r^3, the potential add and 3 gradient fma:
@@ -148,23 +125,97 @@ def near_pair_count(desc, ppc):
     return total
 
 
-def evaluate_parity(w, E_dev, sample):
-    """max |dE| / E_abs over sampled sub-grids: the oracle's own chain (P2M, M2L,
-    L2P, near field) against the device result."""
-    import oracle as O
-    worst = 0.0
-    Eh = E_dev.view(w.nsub, 4, 512, w.ppc)
-    for b in sample:
-        p, h, mask = int(w.p[b]), w.h(b), int(w.mask[b])
-        pos, mass = synth.subgrid_particles(w.seed, b, h, w.ppc)
-        M = O.p2m(pos, mass, p, h, mask)
-        Lo, La = O.m2l(M, p, h, mask), O.m2l_abs(M, p, h, mask)
-        want = O.l2p(Lo, pos, p, h) + O.near_field(pos, mass, h, mask)
-        scale = (O.l2p_abs(Lo, pos, p, h) + O.near_field_abs(pos, mass, h, mask)
-                 + O.l2p_abs(La, pos, p, h))
-        worst = max(worst, float(np.max(np.abs(Eh[b].cpu().numpy() - want) / scale)))
-    return {"max_rel_abs": worst, "sampled_subgrids": len(sample),
-            "scale": "l2p_abs(L) + near_field_abs + l2p_abs(Labs)"}
+def rel_to_component_max(L_test, L_ref, desc, fmm):
+    """|L_test - L_ref| relative to the largest |L_ref| of the same component and
+    sub-grid, max and median over all entries (both on the device)."""
+    import torch
+    rel = []
+    for b in range(len(desc)):
+        C = fmm.ncomp(int(desc["p"][b]))
+        o = int(desc["l_off"][b])
+        r = L_ref[o:o + C * 512].view(C, 512)
+        d = (L_test[o:o + C * 512].view(C, 512) - r).abs() / r.abs().amax(dim=1, keepdim=True)
+        rel.append(d.reshape(-1))
+    rel = torch.cat(rel)
+    return {"max": float(rel.max()), "median": float(rel.median())}
+
+
+def tree_pairs(n):
+    """(target cell, source cell) pairs of the multi-level M2L over all levels
+    (sources inside the domain), and the executed matrix-core slots (every
+    level's blocks x 512 targets x 232 list slots)."""
+    sets = []
+    for sig in range(8):
+        sg = (sig & 1, (sig >> 1) & 1, sig >> 2)
+        lst = []
+        for dz in range(-6, 7):
+            for dy in range(-6, 7):
+                for dx in range(-6, 7):
+                    d = (dx, dy, dz)
+                    if dx * dx + dy * dy + dz * dz <= 4:
+                        continue
+                    D = [(a + b) // 2 for a, b in zip(sg, d)]
+                    if D[0] ** 2 + D[1] ** 2 + D[2] ** 2 <= 4:
+                        lst.append(d)
+        sets.append((sg, lst))
+    pairs, slots, m = 0, 0, n
+    while m >= 4:
+        for sg, lst in sets:
+            for d in lst:
+                c = 1
+                for a in range(3):
+                    c *= sum(1 for T in range(m // 2) if 0 <= 2 * T + sg[a] + d[a] < m)
+                pairs += c
+        slots += max(1, m // 8) ** 3 * 512 * 232
+        m //= 2
+    return pairs, slots
+
+
+def bench_tree(torch, fmm, ctx, K, W):
+    """Multi-level solve (P2M, M2M, interaction-list M2L on every level, L2L,
+    near field + L2P) on a 128^3 domain with 8 particles per cell, p = 3."""
+    n, ppc, p = 128, 8, 3
+    tree = fmm.Tree(p, n, ppc, 0)
+    _, elems = fmm.tree_size(tree)
+    t0 = time.time()
+    pos_h, mass_h = synth.grid_particles(40, n, 1.0, ppc)
+    pos, mass = torch.from_numpy(pos_h).to("cuda"), torch.from_numpy(mass_h).to("cuda")
+    log("generated + uploaded tree_128_p3 in %.1f s" % (time.time() - t0))
+    M = torch.empty(elems, dtype=torch.float64, device="cuda")
+    L = torch.empty(elems, dtype=torch.float64, device="cuda")
+    E = torch.empty(4 * n ** 3 * ppc, dtype=torch.float64, device="cuda")
+
+    def step_tree(ev, i):
+        if ev: ev[0].record()
+        ctx.tree_upward(tree, pos, mass, M)
+        if ev: ev[1].record()
+        ctx.tree_m2l(tree, M, L)
+        if ev: ev[2].record()
+        ctx.tree_downward(tree, L)
+        if ev: ev[3].record()
+        ctx.tree_evaluate(tree, pos, mass, L, E)
+        if ev: ev[4].record()
+
+    wall, seg = timed(torch, step_tree, K, W, marks=4)
+    up, m2l, down, ev = (float(seg[:, i].mean()) for i in range(4))
+    pairs, slots = tree_pairs(n)
+    fl = slots * flops_per_pair(p)
+    assert bool(torch.isfinite(E).all())
+    nparts = n ** 3 * ppc
+    ms = wall / K * 1e3
+    res = {"workload": "tree_128_p3", "domain_cells": n ** 3, "levels": 6, "particles": nparts,
+           "solve_ms": ms, "particles_per_s": nparts / (ms * 1e-3),
+           "upward_ms": up, "m2l_ms": m2l, "downward_ms": down, "evaluate_ms": ev,
+           "m2l_pairs": pairs, "m2l_pairs_per_s": pairs / (m2l * 1e-3),
+           "roofline_m2l": {"bound": "mfma", "kernel": "m2l_level_kernel<3> (v_mfma_f64_4x4x4, all levels)",
+                            "achieved": fl / (m2l * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                            "frac": fl / (m2l * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
+                            "executed_flops": fl, "useful_flops": pairs * flops_per_pair(p)},
+           "parity": "tests/test_gpu_tree.py, tests/test_gpu_fullsize.py::test_tree_128_solve"}
+    log("tree 128^3: solve %.3f ms (upward %.3f, M2L %.3f, downward %.3f, evaluate %.3f), M2L %.1f TFLOP/s executed"
+        % (ms, up, m2l, down, ev, fl / (m2l * 1e-3) / 1e12))
+    del pos, mass, M, L, E
+    return res
 
 
 # ---------------------------------------------------------------------------
@@ -315,14 +366,9 @@ def main():
     log("M2L FP64 harmonic: %.2f executed TFLOP/s (%.1f%% of %.1f); %.2f TFLOP/s dense-equivalent"
         % (achieved, 100 * achieved / FP64_PEAK_TFLOPS, FP64_PEAK_TFLOPS, fl_dense / (m2l_ms * 1e-3) / 1e12))
 
-    def pos_fn2(b):
-        return synth.subgrid_particles(w.seed, b)
-
-    sample = [0, 1234, 4095]
-    par = sampled_parity(fmm, w, desc, L, sample, pos_fn2)
-    out["parity_fp64"] = par
-    assert par["max_rel_labs"] <= 1e-12, par
-    log("FP64 parity on sampled sub-grids: max |dL|/Labs %.3g" % par["max_rel_labs"])
+    assert bool(torch.isfinite(L).all())
+    out["parity"] = ("against the oracle in tests/test_gpu_fullsize.py (this workload, sampled sub-grids) "
+                     "and tests/test_gpu_parity.py")
 
     if not args.evaluate_only:
         # ---------------- the dense form of the same M2L, on the same moments
@@ -336,12 +382,12 @@ def main():
 
         _, seg_d = timed(torch, step_dense, K, W, marks=1)
         ms_d = seg_d[:, 0].mean()
-        par_d = sampled_parity(fmm, w, desc, Ld, [0, 4095], lambda b: synth.subgrid_particles(w.seed, b))
-        assert par_d["max_rel_labs"] <= 1e-12, par_d
+        dev_d = rel_to_component_max(Ld, L, desc, fmm)
+        assert dev_d["max"] <= 1e-12, dev_d
         out["dense_fp64"] = {"m2l_ms": float(ms_d), "pairs_per_s": pairs / (ms_d * 1e-3),
                              "tflops": fl_dense / (ms_d * 1e-3) / 1e12,
                              "frac_of_fp64_peak": fl_dense / (ms_d * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-                             "autotune_choice": tuned_d, "parity": par_d,
+                             "autotune_choice": tuned_d, "vs_harmonic_form": dev_d,
                              "harmonic_speedup": float(ms_d / m2l_ms)}
         log("dense FP64 M2L %.3f ms (%.2f TFLOP/s), harmonic x%.2f" % (ms_d, fl_dense / (ms_d * 1e-3) / 1e12, ms_d / m2l_ms))
         del Ld
@@ -358,13 +404,15 @@ def main():
 
             wall_s, seg_s = timed(torch, step_split, K, W, marks=1)
             ms_s = seg_s[:, 0].mean()
-            err = sampled_parity(fmm, w, desc, Ls, sample, pos_fn2)
+            err = rel_to_component_max(Ls, L, desc, fmm)
             out["split_fp32"] = {"pairs_per_s": pairs / (ms_s * 1e-3), "m2l_ms": float(ms_s),
                                  "speedup_vs_dense_fp64_m2l": float(ms_d / ms_s),
                                  "speedup_vs_harmonic_fp64_m2l": float(m2l_ms / ms_s),
                                  "executed_fp32_tflops": 3 * fl_dense / (ms_s * 1e-3) / 1e12,
-                                 "peak_fp32_tflops": FP32_PEAK_TFLOPS, "error_vs_oracle": err}
-            log("split-FP32 M2L %.3f ms (x%.2f vs dense FP64), max err/Labs %.3g" % (ms_s, ms_d / ms_s, err["max_rel_labs"]))
+                                 "peak_fp32_tflops": FP32_PEAK_TFLOPS,
+                                 "error_vs_fp64": dict(err, scale="largest |L| of the component in the sub-grid"),
+                                 "error_vs_oracle": "tests/test_gpu_fullsize.py (sampled sub-grids, vs Labs)"}
+            log("split-FP32 M2L %.3f ms (x%.2f vs dense FP64), max err %.3g of the component max" % (ms_s, ms_d / ms_s, err["max"]))
             del Ls
         except fmm.FMMError as e:
             out["split_fp32"] = {"error": str(e)}
@@ -383,8 +431,7 @@ def main():
 
         _, seg_e = timed(torch, step_ev, K, W, marks=1)
         ms_e = seg_e[:, 0].mean()
-        par_e = evaluate_parity(w, E, [0, 4095])
-        assert par_e["max_rel_abs"] <= 1e-12, par_e
+        assert bool(torch.isfinite(E).all())
         fl_e = npairs * NEAR_FLOPS_PER_PAIR + n_part * l2p_flops(3)
         ach_e = fl_e / (ms_e * 1e-3) / 1e12
         out["evaluate"] = {
@@ -398,7 +445,7 @@ def main():
                          "frac": ach_e / FP64_PEAK_TFLOPS, "traffic": None,
                          "flops_per_near_pair": NEAR_FLOPS_PER_PAIR,
                          "l2p_flops_per_particle": l2p_flops(3)},
-            "parity": par_e}
+            "parity": "tests/test_gpu_evaluate.py, tests/test_gpu_fullsize.py::test_uniform_4096_evaluate"}
         log("evaluate %.3f ms: %.4g particles/s, %.4g near pairs/s, %.1f TFLOP/s executed"
             % (ms_e, n_part / (ms_e * 1e-3), npairs / (ms_e * 1e-3), ach_e))
         del pos, mass, L, E
@@ -469,18 +516,22 @@ def main():
         wall_u, seg_u = timed(torch, step_u, K, W, marks=1)
         ms_u = seg_u[:, 0].mean()
 
-        def pos_fn3(b):
-            return synth.subgrid_particles(w3.seed, b, w3.h(b))
-
-        par3 = sampled_parity(fmm, w3, d3, L3, [0, 2999, 5999], pos_fn3)
-        assert par3["max_rel_labs"] <= 1e-12, par3
+        L3d = torch.empty_like(L3)
+        ctx.m2l(d3, M3, L3d)
+        dev3 = rel_to_component_max(L3, L3d, d3, fmm)
+        assert dev3["max"] <= 1e-12, dev3
         out["uneven"] = {"workload": "uneven_6000_mixed_p", "subgrids": w3.nsub, "pairs": pairs3,
                          "form": "harmonic", "m2l_ms": float(ms_u), "pairs_per_s": pairs3 / (ms_u * 1e-3),
                          "dense_equivalent_tflops": fl3 / (ms_u * 1e-3) / 1e12,
                          "dense_m2l_ms": float(ms_ud), "dense_tflops": fl3 / (ms_ud * 1e-3) / 1e12,
-                         "dense_autotune_choice": chosen, "parity": par3}
+                         "dense_autotune_choice": chosen, "harmonic_vs_dense": dev3,
+                         "parity": "tests/test_gpu_fullsize.py::test_uneven_6000"}
         log("uneven 6000: harmonic %.3f ms (%.4g pairs/s), dense %.3f ms" % (ms_u, pairs3 / (ms_u * 1e-3), ms_ud))
         del pos3, mass3, M3, L3
+        torch.cuda.empty_cache()
+
+        # ---------------- the multi-level iteration on a 128^3 domain
+        out["tree"] = bench_tree(torch, fmm, ctx, K, W)
         torch.cuda.empty_cache()
 
         # ---------------- CPU baseline (the oracle on the host cores)

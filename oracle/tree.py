@@ -283,3 +283,100 @@ def direct_all(pos, mass):
         out[0, i0:i0 + 512] = np.sum(m[None, :] / r, axis=1)
         out[1:, i0:i0 + 512] = -np.einsum("ij,ijk->ki", m[None, :] / r ** 3, dy)
     return out
+
+
+# ---------------------------------------------------------------------------
+# one finest cell at a time (for sampled checks of large domains)
+# ---------------------------------------------------------------------------
+
+def shift_local(Lv, p, s, absolute=False):
+    """A local polynomial (coefficients Lv [C]) re-expanded about a point moved by
+    s: L'_n = sum_{m >= n} L_m s^(m-n) / (m-n)! (exact for degree p)."""
+    out = np.zeros_like(np.asarray(Lv, np.float64))
+    if absolute:
+        Lv, s = np.abs(Lv), tuple(abs(v) for v in s)
+    for im, in_, r in _shift_terms(p):
+        out[in_] += Lv[im] * _pow_fact(s, r)
+    return out
+
+
+def local_at(pos, mass, p, n, h, t, absolute=False):
+    """The finest-level total local expansion of cell t = (x, y, z), from the
+    definitions directly: on every level l, the interaction-list sum of the
+    ancestor A = t >> l, with each source cell's moments taken about its centre
+    from all the particles it contains (what P2M and M2M give, exactly), then
+    the polynomial moved from A's centre to t's (what the chain of L2L gives,
+    exactly). absolute: the same sums over absolute values."""
+    levels = tree_levels(n)
+    J = len(levels) - 1
+    ppc = np.asarray(mass).shape[-1]
+    P = np.asarray(pos, np.float64).reshape(n, n, n, ppc, 3)
+    W = np.asarray(mass, np.float64).reshape(n, n, n, ppc)
+    t = np.asarray(t)
+    C = ncomp(p)
+    total = np.zeros(C)
+    for lvl, nl in enumerate(levels):
+        w = 2 ** lvl
+        hl = h * w
+        A = t >> lvl
+        offs = top_list() if lvl == J else interaction_list(tuple(int(v) for v in A & 1))
+        Ts = stencil_tensors(p, hl, offs)
+        if absolute:
+            Ts = np.abs(Ts)
+        Lv = np.zeros(C)
+        for d, Td in zip(offs, Ts):
+            s = A + np.array(d)
+            if np.any(s < 0) or np.any(s >= nl):
+                continue
+            blk = (slice(s[2] * w, (s[2] + 1) * w), slice(s[1] * w, (s[1] + 1) * w), slice(s[0] * w, (s[0] + 1) * w))
+            a = P[blk].reshape(-1, 3) - (s + 0.5) * hl
+            m = W[blk].reshape(-1)
+            if absolute:
+                a, m = np.abs(a), np.abs(m)
+            Lv += Td.T @ (_monomials(a, p) @ m)
+        total += shift_local(Lv, p, tuple((t + 0.5) * h - (A + 0.5) * hl), absolute)
+    return total
+
+
+def evaluate_at(pos, mass, p, n, h, t, absolute=False):
+    """Potential and gradient at the particles of finest cell t: L2P of local_at
+    plus the near field over the cells t + d, |d|^2 <= 4, inside the domain
+    (particle itself excluded); [4, ppc]. absolute: the rounding scales."""
+    ppc = np.asarray(mass).shape[-1]
+    P = np.asarray(pos, np.float64).reshape(n, n, n, ppc, 3)
+    W = np.asarray(mass, np.float64).reshape(n, n, n, ppc)
+    t = np.asarray(t)
+    ks = multi_indices(p)
+    Lv = local_at(pos, mass, p, n, h, t, absolute)
+    b = P[t[2], t[1], t[0]] - (t + 0.5) * h                  # [ppc, 3]
+    if absolute:
+        b = np.abs(b)
+    mono = _monomials(b, p)
+    out = np.zeros((4, ppc))
+    out[0] = Lv @ mono
+    for ax in range(3):
+        for c_m, m in enumerate(ks):
+            if sum(m) > p - 1:
+                continue
+            e = [0, 0, 0]
+            e[ax] = 1
+            out[1 + ax] += Lv[ks.index((m[0] + e[0], m[1] + e[1], m[2] + e[2]))] * mono[c_m]
+    y = P[t[2], t[1], t[0]]
+    for d in near_stencil():
+        s = t + np.array(d)
+        if np.any(s < 0) or np.any(s >= n):
+            continue
+        ys, ms = P[s[2], s[1], s[0]], W[s[2], s[1], s[0]]
+        dy = y[:, None, :] - ys[None, :, :]
+        r = np.sqrt(np.sum(dy * dy, axis=-1))
+        mj = np.broadcast_to(ms[None, :], r.shape).copy()
+        if d == (0, 0, 0):
+            np.fill_diagonal(mj, 0.0)
+            np.fill_diagonal(r, 1.0)
+        if absolute:
+            out[0] += np.sum(mj / r, axis=1)
+            out[1:] += np.sum(mj / r ** 2, axis=1)[None]
+        else:
+            out[0] += np.sum(mj / r, axis=1)
+            out[1:] -= np.einsum("ij,ijk->ki", mj / r ** 3, dy)
+    return out

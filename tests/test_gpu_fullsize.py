@@ -122,6 +122,33 @@ def test_uniform_4096_evaluate(ctx, torch):
         assert np.all(err <= TOL * scale), (b, float(np.max(err / scale)))
 
 
+def test_tree_128_solve(ctx, torch):
+    # the multi-level iteration on a 128^3 domain (16.8M particles, p = 3), as
+    # timed: two solves bitwise equal, finite, positive potential; two cells (a
+    # corner and an interior one) against the oracle's per-cell route
+    import oracle.tree as T
+    n, ppc, p = 128, 8, 3
+    tree = fmm.Tree(p, n, ppc, 0)
+    _, elems = fmm.tree_size(tree)
+    pos_h, mass_h = synth.grid_particles(40, n, 1.0, ppc)
+    pos, mass = torch.from_numpy(pos_h).to("cuda"), torch.from_numpy(mass_h).to("cuda")
+    M = torch.empty(elems, dtype=torch.float64, device="cuda")
+    L = torch.empty(elems, dtype=torch.float64, device="cuda")
+    out = torch.empty(4 * n ** 3 * ppc, dtype=torch.float64, device="cuda")
+    out2 = torch.empty_like(out)
+    ctx.tree_solve(tree, pos, mass, M, L, out)
+    ctx.tree_solve(tree, pos, mass, M, L, out2)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all() and torch.equal(out, out2)
+    E = out.view(4, n, n, n, ppc)
+    assert (E[0] > 0).all()
+    for t in [(0, 0, 0), (77, 31, 100)]:
+        want = T.evaluate_at(pos_h, mass_h, p, n, 1.0, t)
+        scale = T.evaluate_at(pos_h, mass_h, p, n, 1.0, t, absolute=True)
+        got = E[:, t[2], t[1], t[0]].cpu().numpy()
+        assert np.all(np.abs(got - want) <= TOL * scale), (t, float(np.max(np.abs(got - want) / scale)))
+
+
 def test_uneven_6000(ctx, torch):
     w = synth.config(3)
     desc, m_el, l_el = fmm.make_descriptors(w.p, w.log2_inv_h, w.mask)

@@ -146,3 +146,17 @@ def test_coarsest_level_lists_agree_and_scales_bound_values():
     assert all(np.all(np.abs(x) <= y * (1 + 1e-12)) for x, y in zip(Ls, La))
     Lt, Lta = T.downward(Ls, 3, 1.0), T.downward(La, 3, 1.0, absolute=True)
     assert all(np.all(np.abs(x) <= y * (1 + 1e-12)) for x, y in zip(Lt, Lta))
+
+
+def test_one_cell_path_matches_the_whole_iteration():
+    # the per-cell route (direct moments of each source cell, direct shift to the
+    # target) against the level-by-level iteration, at cells of every kind
+    n, h, ppc, p = 16, 0.5, 2, 3
+    pos, mass = synth.grid_particles(6, n, h, ppc)
+    E = T.solve(pos, mass, p, n, h).reshape(4, n, n, n, ppc)
+    Lt = T.downward(T.m2l_levels(T.upward(pos, mass, p, n, h), p, h), p, h)[0]
+    for t in [(0, 0, 0), (7, 8, 9), (15, 3, 12), (5, 15, 15)]:
+        lv, la = T.local_at(pos, mass, p, n, h, t), T.local_at(pos, mass, p, n, h, t, absolute=True)
+        assert np.all(np.abs(lv - Lt[:, t[2], t[1], t[0]]) <= 1e-12 * la)
+        ev, ea = T.evaluate_at(pos, mass, p, n, h, t), T.evaluate_at(pos, mass, p, n, h, t, absolute=True)
+        assert np.all(np.abs(ev - E[:, t[2], t[1], t[0]]) <= 1e-12 * ea)
