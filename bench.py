@@ -175,7 +175,8 @@ def bench_tree(torch, fmm, ctx, K, W):
     """Multi-level solve (P2M, M2M, interaction-list M2L on every level, L2L,
     near field + L2P) on a 128^3 domain with 8 particles per cell, p = 3."""
     n, ppc, p = 128, 8, 3
-    tree = fmm.Tree(p, n, ppc, 0)
+    tree = fmm.Tree(p, n, ppc, 0, 1)      # harmonic form of the level M2L
+    dense = fmm.Tree(p, n, ppc, 0, 0)
     _, elems = fmm.tree_size(tree)
     t0 = time.time()
     pos_h, mass_h = synth.grid_particles(40, n, 1.0, ppc)
@@ -198,22 +199,36 @@ def bench_tree(torch, fmm, ctx, K, W):
 
     wall, seg = timed(torch, step_tree, K, W, marks=4)
     up, m2l, down, ev = (float(seg[:, i].mean()) for i in range(4))
+    Ld = torch.empty_like(L)
+
+    def step_dense(ev_, i):
+        if ev_: ev_[0].record()
+        ctx.tree_m2l(dense, M, Ld)
+        if ev_: ev_[1].record()
+
+    _, seg_d = timed(torch, step_dense, K, W, marks=1)
+    m2l_dense = float(seg_d[:, 0].mean())
+    del Ld
     pairs, slots = tree_pairs(n)
-    fl = slots * flops_per_pair(p)
+    fl = slots * harmonic_flops_per_pair(p)
+    fl_dense = slots * flops_per_pair(p)
     assert bool(torch.isfinite(E).all())
     nparts = n ** 3 * ppc
     ms = wall / K * 1e3
     res = {"workload": "tree_128_p3", "domain_cells": n ** 3, "levels": 6, "particles": nparts,
            "solve_ms": ms, "particles_per_s": nparts / (ms * 1e-3),
            "upward_ms": up, "m2l_ms": m2l, "downward_ms": down, "evaluate_ms": ev,
-           "m2l_pairs": pairs, "m2l_pairs_per_s": pairs / (m2l * 1e-3),
-           "roofline_m2l": {"bound": "mfma", "kernel": "m2l_level_kernel<3> (v_mfma_f64_4x4x4, all levels)",
+           "m2l_pairs": pairs, "m2l_pairs_per_s": pairs / (m2l * 1e-3), "m2l_form": "harmonic",
+           "m2l_dense_ms": m2l_dense, "m2l_dense_tflops": fl_dense / (m2l_dense * 1e-3) / 1e12,
+           "roofline_m2l": {"bound": "mfma", "kernel": "m2l_level_kernel<3, true> (v_mfma_f64_4x4x4, harmonic form, all levels)",
                             "achieved": fl / (m2l * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                             "frac": fl / (m2l * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
-                            "executed_flops": fl, "useful_flops": pairs * flops_per_pair(p)},
+                            "executed_flops": fl, "flops_per_slot": harmonic_flops_per_pair(p),
+                            "fp64_dense_equivalent_tflops": fl_dense / (m2l * 1e-3) / 1e12,
+                            "useful_slot_fraction": pairs / slots},
            "parity": "tests/test_gpu_tree.py, tests/test_gpu_fullsize.py::test_tree_128_solve"}
-    log("tree 128^3: solve %.3f ms (upward %.3f, M2L %.3f, downward %.3f, evaluate %.3f), M2L %.1f TFLOP/s executed"
-        % (ms, up, m2l, down, ev, fl / (m2l * 1e-3) / 1e12))
+    log("tree 128^3: solve %.3f ms (upward %.3f, M2L %.3f, downward %.3f, evaluate %.3f), M2L %.1f TFLOP/s executed;"
+        " dense-form M2L %.3f ms" % (ms, up, m2l, down, ev, fl / (m2l * 1e-3) / 1e12, m2l_dense))
     del pos, mass, M, L, E
     return res
 

@@ -199,6 +199,8 @@ typedef struct {
     int32_t n;        /* finest cells per axis: 8, 16, 32, 64 or 128 */
     int32_t ppc;      /* particles per finest cell, 1..64 */
     int32_t log2_h;   /* finest spacing h = 2^log2_h, -4 <= log2_h <= 4 */
+    int32_t harmonic; /* M2L form: 0 dense C x C, 1 harmonic (as FMM_FP64_HARMONIC: equal up
+                         to rounding, (p+1)^2 folded components) */
 } fmm_tree;
 
 /* Host query: number of levels (J + 1) and the float64 elements of one M or

@@ -505,6 +505,7 @@ static fmm_status check_tree(fmm_ctx* ctx, const fmm_tree* t) {
     return set_err(ctx, FMM_EINVAL, "tree.n must be 8, 16, 32, 64 or 128");
   if (t->ppc < 1 || t->ppc > 64) return set_err(ctx, FMM_EINVAL, "tree.ppc not in [1, 64]");
   if (t->log2_h < -4 || t->log2_h > 4) return set_err(ctx, FMM_EINVAL, "tree.log2_h not in [-4, 4]");
+  if (t->harmonic != 0 && t->harmonic != 1) return set_err(ctx, FMM_EINVAL, "tree.harmonic not 0/1");
   return FMM_OK;
 }
 
@@ -554,8 +555,8 @@ static fmm_status tree_upward(fmm_ctx* ctx, const fmm_tree* t, const double* pos
 static fmm_status tree_m2l(fmm_ctx* ctx, const fmm_tree* t, const double* M, double* L, hipStream_t s) {
   const int nl = tree_nlevels(t->n);
   for (int l = 0, m = t->n; l < nl; ++l, m /= 2)
-    HIP_TRY(ctx, launch_tree_m2l(t->p, ctx->tree, M + tree_level_off(t, l), L + tree_level_off(t, l), m,
-                                 t->log2_h + l, s));
+    HIP_TRY(ctx, launch_tree_m2l(t->p, ctx->tree, ctx->mfma, t->harmonic != 0, M + tree_level_off(t, l),
+                                 L + tree_level_off(t, l), m, t->log2_h + l, s));
   return FMM_OK;
 }
 

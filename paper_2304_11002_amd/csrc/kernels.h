@@ -31,8 +31,10 @@ hipError_t launch_evaluate_grid(int p, int n, double h, const double* pos, const
                                 int ppc, const double* L, double* out, hipStream_t s);
 
 // tree.hip: the multi-level iteration on a uniform octree (level arrays [C][n^3])
+struct MfmaTables;
 struct TreeTables {
   double* B[kMaxP + 1] = {};   // per order: interaction-list tables in consumption order
+  double* Bh[kMaxP + 1] = {};  // the same for the harmonic form
   int* doff = nullptr;         // [8 parities][58 quads][4] window offsets of the lists
 };
 hipError_t tree_tables_create(TreeTables* tt, const double* const* d_T, const int* stencil_xyz,
@@ -42,8 +44,8 @@ hipError_t launch_tree_p2m(int p, const double* pos, const double* mass, int ppc
                            double* M, hipStream_t s);
 hipError_t launch_tree_m2m(int p, const double* Mc, double* Mp, int nc, double hc, hipStream_t s);
 hipError_t launch_tree_l2l(int p, const double* Lp, double* Lc, int nc, double hc, hipStream_t s);
-hipError_t launch_tree_m2l(int p, const TreeTables& tt, const double* M, double* L, int n, int lg,
-                           hipStream_t s);
+hipError_t launch_tree_m2l(int p, const TreeTables& tt, const MfmaTables& mt, bool harmonic,
+                           const double* M, double* L, int n, int lg, hipStream_t s);
 
 // m2l_ref.hip: sub-grids listed in d_ids (all of order p)
 hipError_t launch_m2l_ref(int p, bool backward, const DevDesc* d_desc, const int* d_ids, int count,

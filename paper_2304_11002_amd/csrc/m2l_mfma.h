@@ -99,6 +99,11 @@ struct MfmaTables {
 
 hipError_t mfma_tables_create(MfmaTables* t, double* const* d_T, const int* d_stencil,
                               hipStream_t s);
+// The harmonic form's plan for order p: full index (in I_p) of each round's two
+// folded rows (rowk[2r], rowk[2r+1]; -1 if absent) and of each harmonic column
+// (colk, -1 past (p+1)^2), and the number of rounds. The device copies of the
+// rounds' fold plans and of L's expansion are MfmaTables::hround / hexp.
+bool harmonic_plan_maps(int p, int32_t rowk[32], int32_t colk[32], int* nrounds);
 void mfma_tables_destroy(MfmaTables* t);
 
 int mfma_num_configs();

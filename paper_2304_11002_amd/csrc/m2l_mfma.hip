@@ -1481,6 +1481,17 @@ bool build_harmonic(int p, HostHarmonic* out) {
 
 }  // namespace
 
+bool harmonic_plan_maps(int p, int32_t rowk[32], int32_t colk[32], int* nrounds) {
+  HostHarmonic hh;
+  if (!build_harmonic(p, &hh)) return false;
+  for (int i = 0; i < 32; ++i) {
+    rowk[i] = hh.maps.rowk[i];
+    colk[i] = hh.maps.colk[i];
+  }
+  *nrounds = (int)hh.rounds.size();
+  return true;
+}
+
 hipError_t mfma_tables_create(MfmaTables* t, double* const* d_T, const int* d_stencil,
                               hipStream_t s) {
   hipError_t e;

@@ -24,10 +24,14 @@
 // one offset list and one table stream: v_mfma_f64_4x4x4_4b over
 // [16 cells x 4 offsets] x [4 offsets x 4 columns] as in the single-level
 // kernels, with the 18^3 source window of two moment components per round in
-// LDS.
+// LDS. The harmonic form (as FMM_FP64_HARMONIC: T_d is harmonic in both
+// indices, so the moments fold onto the (p+1)^2 components with kz <= 1 and
+// only those columns of L are computed, then expanded) uses the single-level
+// form's fold plan per round and expansion of L.
 #include <vector>
 
 #include "kernels.h"
+#include "m2l_mfma.h"
 
 namespace fmm {
 
@@ -178,14 +182,43 @@ __global__ void pack_tree_kernel(const double* __restrict__ T, int C, const int*
   }
 }
 
-template <int P>
+// Harmonic tables: Bh[sigma][round][quad][c2][group][kk * 4 + j] =
+// T_d[rowk[2 round + c2]][colk[4 group + j]] (zero where a map is -1).
+struct TreeHMaps {
+  int rowk[32];
+  int colk[32];
+};
+__global__ void pack_tree_h_kernel(const double* __restrict__ T, int C, int R, int NG,
+                                   const int* __restrict__ sidx, TreeHMaps mp, double* __restrict__ B) {
+  const int64_t total = (int64_t)8 * R * kTreeQuads * 2 * NG * 16;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r_ = e;
+    const int v = (int)(r_ % 16); r_ /= 16;
+    const int g = (int)(r_ % NG); r_ /= NG;
+    const int c2 = (int)(r_ % 2); r_ /= 2;
+    const int q = (int)(r_ % kTreeQuads); r_ /= kTreeQuads;
+    const int r = (int)(r_ % R);
+    const int sigma = (int)(r_ / R);
+    const int kk = v >> 2, j = v & 3;
+    const int k = mp.rowk[2 * r + c2], nn = 4 * g + j < 32 ? mp.colk[4 * g + j] : -1;
+    const int s = sidx[(sigma * kTreeQuads + q) * 4 + kk];
+    B[e] = (s >= 0 && k >= 0 && nn >= 0) ? T[((int64_t)s * C + k) * C + nn] : 0.0;
+  }
+}
+
+template <int P, bool HARM>
 __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
     const double* __restrict__ M, double* __restrict__ L, int n, int lg,
-    const double* __restrict__ B, const int* __restrict__ doff) {
+    const double* __restrict__ B, const int* __restrict__ doff, const HRound* __restrict__ hround,
+    const HExp* __restrict__ hexp) {
   constexpr int C = ncomp(P);
-  constexpr int NG = (C + 3) / 4;
-  constexpr int ROUNDS = (C + 1) / 2;
-  __shared__ double2 smem[kTreeWCells];
+  constexpr int CR = HARM ? (P + 1) * (P + 1) : C;   // contracted components (rows and columns)
+  constexpr int NG = (CR + 3) / 4;
+  constexpr int ROUNDS = (CR + 1) / 2;
+  // the window, and afterwards (harmonic form) the harmonic columns of the block
+  constexpr int SMEM = HARM && kNTarget * CR / 2 > kTreeWCells ? kNTarget * CR / 2 : kTreeWCells;
+  __shared__ double2 smem[SMEM];
   __shared__ int s_doff[8 * kTreeQuads * 4];
   const int nb = n >= 8 ? n / 8 : 1;
   const int blk = blockIdx.x;
@@ -211,24 +244,51 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
     for (int g = 0; g < NG; ++g) acc[t][g] = 0.0;
 
   const int* dq = s_doff + wave * kTreeQuads * 4 + kk;
+  // this thread's window cells: global index, or -1 outside the domain
+  int64_t wg[kTreeStage];
+#pragma unroll
+  for (int i = 0; i < kTreeStage; ++i) {
+    const int c = tid + i * kTreeThreads;
+    const int gx = B0x - 5 + c % kTreeW, gy = B0y - 5 + (c / kTreeW) % kTreeW,
+              gz = B0z - 5 + c / (kTreeW * kTreeW);
+    wg[i] = (c < kTreeWCells && gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n)
+                ? gx + (int64_t)n * gy + (int64_t)n * n * gz
+                : -1;
+  }
   for (int r = 0; r < ROUNDS; ++r) {
-    const int k0 = 2 * r, k1 = 2 * r + 1;
-    const double s0 = ldexp(1.0, -lg * order_of(k0));
-    const double s1 = k1 < C ? ldexp(1.0, -lg * order_of(k1)) : 0.0;
-    const double* src0 = M + (int64_t)k0 * n3;
-    const double* src1 = M + (int64_t)(k1 < C ? k1 : k0) * n3;
+    double s0, s1;
     double2 v[kTreeStage];
 #pragma unroll
-    for (int i = 0; i < kTreeStage; ++i) {
-      const int c = tid + i * kTreeThreads;
-      v[i] = make_double2(0.0, 0.0);
-      if (c < kTreeWCells) {
-        const int gx = B0x - 5 + c % kTreeW, gy = B0y - 5 + (c / kTreeW) % kTreeW,
-                  gz = B0z - 5 + c / (kTreeW * kTreeW);
-        if (gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n) {
-          const int64_t g = gx + (int64_t)n * gy + (int64_t)n * n * gz;
-          v[i].x = src0[g];
-          v[i].y = src1[g];
+    for (int i = 0; i < kTreeStage; ++i) v[i] = make_double2(0.0, 0.0);
+    if (HARM) {
+      // the round's two folded components, each an integer combination of moment
+      // components of one order
+      const HRound& rd = hround[r];
+      s0 = ldexp(1.0, -lg * rd.ord0);
+      s1 = rd.ord1 >= 0 ? ldexp(1.0, -lg * rd.ord1) : 0.0;
+      for (int u = 0; u < rd.nsup; ++u) {
+        const double* src = M + (int64_t)rd.comp[u] * n3;
+        const double a0 = rd.c0[u], a1 = rd.c1[u];
+#pragma unroll
+        for (int i = 0; i < kTreeStage; ++i) {
+          if (wg[i] >= 0) {
+            const double m = src[wg[i]];
+            v[i].x = __builtin_fma(a0, m, v[i].x);
+            v[i].y = __builtin_fma(a1, m, v[i].y);
+          }
+        }
+      }
+    } else {
+      const int k0 = 2 * r, k1 = 2 * r + 1;
+      s0 = ldexp(1.0, -lg * order_of(k0));
+      s1 = k1 < C ? ldexp(1.0, -lg * order_of(k1)) : 0.0;
+      const double* src0 = M + (int64_t)k0 * n3;
+      const double* src1 = M + (int64_t)(k1 < C ? k1 : k0) * n3;
+#pragma unroll
+      for (int i = 0; i < kTreeStage; ++i) {
+        if (wg[i] >= 0) {
+          v[i].x = src0[wg[i]];
+          v[i].y = src1[wg[i]];
         }
       }
     }
@@ -277,15 +337,50 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
 
   // D layout: this lane holds cell (2 xi + sx, 2 yi + sy) of each tile, column j
   const int xi = lane >> 4, yi = (lane & 15) >> 2, j = lane & 3;
+  if (!HARM) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int gx = B0x + 2 * xi + sx, gy = B0y + 2 * yi + sy, gz = B0z + 2 * t + sz;
+      if (gx >= n || gy >= n || gz >= n) continue;
+      const int64_t g = gx + (int64_t)n * gy + (int64_t)n * n * gz;
+#pragma unroll
+      for (int gg = 0; gg < NG; ++gg) {
+        const int nn = 4 * gg + j;
+        if (nn < C) L[nn * n3 + g] = ldexp(acc[t][gg], -lg * (1 + order_of(nn)));
+      }
+    }
+    return;
+  }
+  // harmonic columns (column c has order floor(sqrt(c))) through LDS, then each
+  // thread expands one target cell to all C components
+  __syncthreads();                                  // the window is no longer read
+  double* sh = reinterpret_cast<double*>(smem);     // [512 cells][CR]
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int gx = B0x + 2 * xi + sx, gy = B0y + 2 * yi + sy, gz = B0z + 2 * t + sz;
-    if (gx >= n || gy >= n || gz >= n) continue;
-    const int64_t g = gx + (int64_t)n * gy + (int64_t)n * n * gz;
+    const int cell = (2 * xi + sx) + 8 * (2 * yi + sy) + 64 * (2 * t + sz);
 #pragma unroll
     for (int gg = 0; gg < NG; ++gg) {
-      const int nn = 4 * gg + j;
-      if (nn < C) L[nn * n3 + g] = ldexp(acc[t][gg], -lg * (1 + order_of(nn)));
+      const int c = 4 * gg + j;
+      if (c < CR) {
+        int ord = 0;
+        while ((ord + 1) * (ord + 1) <= c) ++ord;
+        sh[cell * CR + c] = ldexp(acc[t][gg], -lg * (1 + ord));
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const int cell = tid;                           // 512 threads, 512 cells
+    const int gx = B0x + (cell & 7), gy = B0y + ((cell >> 3) & 7), gz = B0z + (cell >> 6);
+    if (gx < n && gy < n && gz < n) {
+      const int64_t g = gx + (int64_t)n * gy + (int64_t)n * n * gz;
+      const double* lh = sh + cell * CR;
+      for (int nn = 0; nn < C; ++nn) {
+        const HExp& ex = hexp[nn];
+        double v = 0.0;
+        for (int u = 0; u < ex.nterm; ++u) v = __builtin_fma(ex.coef[u], lh[ex.col[u]], v);
+        L[nn * n3 + g] = v;
+      }
     }
   }
 }
@@ -352,6 +447,18 @@ hipError_t tree_tables_create(TreeTables* tt, const double* const* d_T, const in
     if ((e = hipMalloc(&tt->B[p], sizeof(double) * count)) != hipSuccess) break;
     hipLaunchKernelGGL(pack_tree_kernel, dim3(1024), dim3(256), 0, s, d_T[p], C, d_sidx, tt->B[p]);
     if ((e = hipGetLastError()) != hipSuccess) break;
+    TreeHMaps mp;
+    int rh = 0;
+    if (!harmonic_plan_maps(p, mp.rowk, mp.colk, &rh) || rh != ((p + 1) * (p + 1) + 1) / 2) {
+      e = hipErrorInvalidValue;
+      break;
+    }
+    const int CRh = (p + 1) * (p + 1), NGh = (CRh + 3) / 4;
+    const size_t counth = (size_t)8 * rh * kTreeQuads * 2 * NGh * 16;
+    if ((e = hipMalloc(&tt->Bh[p], sizeof(double) * counth)) != hipSuccess) break;
+    hipLaunchKernelGGL(pack_tree_h_kernel, dim3(1024), dim3(256), 0, s, d_T[p], C, rh, NGh, d_sidx, mp,
+                       tt->Bh[p]);
+    if ((e = hipGetLastError()) != hipSuccess) break;
   }
   hipError_t e2 = hipStreamSynchronize(s);
   (void)hipFree(d_sidx);
@@ -359,8 +466,10 @@ hipError_t tree_tables_create(TreeTables* tt, const double* const* d_T, const in
 }
 
 void tree_tables_destroy(TreeTables* tt) {
-  for (int p = 0; p <= kMaxP; ++p)
+  for (int p = 0; p <= kMaxP; ++p) {
     if (tt->B[p]) (void)hipFree(tt->B[p]);
+    if (tt->Bh[p]) (void)hipFree(tt->Bh[p]);
+  }
   if (tt->doff) (void)hipFree(tt->doff);
   *tt = TreeTables{};
 }
@@ -402,16 +511,23 @@ hipError_t launch_tree_l2l(int p, const double* Lp, double* Lc, int nc, double h
   return hipGetLastError();
 }
 
-hipError_t launch_tree_m2l(int p, const TreeTables& tt, const double* M, double* L, int n, int lg,
-                           hipStream_t s) {
+hipError_t launch_tree_m2l(int p, const TreeTables& tt, const MfmaTables& mt, bool harmonic,
+                           const double* M, double* L, int n, int lg, hipStream_t s) {
   const int nb = n >= 8 ? n / 8 : 1;
   const dim3 grid((unsigned)(nb * nb * nb)), block(kTreeThreads);
-  switch (p) {
-    case 2: hipLaunchKernelGGL(m2l_level_kernel<2>, grid, block, 0, s, M, L, n, lg, tt.B[2], tt.doff); break;
-    case 3: hipLaunchKernelGGL(m2l_level_kernel<3>, grid, block, 0, s, M, L, n, lg, tt.B[3], tt.doff); break;
-    case 4: hipLaunchKernelGGL(m2l_level_kernel<4>, grid, block, 0, s, M, L, n, lg, tt.B[4], tt.doff); break;
+#define TREE_LAUNCH(P, H)                                                                           \
+  hipLaunchKernelGGL((m2l_level_kernel<P, H>), grid, block, 0, s, M, L, n, lg, H ? tt.Bh[P] : tt.B[P], \
+                     tt.doff, mt.hround[P], mt.hexp[P])
+  switch (p * 2 + (harmonic ? 1 : 0)) {
+    case 4: TREE_LAUNCH(2, false); break;
+    case 5: TREE_LAUNCH(2, true); break;
+    case 6: TREE_LAUNCH(3, false); break;
+    case 7: TREE_LAUNCH(3, true); break;
+    case 8: TREE_LAUNCH(4, false); break;
+    case 9: TREE_LAUNCH(4, true); break;
     default: return hipErrorInvalidValue;
   }
+#undef TREE_LAUNCH
   return hipGetLastError();
 }
 

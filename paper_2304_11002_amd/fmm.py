@@ -34,9 +34,9 @@ assert DESC_DTYPE.itemsize == 40
 
 class Tree(ctypes.Structure):
     """fmm_tree: a uniform n^3 domain of finest spacing 2^log2_h, order p, ppc
-    particles per finest cell."""
+    particles per finest cell; harmonic = 1 selects the harmonic form of M2L."""
     _fields_ = [("p", ctypes.c_int32), ("n", ctypes.c_int32), ("ppc", ctypes.c_int32),
-                ("log2_h", ctypes.c_int32)]
+                ("log2_h", ctypes.c_int32), ("harmonic", ctypes.c_int32)]
 
 
 class FMMError(RuntimeError):

@@ -165,7 +165,7 @@ def test_tree_argument_checks(hctx, lib):
     assert fmm.tree_size(fmm.Tree(2, 128, 1, -4)) == (6, 10 * sum(m ** 3 for m in (128, 64, 32, 16, 8, 4)))
     for bad in (fmm.Tree(1, 16, 8, 0), fmm.Tree(5, 16, 8, 0), fmm.Tree(3, 12, 8, 0), fmm.Tree(3, 4, 8, 0),
                 fmm.Tree(3, 256, 8, 0), fmm.Tree(3, 16, 0, 0), fmm.Tree(3, 16, 65, 0), fmm.Tree(3, 16, 8, 5),
-                fmm.Tree(3, 16, 8, -5)):
+                fmm.Tree(3, 16, 8, -5), fmm.Tree(3, 16, 8, 0, 2)):
         with pytest.raises(fmm.FMMError) as e:
             fmm.tree_size(bad)
         assert e.value.status == fmm.FMM_EINVAL

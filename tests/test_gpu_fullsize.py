@@ -128,7 +128,7 @@ def test_tree_128_solve(ctx, torch):
     # corner and an interior one) against the oracle's per-cell route
     import oracle.tree as T
     n, ppc, p = 128, 8, 3
-    tree = fmm.Tree(p, n, ppc, 0)
+    tree = fmm.Tree(p, n, ppc, 0, 1)         # the harmonic form of the level M2L, as timed
     _, elems = fmm.tree_size(tree)
     pos_h, mass_h = synth.grid_particles(40, n, 1.0, ppc)
     pos, mass = torch.from_numpy(pos_h).to("cuda"), torch.from_numpy(mass_h).to("cuda")

@@ -74,13 +74,15 @@ def test_tree_steps_match_oracle(ctx, torch, p, n, ppc, lh):
     Mo, Ma = T.upward(pos, mass, p, n, h), T.upward(pos, mass, p, n, h, absolute=True)
     for lvl, (g, w, s) in enumerate(zip(split_levels(M.cpu().numpy(), p, n), Mo, Ma)):
         check(g, w, s, "M level %d" % lvl)
-    # every level's M2L, on the oracle's moments
-    L = torch.full((elems,), float("nan"), dtype=torch.float64, device="cuda")
-    ctx.tree_m2l(tree, to_dev(flatten(Mo)), L)
-    torch.cuda.synchronize()
+    # every level's M2L, on the oracle's moments, in the dense and the harmonic form
     Lo, La = T.m2l_levels(Mo, p, h), T.m2l_levels(Mo, p, h, absolute=True)
-    for lvl, (g, w, s) in enumerate(zip(split_levels(L.cpu().numpy(), p, n), Lo, La)):
-        check(g, w, s, "L level %d" % lvl)
+    for harmonic in (0, 1):
+        th = fmm.Tree(p, n, ppc, lh, harmonic)
+        L = torch.full((elems,), float("nan"), dtype=torch.float64, device="cuda")
+        ctx.tree_m2l(th, to_dev(flatten(Mo)), L)
+        torch.cuda.synchronize()
+        for lvl, (g, w, s) in enumerate(zip(split_levels(L.cpu().numpy(), p, n), Lo, La)):
+            check(g, w, s, "L level %d (harmonic %d)" % (lvl, harmonic))
     # downward, on the oracle's per-level expansions
     Ld = to_dev(flatten(Lo))
     ctx.tree_downward(tree, Ld)
@@ -97,10 +99,11 @@ def test_tree_steps_match_oracle(ctx, torch, p, n, ppc, lh):
     check(out.cpu().numpy().reshape(4, n ** 3, ppc), want, scale, "evaluation")
 
 
-@pytest.mark.parametrize("p,n,ppc,lh", [(3, 16, 2, 0), (4, 16, 1, -2)])
-def test_tree_solve_matches_oracle_and_the_steps(ctx, torch, p, n, ppc, lh):
+@pytest.mark.parametrize("p,n,ppc,lh,harmonic", [(3, 16, 2, 0, 0), (4, 16, 1, -2, 0), (3, 16, 2, 0, 1),
+                                                   (4, 16, 1, -2, 1), (2, 32, 1, 1, 1)])
+def test_tree_solve_matches_oracle_and_the_steps(ctx, torch, p, n, ppc, lh, harmonic):
     h = 2.0 ** lh
-    tree = fmm.Tree(p, n, ppc, lh)
+    tree = fmm.Tree(p, n, ppc, lh, harmonic)
     _, elems = fmm.tree_size(tree)
     pos, mass = synth.grid_particles(20 + p, n, h, ppc)
     dpos, dmass = to_dev(pos), to_dev(mass)
