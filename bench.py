@@ -303,6 +303,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="oracle seconds per host core for cpu_baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the step (for profiling)")
+    ap.add_argument("--tree-only", action="store_true",
+                    help="only the multi-level solve on 128^3 (for profiling)")
     ap.add_argument("--evaluate-only", action="store_true",
                     help="only the step and the evaluation at the particles (for profiling)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
@@ -330,6 +332,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ctx = fmm.Context(0)
     K, W = args.steps, args.warmup
+    if args.tree_only:
+        print(json.dumps({"tree": bench_tree(torch, fmm, ctx, K, W)}), flush=True)
+        ctx.close()
+        return
     out = {"metric": METRIC, "unit": "pairs/s", "n_gpus": 1, "steps": K, "warmup": W,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic"}

@@ -554,9 +554,14 @@ static fmm_status tree_upward(fmm_ctx* ctx, const fmm_tree* t, const double* pos
 
 static fmm_status tree_m2l(fmm_ctx* ctx, const fmm_tree* t, const double* M, double* L, hipStream_t s) {
   const int nl = tree_nlevels(t->n);
-  for (int l = 0, m = t->n; l < nl; ++l, m /= 2)
-    HIP_TRY(ctx, launch_tree_m2l(t->p, ctx->tree, ctx->mfma, t->harmonic != 0, M + tree_level_off(t, l),
-                                 L + tree_level_off(t, l), m, t->log2_h + l, s));
+  int n[8], lg[8];
+  int64_t off[8];
+  for (int l = 0, m = t->n; l < nl; ++l, m /= 2) {
+    n[l] = m;
+    lg[l] = t->log2_h + l;
+    off[l] = tree_level_off(t, l);
+  }
+  HIP_TRY(ctx, launch_tree_m2l(t->p, ctx->tree, ctx->mfma, t->harmonic != 0, M, L, nl, n, lg, off, s));
   return FMM_OK;
 }
 

@@ -44,8 +44,11 @@ hipError_t launch_tree_p2m(int p, const double* pos, const double* mass, int ppc
                            double* M, hipStream_t s);
 hipError_t launch_tree_m2m(int p, const double* Mc, double* Mp, int nc, double hc, hipStream_t s);
 hipError_t launch_tree_l2l(int p, const double* Lp, double* Lc, int nc, double hc, hipStream_t s);
+// every level in one launch: level l has n[l] cells per axis, spacing 2^lg[l],
+// and sits at element offset off[l] of M and L
 hipError_t launch_tree_m2l(int p, const TreeTables& tt, const MfmaTables& mt, bool harmonic,
-                           const double* M, double* L, int n, int lg, hipStream_t s);
+                           const double* M, double* L, int nlev, const int* n, const int* lg,
+                           const int64_t* off, hipStream_t s);
 
 // m2l_ref.hip: sub-grids listed in d_ids (all of order p)
 hipError_t launch_m2l_ref(int p, bool backward, const DevDesc* d_desc, const int* d_ids, int count,

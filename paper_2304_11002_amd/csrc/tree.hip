@@ -43,6 +43,7 @@ constexpr int kTreeList = 231;                     // interaction-list length pe
 constexpr int kTreeQuads = (kTreeList + 3) / 4;    // 58 (the last quad has one empty slot)
 constexpr int kTreeThreads = 512;
 constexpr int kTreeStage = (kTreeWCells + kTreeThreads - 1) / kTreeThreads;
+constexpr int kTreeMaxLevels = 8;
 
 __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
@@ -207,9 +208,20 @@ __global__ void pack_tree_h_kernel(const double* __restrict__ T, int C, int R, i
   }
 }
 
+// Every level in one launch: the levels' blocks back to back, coarsest level
+// first, so the few long-running blocks of the small levels start at once and
+// overlap with the finest level's many blocks.
+struct TreeLevels {
+  int nlev;
+  int first[kTreeMaxLevels + 1];   // first block of each level in launch order, then the total
+  int n[kTreeMaxLevels];           // cells per axis
+  int lg[kTreeMaxLevels];          // log2 of the spacing
+  int64_t off[kTreeMaxLevels];     // element offset of the level in M and L
+};
+
 template <int P, bool HARM>
 __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
-    const double* __restrict__ M, double* __restrict__ L, int n, int lg,
+    const double* __restrict__ Mall, double* __restrict__ Lall, TreeLevels lv,
     const double* __restrict__ B, const int* __restrict__ doff, const HRound* __restrict__ hround,
     const HExp* __restrict__ hexp) {
   constexpr int C = ncomp(P);
@@ -220,8 +232,13 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
   constexpr int SMEM = HARM && kNTarget * CR / 2 > kTreeWCells ? kNTarget * CR / 2 : kTreeWCells;
   __shared__ double2 smem[SMEM];
   __shared__ int s_doff[8 * kTreeQuads * 4];
+  int li = 0;
+  while (li + 1 < lv.nlev && (int)blockIdx.x >= lv.first[li + 1]) ++li;
+  const int n = lv.n[li], lg = lv.lg[li];
+  const double* __restrict__ M = Mall + lv.off[li];
+  double* __restrict__ L = Lall + lv.off[li];
   const int nb = n >= 8 ? n / 8 : 1;
-  const int blk = blockIdx.x;
+  const int blk = (int)blockIdx.x - lv.first[li];
   const int B0x = 8 * (blk % nb), B0y = 8 * ((blk / nb) % nb), B0z = 8 * (blk / (nb * nb));
   const int64_t n3 = (int64_t)n * n * n;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -300,11 +317,14 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
     }
     __syncthreads();
     const double* Br = B + ((int64_t)(wave * ROUNDS + r) * kTreeQuads) * 2 * NG * 16 + kk * 4 + (lane & 3);
-    double nb0[NG], nb1[NG];
+    // table operands are loaded two quads ahead of their products
+    double nb0[NG], nb1[NG], mb0[NG], mb1[NG];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
       nb0[g] = Br[g * 16];
       nb1[g] = Br[(NG + g) * 16];
+      mb0[g] = Br[2 * NG * 16 + g * 16];
+      mb1[g] = Br[2 * NG * 16 + (NG + g) * 16];
     }
     for (int q = 0; q < kTreeQuads; ++q) {
       double b0[NG], b1[NG];
@@ -312,13 +332,15 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
       for (int g = 0; g < NG; ++g) {
         b0[g] = nb0[g];
         b1[g] = nb1[g];
+        nb0[g] = mb0[g];
+        nb1[g] = mb1[g];
       }
-      if (q + 1 < kTreeQuads) {
-        const double* Bn = Br + (int64_t)(q + 1) * 2 * NG * 16;
+      if (q + 2 < kTreeQuads) {
+        const double* Bn = Br + (int64_t)(q + 2) * 2 * NG * 16;
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-          nb0[g] = Bn[g * 16];
-          nb1[g] = Bn[(NG + g) * 16];
+          mb0[g] = Bn[g * 16];
+          mb1[g] = Bn[(NG + g) * 16];
         }
       }
       const int dl = dq[q * 4];
@@ -512,11 +534,25 @@ hipError_t launch_tree_l2l(int p, const double* Lp, double* Lc, int nc, double h
 }
 
 hipError_t launch_tree_m2l(int p, const TreeTables& tt, const MfmaTables& mt, bool harmonic,
-                           const double* M, double* L, int n, int lg, hipStream_t s) {
-  const int nb = n >= 8 ? n / 8 : 1;
-  const dim3 grid((unsigned)(nb * nb * nb)), block(kTreeThreads);
+                           const double* M, double* L, int nlev, const int* n, const int* lg,
+                           const int64_t* off, hipStream_t s) {
+  if (nlev < 1 || nlev > kTreeMaxLevels) return hipErrorInvalidValue;
+  TreeLevels lv{};
+  lv.nlev = nlev;
+  int total = 0;
+  for (int i = 0; i < nlev; ++i) {            // coarsest level first
+    const int l = nlev - 1 - i;
+    const int nb = n[l] >= 8 ? n[l] / 8 : 1;
+    lv.first[i] = total;
+    lv.n[i] = n[l];
+    lv.lg[i] = lg[l];
+    lv.off[i] = off[l];
+    total += nb * nb * nb;
+  }
+  lv.first[nlev] = total;
+  const dim3 grid((unsigned)total), block(kTreeThreads);
 #define TREE_LAUNCH(P, H)                                                                           \
-  hipLaunchKernelGGL((m2l_level_kernel<P, H>), grid, block, 0, s, M, L, n, lg, H ? tt.Bh[P] : tt.B[P], \
+  hipLaunchKernelGGL((m2l_level_kernel<P, H>), grid, block, 0, s, M, L, lv, H ? tt.Bh[P] : tt.B[P],   \
                      tt.doff, mt.hround[P], mt.hexp[P])
   switch (p * 2 + (harmonic ? 1 : 0)) {
     case 4: TREE_LAUNCH(2, false); break;
