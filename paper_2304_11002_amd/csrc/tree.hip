@@ -37,12 +37,10 @@ namespace fmm {
 
 namespace {
 
-constexpr int kTreeW = 18;                         // window: block cells -5 .. 12 per axis
-constexpr int kTreeWCells = kTreeW * kTreeW * kTreeW;
+constexpr int kTreeW = 18;                         // window (y, z): block cells -5 .. 12
 constexpr int kTreeList = 231;                     // interaction-list length per parity
 constexpr int kTreeQuads = (kTreeList + 3) / 4;    // 58 (the last quad has one empty slot)
 constexpr int kTreeThreads = 512;
-constexpr int kTreeStage = (kTreeWCells + kTreeThreads - 1) / kTreeThreads;
 constexpr int kTreeMaxLevels = 8;
 
 __device__ __forceinline__ double mfma4(double a, double b, double c) {
@@ -219,7 +217,9 @@ struct TreeLevels {
   int64_t off[kTreeMaxLevels];     // element offset of the level in M and L
 };
 
-template <int P, bool HARM>
+// NBLK: 8^3 target blocks per workgroup, side by side in x (the table operands
+// of a quad then serve 4 NBLK tiles per wave)
+template <int P, bool HARM, int NBLK>
 __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
     const double* __restrict__ Mall, double* __restrict__ Lall, TreeLevels lv,
     const double* __restrict__ B, const int* __restrict__ doff, const HRound* __restrict__ hround,
@@ -228,8 +228,12 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
   constexpr int CR = HARM ? (P + 1) * (P + 1) : C;   // contracted components (rows and columns)
   constexpr int NG = (CR + 3) / 4;
   constexpr int ROUNDS = (CR + 1) / 2;
-  // the window, and afterwards (harmonic form) the harmonic columns of the block
-  constexpr int SMEM = HARM && kNTarget * CR / 2 > kTreeWCells ? kNTarget * CR / 2 : kTreeWCells;
+  constexpr int WX = 8 * NBLK + 10;                   // window cells in x
+  constexpr int kTreeWCells = WX * kTreeW * kTreeW;
+  constexpr int kTreeStage = (kTreeWCells + kTreeThreads - 1) / kTreeThreads;
+  constexpr int TPW = 4 * NBLK;                       // 16-cell tiles per wave
+  // the window, and afterwards (harmonic form) the harmonic columns of the blocks
+  constexpr int SMEM = HARM && NBLK * kNTarget * CR / 2 > kTreeWCells ? NBLK * kNTarget * CR / 2 : kTreeWCells;
   __shared__ double2 smem[SMEM];
   __shared__ int s_doff[8 * kTreeQuads * 4];
   int li = 0;
@@ -238,25 +242,30 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
   const double* __restrict__ M = Mall + lv.off[li];
   double* __restrict__ L = Lall + lv.off[li];
   const int nb = n >= 8 ? n / 8 : 1;
+  const int nbx = n >= 8 * NBLK ? n / (8 * NBLK) : 1;
   const int blk = (int)blockIdx.x - lv.first[li];
-  const int B0x = 8 * (blk % nb), B0y = 8 * ((blk / nb) % nb), B0z = 8 * (blk / (nb * nb));
+  const int B0x = 8 * NBLK * (blk % nbx), B0y = 8 * ((blk / nbx) % nb), B0z = 8 * (blk / (nbx * nb));
   const int64_t n3 = (int64_t)n * n * n;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // parity class of this wave
   const int sx = wave & 1, sy = (wave >> 1) & 1, sz = wave >> 2;
   const int kk = lane >> 4, ci = lane & 15;
-  for (int i = tid; i < 8 * kTreeQuads * 4; i += kTreeThreads) s_doff[i] = doff[i];
-
-  // tile t: plane z = 2 t + sz, cells (2 (ci & 3) + sx, 2 (ci >> 2) + sy)
-  int abase[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int z = 2 * t + sz, x = 2 * (ci & 3) + sx, y = 2 * (ci >> 2) + sy;
-    abase[t] = (x + 5) + kTreeW * (y + 5) + kTreeW * kTreeW * (z + 5);
+  // offsets of the lists, packed (dx + 8) | (dy + 8) << 5 | (dz + 8) << 10, as window deltas
+  for (int i = tid; i < 8 * kTreeQuads * 4; i += kTreeThreads) {
+    const int v = doff[i];
+    s_doff[i] = ((v & 31) - 8) + WX * (((v >> 5) & 31) - 8) + WX * kTreeW * (((v >> 10) & 31) - 8);
   }
-  double acc[4][NG];
+
+  // tile t: block t / 4, plane z = 2 (t % 4) + sz, cells (8 (t / 4) + 2 (ci & 3) + sx, 2 (ci >> 2) + sy)
+  int abase[TPW];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < TPW; ++t) {
+    const int z = 2 * (t & 3) + sz, x = 8 * (t >> 2) + 2 * (ci & 3) + sx, y = 2 * (ci >> 2) + sy;
+    abase[t] = (x + 5) + WX * (y + 5) + WX * kTreeW * (z + 5);
+  }
+  double acc[TPW][NG];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
 #pragma unroll
     for (int g = 0; g < NG; ++g) acc[t][g] = 0.0;
 
@@ -266,8 +275,8 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
 #pragma unroll
   for (int i = 0; i < kTreeStage; ++i) {
     const int c = tid + i * kTreeThreads;
-    const int gx = B0x - 5 + c % kTreeW, gy = B0y - 5 + (c / kTreeW) % kTreeW,
-              gz = B0z - 5 + c / (kTreeW * kTreeW);
+    const int gx = B0x - 5 + c % WX, gy = B0y - 5 + (c / WX) % kTreeW,
+              gz = B0z - 5 + c / (WX * kTreeW);
     wg[i] = (c < kTreeWCells && gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n)
                 ? gx + (int64_t)n * gy + (int64_t)n * n * gz
                 : -1;
@@ -344,11 +353,11 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
         }
       }
       const int dl = dq[q * 4];
-      double2 a[4];
+      double2 a[TPW];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) a[t] = smem[abase[t] + dl];
+      for (int t = 0; t < TPW; ++t) a[t] = smem[abase[t] + dl];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < TPW; ++t) {
 #pragma unroll
         for (int g = 0; g < NG; ++g) acc[t][g] = mfma4(a[t].x, b0[g], acc[t][g]);
 #pragma unroll
@@ -361,8 +370,8 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
   const int xi = lane >> 4, yi = (lane & 15) >> 2, j = lane & 3;
   if (!HARM) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int gx = B0x + 2 * xi + sx, gy = B0y + 2 * yi + sy, gz = B0z + 2 * t + sz;
+    for (int t = 0; t < TPW; ++t) {
+      const int gx = B0x + 8 * (t >> 2) + 2 * xi + sx, gy = B0y + 2 * yi + sy, gz = B0z + 2 * (t & 3) + sz;
       if (gx >= n || gy >= n || gz >= n) continue;
       const int64_t g = gx + (int64_t)n * gy + (int64_t)n * n * gz;
 #pragma unroll
@@ -376,10 +385,10 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
   // harmonic columns (column c has order floor(sqrt(c))) through LDS, then each
   // thread expands one target cell to all C components
   __syncthreads();                                  // the window is no longer read
-  double* sh = reinterpret_cast<double*>(smem);     // [512 cells][CR]
+  double* sh = reinterpret_cast<double*>(smem);     // [512 NBLK cells][CR], x fastest over 8 NBLK
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int cell = (2 * xi + sx) + 8 * (2 * yi + sy) + 64 * (2 * t + sz);
+  for (int t = 0; t < TPW; ++t) {
+    const int cell = (8 * (t >> 2) + 2 * xi + sx) + 8 * NBLK * ((2 * yi + sy) + 8 * (2 * (t & 3) + sz));
 #pragma unroll
     for (int gg = 0; gg < NG; ++gg) {
       const int c = 4 * gg + j;
@@ -391,9 +400,8 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
     }
   }
   __syncthreads();
-  {
-    const int cell = tid;                           // 512 threads, 512 cells
-    const int gx = B0x + (cell & 7), gy = B0y + ((cell >> 3) & 7), gz = B0z + (cell >> 6);
+  for (int cell = tid; cell < NBLK * kNTarget; cell += kTreeThreads) {
+    const int gx = B0x + cell % (8 * NBLK), gy = B0y + (cell / (8 * NBLK)) % 8, gz = B0z + cell / (64 * NBLK);
     if (gx < n && gy < n && gz < n) {
       const int64_t g = gx + (int64_t)n * gy + (int64_t)n * n * gz;
       const double* lh = sh + cell * CR;
@@ -440,7 +448,7 @@ hipError_t tree_tables_create(TreeTables* tt, const double* const* d_T, const in
                               int nstencil, hipStream_t s) {
   const std::vector<int> lists = tree_lists();
   if (lists.empty()) return hipErrorInvalidValue;
-  std::vector<int> sidx(8 * kTreeQuads * 4, -1), doff(8 * kTreeQuads * 4, 0);
+  std::vector<int> sidx(8 * kTreeQuads * 4, -1), doff(8 * kTreeQuads * 4, 8 | (8 << 5) | (8 << 10));
   for (int sigma = 0; sigma < 8; ++sigma)
     for (int e = 0; e < kTreeList; ++e) {
       const int* d = &lists[3 * (sigma * kTreeList + e)];
@@ -452,7 +460,7 @@ hipError_t tree_tables_create(TreeTables* tt, const double* const* d_T, const in
         }
       if (found < 0) return hipErrorInvalidValue;
       sidx[sigma * kTreeQuads * 4 + e] = found;
-      doff[sigma * kTreeQuads * 4 + e] = d[0] + kTreeW * d[1] + kTreeW * kTreeW * d[2];
+      doff[sigma * kTreeQuads * 4 + e] = (d[0] + 8) | ((d[1] + 8) << 5) | ((d[2] + 8) << 10);
     }
   hipError_t e;
   int* d_sidx = nullptr;
@@ -540,20 +548,22 @@ hipError_t launch_tree_m2l(int p, const TreeTables& tt, const MfmaTables& mt, bo
   TreeLevels lv{};
   lv.nlev = nlev;
   int total = 0;
+  const int nblk = p <= 3 ? 2 : 1;             // blocks per workgroup (registers at p = 4)
   for (int i = 0; i < nlev; ++i) {            // coarsest level first
     const int l = nlev - 1 - i;
     const int nb = n[l] >= 8 ? n[l] / 8 : 1;
+    const int nbx = n[l] >= 8 * nblk ? n[l] / (8 * nblk) : 1;
     lv.first[i] = total;
     lv.n[i] = n[l];
     lv.lg[i] = lg[l];
     lv.off[i] = off[l];
-    total += nb * nb * nb;
+    total += nbx * nb * nb;
   }
   lv.first[nlev] = total;
   const dim3 grid((unsigned)total), block(kTreeThreads);
-#define TREE_LAUNCH(P, H)                                                                           \
-  hipLaunchKernelGGL((m2l_level_kernel<P, H>), grid, block, 0, s, M, L, lv, H ? tt.Bh[P] : tt.B[P],   \
-                     tt.doff, mt.hround[P], mt.hexp[P])
+#define TREE_LAUNCH(P, H)                                                                              \
+  hipLaunchKernelGGL((m2l_level_kernel<P, H, (P <= 3 ? 2 : 1)>), grid, block, 0, s, M, L, lv,           \
+                     H ? tt.Bh[P] : tt.B[P], tt.doff, mt.hround[P], mt.hexp[P])
   switch (p * 2 + (harmonic ? 1 : 0)) {
     case 4: TREE_LAUNCH(2, false); break;
     case 5: TREE_LAUNCH(2, true); break;
