@@ -60,6 +60,34 @@ __device__ __forceinline__ void powers(double bx, double by, double bz, double (
   }
 }
 
+// The (k, q) pairs with q <= k componentwise and their difference r = k - q,
+// built at compile time so the shift loops unroll into straight-line code.
+template <int P>
+struct ShiftTerms {
+  int n;
+  signed char k[ncomp(P) * ncomp(P)], q[ncomp(P) * ncomp(P)];
+  signed char rx[ncomp(P) * ncomp(P)], ry[ncomp(P) * ncomp(P)], rz[ncomp(P) * ncomp(P)];
+};
+template <int P>
+constexpr ShiftTerms<P> make_shift_terms() {
+  ShiftTerms<P> t{};
+  for (int ck = 0; ck < ncomp(P); ++ck) {
+    const MI k = mi_of(ck);
+    for (int cq = 0; cq < ncomp(P); ++cq) {
+      const MI q = mi_of(cq);
+      if (q.x <= k.x && q.y <= k.y && q.z <= k.z) {
+        t.k[t.n] = (signed char)ck;
+        t.q[t.n] = (signed char)cq;
+        t.rx[t.n] = (signed char)(k.x - q.x);
+        t.ry[t.n] = (signed char)(k.y - q.y);
+        t.rz[t.n] = (signed char)(k.z - q.z);
+        ++t.n;
+      }
+    }
+  }
+  return t;
+}
+
 template <int P>
 __global__ void __launch_bounds__(256) p2m_grid_kernel(const double* __restrict__ pos,
                                                        const double* __restrict__ mass, int ppc,
@@ -110,16 +138,10 @@ __global__ void __launch_bounds__(256) m2m_kernel(const double* __restrict__ Mc,
     for (int c = 0; c < C; ++c) mc[c] = Mc[c * nc3 + g];
     double px[P + 1], py[P + 1], pz[P + 1];
     powers<P>((ox - 0.5) * hc, (oy - 0.5) * hc, (oz - 0.5) * hc, px, py, pz);
+    constexpr ShiftTerms<P> T = make_shift_terms<P>();
 #pragma unroll
-    for (int ck = 0; ck < C; ++ck) {
-      const MI k = mi_of(ck);
-#pragma unroll
-      for (int cq = 0; cq < C; ++cq) {
-        const MI q = mi_of(cq);
-        if (q.x <= k.x && q.y <= k.y && q.z <= k.z)
-          acc[ck] = __builtin_fma(mc[cq], px[k.x - q.x] * py[k.y - q.y] * pz[k.z - q.z], acc[ck]);
-      }
-    }
+    for (int e = 0; e < T.n; ++e)
+      acc[T.k[e]] = __builtin_fma(mc[T.q[e]], px[T.rx[e]] * py[T.ry[e]] * pz[T.rz[e]], acc[T.k[e]]);
   }
 #pragma unroll
   for (int c = 0; c < C; ++c) Mp[c * np3 + i] = acc[c];
@@ -142,18 +164,16 @@ __global__ void __launch_bounds__(256) l2l_kernel(const double* __restrict__ Lp,
   for (int c = 0; c < C; ++c) lp[c] = Lp[c * np3 + G];
   double px[P + 1], py[P + 1], pz[P + 1];
   powers<P>(((x & 1) - 0.5) * hc, ((y & 1) - 0.5) * hc, ((z & 1) - 0.5) * hc, px, py, pz);
+  // child n from parent m >= n: the terms (k, q) = (m, n) of the shift table
+  constexpr ShiftTerms<P> T = make_shift_terms<P>();
+  double s[C];
 #pragma unroll
-  for (int cn = 0; cn < C; ++cn) {
-    const MI nn = mi_of(cn);
-    double s = 0.0;
+  for (int c = 0; c < C; ++c) s[c] = 0.0;
 #pragma unroll
-    for (int cm = 0; cm < C; ++cm) {
-      const MI m = mi_of(cm);
-      if (nn.x <= m.x && nn.y <= m.y && nn.z <= m.z)
-        s = __builtin_fma(lp[cm], px[m.x - nn.x] * py[m.y - nn.y] * pz[m.z - nn.z], s);
-    }
-    Lc[cn * nc3 + j] += s;
-  }
+  for (int e = 0; e < T.n; ++e)
+    s[T.q[e]] = __builtin_fma(lp[T.k[e]], px[T.rx[e]] * py[T.ry[e]] * pz[T.rz[e]], s[T.q[e]]);
+#pragma unroll
+  for (int c = 0; c < C; ++c) Lc[c * nc3 + j] += s[c];
 }
 
 // Tables of the level kernel, per order p:
