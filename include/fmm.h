@@ -90,6 +90,10 @@ typedef struct {
 #define FMM_OPT_M2L_KERNEL  1  /* 0 auto (default), 1 reference VALU kernel, 2 MFMA kernel */
 #define FMM_OPT_USE_GRAPH   2  /* 1 (default): replay cached hipGraphs for M2L; 0: plain launches */
 #define FMM_OPT_TILE_CONFIG 3  /* -1 (default): autotuned/built-in choice; >= 0 forces a table entry */
+#define FMM_OPT_P2M_WINDOW  5  /* fmm_p2m: 0 (default) writes every cell of the frame; 1 reads and writes
+                                  only the frame rows (y, z) in [2,22)^2 (all 24 cells of each), which
+                                  hold the reachable window [2,22)^3, the only cells fmm_m2l reads (the
+                                  other cells of M keep their contents) */
 #define FMM_OPT_ADJOINT_FORM 4 /* fmm_m2l_backward: 0 (default) dense form; 1 harmonic form (the
                                   transpose of the FMM_FP64_HARMONIC operator: dL folded to the
                                   (p+1)^2 harmonic columns, dM expanded from the folded components;
@@ -121,8 +125,10 @@ fmm_status fmm_pair_count(const fmm_subgrid* desc, int64_t nsub, int64_t* pairs)
 
 /* P2M (row "P2M": leaf moments about the cell centres; the paper's leaf
  * cells are the a = 0 special case). pos/mass as above, ppc particles per
- * cell (1..64). Writes all C * 13824 moments of each sub-grid; cells of
- * absent blocks get 0 and their particles are not read. */
+ * cell (1..64). Writes all C * 13824 moments of each sub-grid (with
+ * FMM_OPT_P2M_WINDOW = 1 only those of the rows holding the reachable
+ * window, whose particles are then the only ones read); cells of absent
+ * blocks get 0 and their particles are not read. */
 fmm_status fmm_p2m(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
                    const double* pos, const double* mass, int32_t ppc,
                    double* M, void* stream);

@@ -120,6 +120,7 @@ struct fmm_ctx {
   int use_graph = 1;
   int tile_config = -1;
   int adjoint_form = 0;     // FMM_OPT_ADJOINT_FORM
+  int p2m_window = 0;       // FMM_OPT_P2M_WINDOW
 };
 
 namespace {
@@ -421,6 +422,10 @@ fmm_status fmm_set_option(fmm_ctx* ctx, int32_t option, int64_t value) {
       if (value != 0 && value != 1) return set_err(ctx, FMM_EINVAL, "FMM_OPT_USE_GRAPH value not 0/1");
       ctx->use_graph = (int)value;
       return FMM_OK;
+    case FMM_OPT_P2M_WINDOW:
+      if (value != 0 && value != 1) return set_err(ctx, FMM_EINVAL, "FMM_OPT_P2M_WINDOW value not 0/1");
+      ctx->p2m_window = (int)value;
+      return FMM_OK;
     case FMM_OPT_ADJOINT_FORM:
       if (value != 0 && value != 1) return set_err(ctx, FMM_EINVAL, "FMM_OPT_ADJOINT_FORM value not 0/1");
       ctx->adjoint_form = (int)value;
@@ -449,7 +454,8 @@ fmm_status fmm_p2m(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const do
   HIP_TRY(ctx, guard.err);
   DescEntry* e = nullptr;
   CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
-  HIP_TRY(ctx, launch_p2m(e->d_desc, nsub, e->d_ids, e->count, pos, mass, ppc, M, e->part_even, s));
+  HIP_TRY(ctx, launch_p2m(e->d_desc, nsub, e->d_ids, e->count, pos, mass, ppc, M, e->part_even,
+                          ctx->p2m_window != 0, s));
   return mark_used(ctx, e, s);
 }
 

@@ -12,9 +12,10 @@ hipError_t launch_build_tensors(const double* d_D, int order_d, int p, double* d
 // p2m.hip
 // d_ids[p], counts[p]: the sub-grids of order p; all_aligned: every descriptor's
 // part_off is even (16-byte aligned particle blocks)
+// window: only the reachable 20^3 window of each frame is read and written
 hipError_t launch_p2m(const DevDesc* d_desc, int64_t nsub, const int* const* d_ids, const int* counts,
                       const double* pos, const double* mass, int ppc, double* M, bool all_aligned,
-                      hipStream_t s);
+                      bool window, hipStream_t s);
 hipError_t launch_p2m_backward(const DevDesc* d_desc, int64_t nsub, const int* const* d_ids,
                                const int* counts, const double* pos, int ppc, const double* dM,
                                double* dmass, bool all_aligned, hipStream_t s);

@@ -14,6 +14,15 @@ constexpr int kP2MThreads = 256;
 constexpr int kCellBlocks = kNCell / kP2MThreads;   // 54
 static_assert(kNCell % kP2MThreads == 0, "cells per block");
 
+// The frame rows (y, z) in [2, 22)^2, all 24 cells of each: they hold the
+// reachable window [2, 22)^3, the only cells M2L reads, and whole rows keep
+// the stores to M in whole cache lines (a partial line costs more than it
+// saves).
+__device__ __forceinline__ bool in_window(int cell) {
+  const unsigned y = (cell / kFrame) % kFrame - kWin0, z = cell / (kFrame * kFrame) - kWin0;
+  return y < (unsigned)kWin && z < (unsigned)kWin;
+}
+
 template <int P>
 __device__ __forceinline__ void monomials(double ax, double ay, double az, double* out) {
   double px[P + 1], py[P + 1], pz[P + 1];
@@ -34,9 +43,10 @@ __device__ __forceinline__ void monomials(double ax, double ay, double az, doubl
 template <int P>
 __device__ void p2m_cell(const DevDesc& d, const double* __restrict__ pos,
                          const double* __restrict__ mass, int ppc, double* __restrict__ M,
-                         int cell) {
+                         int cell, bool window) {
   constexpr int C = ncomp(P);
   const int jx = cell % kFrame, jy = (cell / kFrame) % kFrame, jz = cell / (kFrame * kFrame);
+  if (window && !in_window(cell)) return;
   double* out = M + d.m_off + cell;
   if (!block_present(d.mask, jx, jy, jz)) {
 #pragma unroll
@@ -64,14 +74,14 @@ __device__ void p2m_cell(const DevDesc& d, const double* __restrict__ pos,
 __global__ void __launch_bounds__(kP2MThreads) p2m_kernel(const DevDesc* __restrict__ desc,
                                                           const double* __restrict__ pos,
                                                           const double* __restrict__ mass, int ppc,
-                                                          double* __restrict__ M) {
+                                                          double* __restrict__ M, bool window) {
   const int b = blockIdx.x / kCellBlocks;
   const int cell = (blockIdx.x % kCellBlocks) * kP2MThreads + threadIdx.x;
   const DevDesc d = desc[b];
   switch (d.p) {
-    case 2: p2m_cell<2>(d, pos, mass, ppc, M, cell); break;
-    case 3: p2m_cell<3>(d, pos, mass, ppc, M, cell); break;
-    case 4: p2m_cell<4>(d, pos, mass, ppc, M, cell); break;
+    case 2: p2m_cell<2>(d, pos, mass, ppc, M, cell, window); break;
+    case 3: p2m_cell<3>(d, pos, mass, ppc, M, cell, window); break;
+    case 4: p2m_cell<4>(d, pos, mass, ppc, M, cell, window); break;
     default: break;
   }
 }
@@ -135,13 +145,17 @@ static_assert(kNCell % kT8 == 0, "cells per block");
 __device__ __forceinline__ bool cell_present(uint32_t mask, int cell) {
   return block_present(mask, cell % kFrame, (cell / kFrame) % kFrame, cell / (kFrame * kFrame));
 }
+// WIN: only the window rows' cells are read and written; their z range
+// [2, 22) is blocks 9 .. 98 of the 108 blocks of 128 cells
+constexpr int kWinBlock0 = (kWin0 * kFrame * kFrame) / 128;                            // 9
+constexpr int kWinBlocks = ((kWin0 + kWin) * kFrame * kFrame + 127) / 128 - kWinBlock0;   // 90
 
 // Each workgroup takes K cell blocks (strided by the grid; K = 4 measured best of 4, 8, 16). The coalesced loads
 // of the next block are issued into registers before this block's moments are
 // computed, so every workgroup keeps loads in flight through its compute and
 // store phases (4 workgroups fit a CU by LDS). p = 4 needs those registers for
 // its moments and takes one block per workgroup.
-template <int P, int K>
+template <int P, int K, bool WIN>
 __global__ void __launch_bounds__(kT8) p2m8_kernel(const DevDesc* __restrict__ desc,
                                                    const int* __restrict__ ids, int nblocks,
                                                    const double* __restrict__ pos,
@@ -150,22 +164,25 @@ __global__ void __launch_bounds__(kT8) p2m8_kernel(const DevDesc* __restrict__ d
   constexpr int C = ncomp(P);
   __shared__ double s_pos[kT8 * kPosStride];
   __shared__ double s_mass[kT8 * kPpc8];
+  constexpr int NB = WIN ? kWinBlocks : kCellBlocks8;   // blocks per sub-grid
+  constexpr int B0 = WIN ? kWinBlock0 : 0;
   const int tid = threadIdx.x;
   double2 rp[12], rm[4];
   // coalesced loads of block B's positions (12 double2 per thread) and masses (4)
+#define P2M8_USE(MASK, C) (cell_present((MASK), (C)) && (!WIN || in_window(C)))
 #define P2M8_ISSUE(B)                                                                          \
   {                                                                                            \
-    const DevDesc dn = desc[ids[(B) / kCellBlocks8]];                                          \
-    const int c0 = ((B) % kCellBlocks8) * kT8;                                                 \
+    const DevDesc dn = desc[ids[(B) / NB]];                                                    \
+    const int c0 = ((B) % NB + B0) * kT8;                                                      \
     const double2* ps = reinterpret_cast<const double2*>(pos + 3 * (dn.part_off + (int64_t)c0 * kPpc8)); \
     const double2* ms = reinterpret_cast<const double2*>(mass + dn.part_off + (int64_t)c0 * kPpc8); \
     _Pragma("unroll") for (int i = 0; i < 12; ++i) {                                           \
       const int v = tid + i * kT8;                                                             \
-      rp[i] = cell_present(dn.mask, c0 + v / 12) ? ps[v] : make_double2(0.0, 0.0);             \
+      rp[i] = P2M8_USE(dn.mask, c0 + v / 12) ? ps[v] : make_double2(0.0, 0.0);                 \
     }                                                                                          \
     _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                            \
       const int v = tid + i * kT8;                                                             \
-      rm[i] = cell_present(dn.mask, c0 + v / 4) ? ms[v] : make_double2(0.0, 0.0);              \
+      rm[i] = P2M8_USE(dn.mask, c0 + v / 4) ? ms[v] : make_double2(0.0, 0.0);                  \
     }                                                                                          \
   }
   int blk = blockIdx.x;
@@ -188,11 +205,13 @@ __global__ void __launch_bounds__(kT8) p2m8_kernel(const DevDesc* __restrict__ d
     __syncthreads();
     const int nb = blk + (int)gridDim.x;
     if (k + 1 < K && nb < nblocks) P2M8_ISSUE(nb);
-    const DevDesc d = desc[ids[blk / kCellBlocks8]];
-    const int cell = (blk % kCellBlocks8) * kT8 + tid;
+    const DevDesc d = desc[ids[blk / NB]];
+    const int cell = (blk % NB + B0) * kT8 + tid;
     const int jx = cell % kFrame, jy = (cell / kFrame) % kFrame, jz = cell / (kFrame * kFrame);
     double* out = M + d.m_off + cell;
-    if (!block_present(d.mask, jx, jy, jz)) {
+    if (WIN && !in_window(cell)) {
+      // outside the window: neither read nor written
+    } else if (!block_present(d.mask, jx, jy, jz)) {
 #pragma unroll
       for (int c = 0; c < C; ++c) out[(size_t)c * kNCell] = 0.0;
     } else {
@@ -215,6 +234,7 @@ __global__ void __launch_bounds__(kT8) p2m8_kernel(const DevDesc* __restrict__ d
     }
   }
 #undef P2M8_ISSUE
+#undef P2M8_USE
 }
 
 // Adjoint: K cell blocks per workgroup as in the forward; the next block's
@@ -302,7 +322,7 @@ static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 
 hipError_t launch_p2m(const DevDesc* d_desc, int64_t nsub, const int* const* d_ids, const int* counts,
                       const double* pos, const double* mass, int ppc, double* M, bool all_aligned,
-                      hipStream_t s) {
+                      bool window, hipStream_t s) {
   const bool fast = ppc == kPpc8 && all_aligned && aligned16(pos) && aligned16(mass);
   if (fast) {
     // one launch per order present, over that order's sub-grids
@@ -310,11 +330,18 @@ hipError_t launch_p2m(const DevDesc* d_desc, int64_t nsub, const int* const* d_i
     for (int p = 2; p <= kMaxP; ++p) {
       for (int64_t b0 = 0; b0 < counts[p]; b0 += per_launch) {
         const int64_t n = counts[p] - b0 < per_launch ? counts[p] - b0 : per_launch;
-        const int nblocks = (int)(n * kCellBlocks8);
+        const int nblocks = (int)(n * (window ? kWinBlocks : kCellBlocks8));
         const dim3 grid4((unsigned)((nblocks + 3) / 4)), grid1((unsigned)nblocks);
-        if (p == 2) hipLaunchKernelGGL((p2m8_kernel<2, 4>), grid4, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, nblocks, pos, mass, M);
-        if (p == 3) hipLaunchKernelGGL((p2m8_kernel<3, 4>), grid4, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, nblocks, pos, mass, M);
-        if (p == 4) hipLaunchKernelGGL((p2m8_kernel<4, 1>), grid1, dim3(kT8), 0, s, d_desc, d_ids[p] + b0, nblocks, pos, mass, M);
+        const int* ids = d_ids[p] + b0;
+        if (window) {
+          if (p == 2) hipLaunchKernelGGL((p2m8_kernel<2, 4, true>), grid4, dim3(kT8), 0, s, d_desc, ids, nblocks, pos, mass, M);
+          if (p == 3) hipLaunchKernelGGL((p2m8_kernel<3, 4, true>), grid4, dim3(kT8), 0, s, d_desc, ids, nblocks, pos, mass, M);
+          if (p == 4) hipLaunchKernelGGL((p2m8_kernel<4, 1, true>), grid1, dim3(kT8), 0, s, d_desc, ids, nblocks, pos, mass, M);
+        } else {
+          if (p == 2) hipLaunchKernelGGL((p2m8_kernel<2, 4, false>), grid4, dim3(kT8), 0, s, d_desc, ids, nblocks, pos, mass, M);
+          if (p == 3) hipLaunchKernelGGL((p2m8_kernel<3, 4, false>), grid4, dim3(kT8), 0, s, d_desc, ids, nblocks, pos, mass, M);
+          if (p == 4) hipLaunchKernelGGL((p2m8_kernel<4, 1, false>), grid1, dim3(kT8), 0, s, d_desc, ids, nblocks, pos, mass, M);
+        }
       }
     }
     return hipGetLastError();
@@ -323,7 +350,7 @@ hipError_t launch_p2m(const DevDesc* d_desc, int64_t nsub, const int* const* d_i
   for (int64_t b0 = 0; b0 < nsub; b0 += per_launch) {
     const int64_t n = nsub - b0 < per_launch ? nsub - b0 : per_launch;
     hipLaunchKernelGGL(p2m_kernel, dim3((unsigned)(n * kCellBlocks)), dim3(kP2MThreads), 0, s,
-                       d_desc + b0, pos, mass, ppc, M);
+                       d_desc + b0, pos, mass, ppc, M, window);
   }
   return hipGetLastError();
 }

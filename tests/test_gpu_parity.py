@@ -418,3 +418,38 @@ def test_harmonic_adjoint_dot_product(ctx, torch):
     lhs = float(np.dot(W, L.cpu().numpy()))
     rhs = float(np.dot(dM.cpu().numpy(), M.cpu().numpy()))
     assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + abs(rhs))
+
+
+def test_p2m_window_option(ctx, torch):
+    # FMM_OPT_P2M_WINDOW = 1: the moments of the frame rows holding the reachable
+    # window bitwise as in the full P2M, every other cell of M untouched, and the
+    # same M2L; also the generic kernel
+    for ppc in (8, 5):
+        w = synth.config(3, nsub=4)
+        w.ppc = ppc
+        desc, m_el, l_el = descriptors(w, range(4))
+        pos, mass = particles(w, range(4))
+        dpos, dmass = to_dev(pos), to_dev(mass)
+        Mf = torch.empty(m_el, dtype=torch.float64, device="cuda")
+        Mw = torch.full((m_el,), float("nan"), dtype=torch.float64, device="cuda")
+        ctx.p2m(desc, dpos, dmass, ppc, Mf)
+        ctx.set_option(fmm.FMM_OPT_P2M_WINDOW, 1)
+        try:
+            ctx.p2m(desc, dpos, dmass, ppc, Mw)
+        finally:
+            ctx.set_option(fmm.FMM_OPT_P2M_WINDOW, 0)
+        torch.cuda.synchronize()
+        rows = np.zeros((24, 24, 24), bool)          # [z][y][x]: rows (y, z) in [2, 22)^2, every x
+        rows[2:22, 2:22, :] = True
+        for vf, vw in zip(split_views(Mf.cpu().numpy(), desc, "M"), split_views(Mw.cpu().numpy(), desc, "M")):
+            assert np.array_equal(vf[:, rows], vw[:, rows])
+            assert np.isnan(vw[:, ~rows]).all()
+        if ppc == 8:
+            ctx.set_option(fmm.FMM_OPT_M2L_KERNEL, MFMA)
+            L1 = torch.empty(l_el, dtype=torch.float64, device="cuda")
+            L2 = torch.empty_like(L1)
+            ctx.m2l(desc, Mf, L1, fmm.FMM_FP64_HARMONIC)
+            ctx.m2l(desc, Mw, L2, fmm.FMM_FP64_HARMONIC)
+            torch.cuda.synchronize()
+            assert torch.equal(L1, L2)
+
