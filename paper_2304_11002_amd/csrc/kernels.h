@@ -36,7 +36,8 @@ struct MfmaTables;
 struct TreeTables {
   double* B[kMaxP + 1] = {};   // per order: interaction-list tables in consumption order
   double* Bh[kMaxP + 1] = {};  // the same for the harmonic form
-  int* doff = nullptr;         // [8 parities][58 quads][4] window offsets of the lists
+  int* doff = nullptr;         // [8 parities][58 quads][4] offsets of the lists, packed
+                               // (dx + 8) | (dy + 8) << 5 | (dz + 8) << 10
 };
 hipError_t tree_tables_create(TreeTables* tt, const double* const* d_T, const int* stencil_xyz,
                               int nstencil, hipStream_t s);

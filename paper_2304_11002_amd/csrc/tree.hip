@@ -249,11 +249,11 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
   constexpr int NG = (CR + 3) / 4;
   constexpr int ROUNDS = (CR + 1) / 2;
   constexpr int WX = 8 * NBLK + 10;                   // window cells in x
-  constexpr int kTreeWCells = WX * kTreeW * kTreeW;
-  constexpr int kTreeStage = (kTreeWCells + kTreeThreads - 1) / kTreeThreads;
+  constexpr int WCELLS = WX * kTreeW * kTreeW;
+  constexpr int STAGE = (WCELLS + kTreeThreads - 1) / kTreeThreads;
   constexpr int TPW = 4 * NBLK;                       // 16-cell tiles per wave
   // the window, and afterwards (harmonic form) the harmonic columns of the blocks
-  constexpr int SMEM = HARM && NBLK * kNTarget * CR / 2 > kTreeWCells ? NBLK * kNTarget * CR / 2 : kTreeWCells;
+  constexpr int SMEM = HARM && NBLK * kNTarget * CR / 2 > WCELLS ? NBLK * kNTarget * CR / 2 : WCELLS;
   __shared__ double2 smem[SMEM];
   __shared__ int s_doff[8 * kTreeQuads * 4];
   int li = 0;
@@ -291,21 +291,21 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
 
   const int* dq = s_doff + wave * kTreeQuads * 4 + kk;
   // this thread's window cells: global index, or -1 outside the domain
-  int64_t wg[kTreeStage];
+  int64_t wg[STAGE];
 #pragma unroll
-  for (int i = 0; i < kTreeStage; ++i) {
+  for (int i = 0; i < STAGE; ++i) {
     const int c = tid + i * kTreeThreads;
     const int gx = B0x - 5 + c % WX, gy = B0y - 5 + (c / WX) % kTreeW,
               gz = B0z - 5 + c / (WX * kTreeW);
-    wg[i] = (c < kTreeWCells && gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n)
+    wg[i] = (c < WCELLS && gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n)
                 ? gx + (int64_t)n * gy + (int64_t)n * n * gz
                 : -1;
   }
   for (int r = 0; r < ROUNDS; ++r) {
     double s0, s1;
-    double2 v[kTreeStage];
+    double2 v[STAGE];
 #pragma unroll
-    for (int i = 0; i < kTreeStage; ++i) v[i] = make_double2(0.0, 0.0);
+    for (int i = 0; i < STAGE; ++i) v[i] = make_double2(0.0, 0.0);
     if (HARM) {
       // the round's two folded components, each an integer combination of moment
       // components of one order
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
         const double* src = M + (int64_t)rd.comp[u] * n3;
         const double a0 = rd.c0[u], a1 = rd.c1[u];
 #pragma unroll
-        for (int i = 0; i < kTreeStage; ++i) {
+        for (int i = 0; i < STAGE; ++i) {
           if (wg[i] >= 0) {
             const double m = src[wg[i]];
             v[i].x = __builtin_fma(a0, m, v[i].x);
@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
       const double* src0 = M + (int64_t)k0 * n3;
       const double* src1 = M + (int64_t)(k1 < C ? k1 : k0) * n3;
 #pragma unroll
-      for (int i = 0; i < kTreeStage; ++i) {
+      for (int i = 0; i < STAGE; ++i) {
         if (wg[i] >= 0) {
           v[i].x = src0[wg[i]];
           v[i].y = src1[wg[i]];
@@ -340,9 +340,9 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
     }
     __syncthreads();   // the previous round's window reads are done
 #pragma unroll
-    for (int i = 0; i < kTreeStage; ++i) {
+    for (int i = 0; i < STAGE; ++i) {
       const int c = tid + i * kTreeThreads;
-      if (c < kTreeWCells) smem[c] = make_double2(v[i].x * s0, v[i].y * s1);
+      if (c < WCELLS) smem[c] = make_double2(v[i].x * s0, v[i].y * s1);
     }
     __syncthreads();
     const double* Br = B + ((int64_t)(wave * ROUNDS + r) * kTreeQuads) * 2 * NG * 16 + kk * 4 + (lane & 3);
