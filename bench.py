@@ -559,6 +559,28 @@ def main():
         out["tree"] = bench_tree(torch, fmm, ctx, K, W)
         torch.cuda.empty_cache()
 
+        # ---------------- one sub-grid: the latency of the step (too small to fill the GPU)
+        w1 = synth.config(1)
+        d1, m1, l1 = fmm.make_descriptors(w1.p, w1.log2_inv_h, w1.mask)
+        p1, ms1 = synth.subgrid_particles(w1.seed)
+        pos1 = torch.from_numpy(p1).to("cuda")
+        mass1 = torch.from_numpy(ms1).to("cuda")
+        M1 = torch.empty(m1, dtype=torch.float64, device="cuda")
+        L1 = torch.empty(l1, dtype=torch.float64, device="cuda")
+
+        def step_one(ev, i):
+            if ev: ev[0].record()
+            ctx.p2m(d1, pos1, mass1, 8, M1)
+            ctx.m2l(d1, M1, L1, fmm.FMM_FP64_HARMONIC)
+            if ev: ev[1].record()
+
+        _, seg1 = timed(torch, step_one, K, W, marks=1)
+        out["single_subgrid"] = {"workload": "single_subgrid_p3", "pairs": fmm.pair_count(d1),
+                                 "step_ms_median": float(np.median(seg1[:, 0])),
+                                 "step_ms_min": float(seg1[:, 0].min())}
+        log("single sub-grid step %.3f ms (median)" % np.median(seg1[:, 0]))
+        del pos1, mass1, M1, L1
+
         # ---------------- CPU baseline (the oracle on the host cores)
         out["cpu_baseline"] = cpu_baseline(w.nsub, args.cpu_seconds)
         log("cpu_baseline %.4g pairs/s on %d cores" % (out["cpu_baseline"]["value"], out["cpu_baseline"]["cores"]))

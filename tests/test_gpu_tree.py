@@ -56,7 +56,10 @@ def check(got, want, scale, what):
         what, bad.sum(), np.nanmax(err / np.maximum(scale, 1e-300)))
 
 
-CASES = [(2, 16, 2, 0), (3, 16, 3, -1), (4, 8, 2, 1), (3, 32, 1, 0)]
+# (p, n, ppc, log2_h): orders 2-4, one to five levels below the top, two-block
+# workgroups (p <= 3) and single blocks (p = 4), and more than 8 particles per
+# cell (the evaluation's particle chunks)
+CASES = [(2, 16, 2, 0), (3, 16, 3, -1), (4, 8, 2, 1), (3, 32, 1, 0), (3, 8, 11, 0)]
 
 
 @pytest.mark.parametrize("p,n,ppc,lh", CASES)
