@@ -88,6 +88,22 @@ def test_uniform_4096_fp64_and_split(ctx, torch):
         rel.append((np.abs(Ls[o:o + 20 * 512].cpu().numpy().reshape(20, 8, 8, 8) - Lo) / La).ravel())
     rel = np.concatenate(rel)
     assert rel.max() < 1e-6 and np.median(rel) < 5e-8
+    # the configuration the step is timed in: P2M over the rows holding the
+    # reachable window, then the autotuned harmonic form, replayed from its graph
+    Mw = torch.full_like(M, float("nan"))
+    ctx.set_option(fmm.FMM_OPT_P2M_WINDOW, 1)
+    try:
+        ctx.p2m(desc, pos, mass, 8, Mw)
+    finally:
+        ctx.set_option(fmm.FMM_OPT_P2M_WINDOW, 0)
+    Lh = torch.empty_like(L)
+    ctx.autotune(desc, Mw, Lh, fmm.FMM_FP64_HARMONIC)
+    ctx.m2l(desc, Mw, Lh, fmm.FMM_FP64_HARMONIC)
+    Lh2 = torch.empty_like(L)
+    ctx.m2l(desc, Mw, Lh2, fmm.FMM_FP64_HARMONIC)
+    torch.cuda.synchronize()
+    assert torch.isfinite(Lh).all() and torch.equal(Lh, Lh2)
+    check_sampled(w, desc, Lh, [0, 1, 2047, 4095])
 
 
 def test_uniform_4096_evaluate(ctx, torch):
