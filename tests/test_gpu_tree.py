@@ -144,3 +144,26 @@ def test_tree_solve_accuracy_against_the_direct_sum(ctx, torch):
     ex = T.direct_all(pos, mass)
     assert np.max(np.abs(E[0] - ex[0]) / ex[0]) < 5e-4
     assert np.median(np.abs(E[1:] - ex[1:]).max(axis=0) / np.abs(ex[1:]).max(axis=0)) < 1.5e-3
+
+
+# a seeded sweep over order, spacing (the extremes of log2_h), form and particle count
+SWEEP = [(p, lh, harm, ppc) for p, lh, harm, ppc in
+         zip([2, 3, 4, 2, 3, 4, 3, 2], [-4, 4, 2, -3, -2, 3, 1, 0], [1, 0, 1, 0, 1, 0, 1, 1], [1, 2, 1, 9, 1, 1, 4, 2])]
+
+
+@pytest.mark.parametrize("p,lh,harmonic,ppc", SWEEP)
+def test_tree_solve_sweep(ctx, torch, p, lh, harmonic, ppc):
+    n, h = 8, 2.0 ** lh
+    tree = fmm.Tree(p, n, ppc, lh, harmonic)
+    _, elems = fmm.tree_size(tree)
+    pos, mass = synth.grid_particles(50 + p + 10 * ppc, n, h, ppc)
+    M = torch.empty(elems, dtype=torch.float64, device="cuda")
+    L = torch.empty(elems, dtype=torch.float64, device="cuda")
+    out = torch.empty(4 * n ** 3 * ppc, dtype=torch.float64, device="cuda")
+    ctx.tree_solve(tree, to_dev(pos), to_dev(mass), M, L, out)
+    torch.cuda.synchronize()
+    want = T.solve(pos, mass, p, n, h)
+    Ma = T.upward(pos, mass, p, n, h, absolute=True)
+    Lta = T.downward(T.m2l_levels(Ma, p, h, absolute=True), p, h, absolute=True)
+    scale = T.l2p_grid_abs(Lta[0], pos, p, n, h) + T.near_grid(pos, mass, n, h, absolute=True)
+    check(out.cpu().numpy().reshape(4, n ** 3, ppc), want, scale, "sweep p=%d lh=%d harmonic=%d ppc=%d" % (p, lh, harmonic, ppc))
