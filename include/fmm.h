@@ -139,6 +139,22 @@ fmm_status fmm_p2m(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
 fmm_status fmm_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
                    const double* M, double* L, fmm_precision prec, void* stream);
 
+/* P2M and M2L in one persistent launch. L is, bit for bit, what fmm_p2m
+ * with FMM_OPT_P2M_WINDOW = 1 followed by fmm_m2l gives, and M receives
+ * what that fmm_p2m writes: the moments of the frame rows holding the
+ * reachable window (the other cells of M are not written), whatever
+ * FMM_OPT_P2M_WINDOW is set to. Each workgroup computes a sub-grid's
+ * moments itself, during the M2L of the sub-grid before it, so the
+ * HBM-bound moment work of some workgroups overlaps the matrix work of the
+ * others. The single launch needs ppc = 8, 16-byte aligned pos and mass,
+ * even part_off and a configuration with LDS-staged tables (every
+ * FMM_FP64_HARMONIC configuration; FMM_FP64 configurations 0 and 1);
+ * otherwise, and with FMM_OPT_M2L_KERNEL = 1, the call runs the two steps
+ * one after the other, with the same results. */
+fmm_status fmm_p2m_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
+                       const double* pos, const double* mass, int32_t ppc,
+                       double* M, double* L, fmm_precision prec, void* stream);
+
 /* Adjoint of M2L with respect to M: dM_k(s) = sum over (t, d) with
  * s = t + d of sum_n dL_n(t) T_d[k][n]. dL laid out like L, dM like M;
  * dM is fully written (zero outside the reachable 20^3 window [2,22)^3

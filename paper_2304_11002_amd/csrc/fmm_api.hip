@@ -654,10 +654,12 @@ static fmm_status run_ref(fmm_ctx* ctx, DescEntry* e, bool backward, const doubl
 }
 
 // Launch the persistent matrix-core kernel, through a cached graph if enabled.
+// pos, mass non-null: the fused P2M + M2L launch (launch_m2l_mfma's fused form).
 static fmm_status run_mfma(fmm_ctx* ctx, DescEntry* e, const double* M, double* L,
-                           fmm_precision prec, int cfg, hipStream_t s) {
+                           fmm_precision prec, int cfg, hipStream_t s,
+                           const double* pos = nullptr, const double* mass = nullptr) {
   if (!ctx->use_graph) {
-    HIP_TRY(ctx, launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, s));
+    HIP_TRY(ctx, launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, s, pos, mass));
     return FMM_OK;
   }
   uint64_t key = fnv1a(&e->hash, sizeof e->hash);
@@ -665,6 +667,8 @@ static fmm_status run_mfma(fmm_ctx* ctx, DescEntry* e, const double* M, double* 
   key = fnv1a(&L, sizeof L, key);
   key = fnv1a(&prec, sizeof prec, key);
   key = fnv1a(&cfg, sizeof cfg, key);
+  key = fnv1a(&pos, sizeof pos, key);
+  key = fnv1a(&mass, sizeof mass, key);
   auto it = ctx->graphs.find(key);
   if (it == ctx->graphs.end()) {
     if (ctx->graphs.size() >= kMaxGraphs) {
@@ -677,7 +681,7 @@ static fmm_status run_mfma(fmm_ctx* ctx, DescEntry* e, const double* M, double* 
     }
     GraphEntry g;
     HIP_TRY(ctx, hipStreamBeginCapture(ctx->internal, hipStreamCaptureModeThreadLocal));
-    hipError_t le = launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, ctx->internal);
+    hipError_t le = launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, ctx->internal, pos, mass);
     hipError_t ce = hipStreamEndCapture(ctx->internal, &g.graph);
     if (le != hipSuccess) return hip_err(ctx, le, "launch_m2l_mfma (capture)");
     if (ce != hipSuccess) return hip_err(ctx, ce, "hipStreamEndCapture");
@@ -718,6 +722,41 @@ fmm_status fmm_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const do
     CHECK_OK(run_ref(ctx, e, false, M, L, s));
   } else {
     CHECK_OK(run_mfma(ctx, e, M, L, prec, pick_config(ctx, e, prec), s));
+  }
+  return mark_used(ctx, e, s);
+}
+
+fmm_status fmm_p2m_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const double* pos,
+                       const double* mass, int32_t ppc, double* M, double* L, fmm_precision prec,
+                       void* stream) {
+  CHECK_OK(check_ctx(ctx));
+  CHECK_OK(check_desc(ctx, desc, nsub));
+  CHECK_OK(check_ppc(ctx, ppc));
+  CHECK_OK(check_ptr(ctx, pos, "pos", nsub));
+  CHECK_OK(check_ptr(ctx, mass, "mass", nsub));
+  CHECK_OK(check_ptr(ctx, M, "M", nsub));
+  CHECK_OK(check_ptr(ctx, L, "L", nsub));
+  if (prec != FMM_FP64 && prec != FMM_SPLIT_FP32 && prec != FMM_FP64_HARMONIC)
+    return set_err(ctx, FMM_EINVAL, "unknown precision");
+  if (prec != FMM_FP64 && ctx->m2l_kernel == 1)
+    return set_err(ctx, FMM_EINVAL, "the reference kernel computes FMM_FP64 only");
+  if (ctx->m2l_kernel != 1 && ctx->tile_config >= 0 && !mfma_config_supports(ctx->tile_config, prec))
+    return set_err(ctx, FMM_EINVAL, "FMM_OPT_TILE_CONFIG selects a configuration of the other precision");
+  if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
+  if (nsub == 0) return FMM_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  DescEntry* e = nullptr;
+  CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
+  const int cfg = pick_config(ctx, e, prec);
+  const bool aligned = ((reinterpret_cast<uintptr_t>(pos) | reinterpret_cast<uintptr_t>(mass)) & 15u) == 0;
+  if (ctx->m2l_kernel != 1 && ppc == 8 && e->part_even && aligned && mfma_config_fusable(cfg)) {
+    CHECK_OK(run_mfma(ctx, e, M, L, prec, cfg, s, pos, mass));
+  } else {
+    HIP_TRY(ctx, launch_p2m(e->d_desc, nsub, e->d_ids, e->count, pos, mass, ppc, M, e->part_even, true, s));
+    if (ctx->m2l_kernel == 1) CHECK_OK(run_ref(ctx, e, false, M, L, s));
+    else CHECK_OK(run_mfma(ctx, e, M, L, prec, cfg, s));
   }
   return mark_used(ctx, e, s);
 }

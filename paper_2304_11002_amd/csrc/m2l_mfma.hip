@@ -23,9 +23,11 @@
 //   B: lane l -> block (l%16)/4, col l%4, k l/16
 //   D: lane l -> block (l%16)/4, col l%4, row l/16 (so: cell 4*((l%16)/4) + l/16)
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.h"
 #include "m2l_mfma.h"
+#include "p2m_common.h"
 
 namespace fmm {
 
@@ -252,7 +254,28 @@ constexpr int kBlThreads = 512;
 // (combinations of moment components of one order, per the round's plan), the
 // products run over the (p+1)^2 harmonic columns, and L is expanded to all C
 // components at the end through LDS.
-template <int P, bool PIPE, bool FULL = false, bool HARM = false>
+// Hook: at the top of round r, when the window buffer and the table buffers are
+// free (every wave is past the previous round's last barrier), hook.run() is
+// called if hook.wants(r, ROUNDS) (uniform over the workgroup); it may use
+// those buffers and must leave no LDS access in flight. Around it the sums so
+// far are parked in the sub-grid's own L slots (written only at the end), so
+// run() has the registers.
+struct NoHook {
+  __device__ bool wants(int, int) const { return false; }
+  __device__ void run() const {}
+};
+// the moments of the next item, at the top of round (workgroup index mod rounds)
+template <class F>
+struct MomentHook {
+  int next, count;
+  F moments;
+  __device__ bool wants(int r, int rounds) const {
+    return next < count && r == (int)(blockIdx.x % (unsigned)rounds);
+  }
+  __device__ void run() const { moments(next); }
+};
+
+template <int P, bool PIPE, bool FULL = false, bool HARM = false, class Hook = NoHook>
 __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* __restrict__ M,
                                                double* __restrict__ L,
                                                const double* __restrict__ Bl,
@@ -260,7 +283,8 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
                                                const uint32_t* __restrict__ touch, double2* smem,
                                                double* sB, const int4* s_off,
                                                const HRound* __restrict__ hround = nullptr,
-                                               const HExp* __restrict__ hexp = nullptr) {
+                                               const HExp* __restrict__ hexp = nullptr,
+                                               Hook hook = Hook()) {
   constexpr int C = ncomp(P);
   constexpr int CR = BlShape<P, HARM>::CR;
   constexpr int NG = BlShape<P, HARM>::NG;
@@ -297,6 +321,27 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
     cl0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(__ballot(on) & 0xffffffffu));
   }
   for (int r = 0; r < ROUNDS; ++r) {
+    if (hook.wants(r, ROUNDS)) {
+      double* park = L + d.l_off;
+      const int pxi = lane >> 4, pyi = (lane & 15) >> 2, pj = lane & 3;
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int tcell = ((t & 1) * 4 + pxi) + kBlock * ((t >> 1) * 4 + pyi) + kBlock * kBlock * wave;
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+          if (4 * g + pj < CR) park[(size_t)(4 * g + pj) * kNTarget + tcell] = acc[t][g];
+      }
+      asm volatile("" ::: "memory");   // the sums are reloaded, not kept in registers
+      hook.run();
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int tcell = ((t & 1) * 4 + pxi) + kBlock * ((t >> 1) * 4 + pyi) + kBlock * kBlock * wave;
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+          acc[t][g] = 4 * g + pj < CR ? park[(size_t)(4 * g + pj) * kNTarget + tcell] : 0.0;
+      }
+    }
     double s0, s1;
     const double *src0 = nullptr, *src1 = nullptr;
     if constexpr (HARM) {
@@ -317,6 +362,10 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
     // window: two halves of loads-then-stores keep the staging registers small
     constexpr int kStage = (kWinCells + NT - 1) / NT;
     constexpr int kHalf = (kStage + 1) / 2;
+    // with a hook, the staging indices are recomputed each round from an opaque
+    // copy of tid instead of being kept live across the rounds (and the hook)
+    int stid = tid;
+    if constexpr (!std::is_same_v<Hook, NoHook>) asm volatile("" : "+v"(stid));
 #pragma unroll
     for (int hb = 0; hb < 2; ++hb) {
       double2 v[kHalf];
@@ -326,7 +375,7 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
         bool on[kHalf];
 #pragma unroll
         for (int i = 0; i < kHalf; ++i) {
-          const int c = tid + (hb * kHalf + i) * NT;
+          const int c = stid + (hb * kHalf + i) * NT;
           v[i] = make_double2(0.0, 0.0);
           const int wx = c % kWin, wy = (c / kWin) % kWin, wz = c / (kWin * kWin);
           const int jx = wx + kWin0, jy = wy + kWin0, jz = wz + kWin0;
@@ -349,7 +398,7 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
       } else {
 #pragma unroll
         for (int i = 0; i < kHalf; ++i) {
-          const int c = tid + (hb * kHalf + i) * NT;
+          const int c = stid + (hb * kHalf + i) * NT;
           v[i] = make_double2(0.0, 0.0);
           if (hb * kHalf + i < kStage && c < kWinCells) {
             const int wx = c % kWin, wy = (c / kWin) % kWin, wz = c / (kWin * kWin);
@@ -365,7 +414,7 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
       if (hb == 0) __syncthreads();   // previous round's reads of smem and sB are done
 #pragma unroll
       for (int i = 0; i < kHalf; ++i) {
-        const int c = tid + (hb * kHalf + i) * NT;
+        const int c = stid + (hb * kHalf + i) * NT;
         if (hb * kHalf + i < kStage && c < kWinCells) smem[c] = make_double2(v[i].x * s0, v[i].y * s1);
       }
     }
@@ -554,49 +603,88 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
   }
 }
 
-template <bool PIPE, bool HARM = false>
+// FUSE: the kernel computes each sub-grid's moments itself (the frame rows
+// holding the reachable window, 8 particles per cell, written to M as the P2M
+// kernel writes them) before that sub-grid's M2L reads them. A workgroup takes
+// its next item when it starts an item and computes the next item's moments at
+// the top of round (workgroup index mod rounds) of the current one, so at any
+// time only about 1/rounds of the workgroups are in their HBM-bound moment
+// phase while the others keep the matrix cores busy. Only the first item's
+// moments are computed before any M2L. The moments are written and read by the
+// same workgroup, with barriers between.
+template <bool PIPE, bool HARM = false, bool FUSE = false>
 __global__ void __launch_bounds__(kBlThreads) m2l_fwd_bl_kernel(
     const WorkItem* __restrict__ items, int count, unsigned* __restrict__ counter,
-    const DevDesc* __restrict__ desc, const double* __restrict__ M, double* __restrict__ L,
+    const DevDesc* __restrict__ desc, const double* M, double* __restrict__ L,
     const double* __restrict__ B2, const double* __restrict__ B3, const double* __restrict__ B4,
     const int* __restrict__ lds_off, const uint32_t* __restrict__ touch,
     const HRound* __restrict__ hr2, const HRound* __restrict__ hr3, const HRound* __restrict__ hr4,
-    const HExp* __restrict__ he2, const HExp* __restrict__ he3, const HExp* __restrict__ he4) {
+    const HExp* __restrict__ he2, const HExp* __restrict__ he3, const HExp* __restrict__ he4,
+    const double* __restrict__ pos = nullptr, const double* __restrict__ mass = nullptr) {
   __shared__ double2 smem[kWinCells];
   __shared__ double sB[2 * kBlChunkMax];
   __shared__ int4 s_off[kQuads];
   __shared__ int s_item;
+  static_assert(kP2MRowsLds <= 2 * kWinCells && kBlThreads == kP2MRowsThreads,
+                "the moment phase fits the window buffer and the workgroup");
   if (PIPE) {
     const int4* off4 = reinterpret_cast<const int4*>(lds_off);
     for (int i = threadIdx.x; i < kQuads; i += blockDim.x) s_off[i] = off4[i];
   }
+  // moments of item `it` into M (the window buffer is free whenever this runs)
+  auto moments = [&](int it) __attribute__((always_inline)) {
+    const DevDesc dn = desc[items[it].sub];
+    double* Mw = const_cast<double*>(M);
+    double* lds = reinterpret_cast<double*>(smem);
+    switch (dn.p) {
+      case 2: p2m_window_rows<2>(dn, pos, mass, Mw, lds); break;
+      case 3: p2m_window_rows<3>(dn, pos, mass, Mw, lds); break;
+      case 4: p2m_window_rows<4>(dn, pos, mass, Mw, lds); break;
+      default: break;
+    }
+  };
+  int cur = 0;
+  if constexpr (FUSE) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    cur = s_item;
+    __syncthreads();   // every thread holds cur before s_item is written again
+    if (cur < count) moments(cur);
+  }
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
     __syncthreads();
-    const int item = s_item;
+    // FUSE: s_item is the next item, whose moments are computed during this one
+    const int item = FUSE ? cur : s_item;
+    const int next = s_item;
     if (item >= count) break;
     const DevDesc d = desc[items[item].sub];
     const bool full = d.mask == kFullMask;
+    const auto hook = [&]() {
+      if constexpr (FUSE) return MomentHook<decltype(moments)>{next, count, moments};
+      else return NoHook{};
+    }();
     switch (d.p) {
       case 2:
         if (PIPE && full)
-          fwd_bl_subgrid<2, PIPE, true, HARM>(d, M, L, B2, lds_off, touch, smem, sB, s_off, hr2, he2);
+          fwd_bl_subgrid<2, PIPE, true, HARM>(d, M, L, B2, lds_off, touch, smem, sB, s_off, hr2, he2, hook);
         else
-          fwd_bl_subgrid<2, PIPE, false, HARM>(d, M, L, B2, lds_off, touch, smem, sB, s_off, hr2, he2);
+          fwd_bl_subgrid<2, PIPE, false, HARM>(d, M, L, B2, lds_off, touch, smem, sB, s_off, hr2, he2, hook);
         break;
       case 3:
         if (PIPE && full)
-          fwd_bl_subgrid<3, PIPE, true, HARM>(d, M, L, B3, lds_off, touch, smem, sB, s_off, hr3, he3);
+          fwd_bl_subgrid<3, PIPE, true, HARM>(d, M, L, B3, lds_off, touch, smem, sB, s_off, hr3, he3, hook);
         else
-          fwd_bl_subgrid<3, PIPE, false, HARM>(d, M, L, B3, lds_off, touch, smem, sB, s_off, hr3, he3);
+          fwd_bl_subgrid<3, PIPE, false, HARM>(d, M, L, B3, lds_off, touch, smem, sB, s_off, hr3, he3, hook);
         break;
       case 4:
         // (the p = 4 operand sets do not fit the registers of the pipelined loop)
-        fwd_bl_subgrid<4, false, false, HARM>(d, M, L, B4, lds_off, touch, smem, sB, s_off, hr4, he4);
+        fwd_bl_subgrid<4, false, false, HARM>(d, M, L, B4, lds_off, touch, smem, sB, s_off, hr4, he4, hook);
         break;
       default: break;
     }
-    __syncthreads();
+    __syncthreads();   // every thread has read s_item; the item's LDS use is done
+    cur = next;
   }
 }
 
@@ -1619,18 +1707,31 @@ int mfma_default_config(fmm_precision prec) {
   return 0;
 }
 
+bool mfma_config_fusable(int cfg) { return cfg >= 0 && cfg < kNumConfigs && kConfigs[cfg].ldstab > 0; }
+
 hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc* d_desc,
                            const double* M, double* L, fmm_precision prec, int cfg,
-                           hipStream_t s) {
+                           hipStream_t s, const double* pos, const double* mass) {
   if (w.count == 0) return hipSuccess;
   if (!mfma_config_supports(cfg, prec)) return hipErrorInvalidValue;
+  const bool fuse = pos != nullptr;
+  if (fuse && (!mfma_config_fusable(cfg) || mass == nullptr)) return hipErrorInvalidValue;
   const int grid = std::min(t.num_cu, w.count);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, w.counter);
   const Config& c = kConfigs[cfg];
+  const HRound* nr = nullptr;
+  const HExp* ne = nullptr;
+#define BL_LAUNCH(PIPEV, HARMV, FUSEV, B, HR, HE)                                                    \
+  hipLaunchKernelGGL((m2l_fwd_bl_kernel<PIPEV, HARMV, FUSEV>), dim3(grid), dim3(kBlThreads), 0, s,   \
+                     w.items, w.count, w.counter, d_desc, M, L, B[2], B[3], B[4], t.lds_off, t.touch, \
+                     HR[0], HR[1], HR[2], HE[0], HE[1], HE[2], pos, mass)
+  const HRound* hr[3] = {t.hround[2], t.hround[3], t.hround[4]};
+  const HExp* he[3] = {t.hexp[2], t.hexp[3], t.hexp[4]};
+  const HRound* hr0[3] = {nr, nr, nr};
+  const HExp* he0[3] = {ne, ne, ne};
   if (c.prec == FMM_FP64_HARMONIC) {
-    hipLaunchKernelGGL((m2l_fwd_bl_kernel<true, true>), dim3(grid), dim3(kBlThreads), 0, s, w.items,
-                       w.count, w.counter, d_desc, M, L, t.fwdh[2], t.fwdh[3], t.fwdh[4], t.lds_off,
-                       t.touch, t.hround[2], t.hround[3], t.hround[4], t.hexp[2], t.hexp[3], t.hexp[4]);
+    if (fuse) BL_LAUNCH(true, true, true, t.fwdh, hr, he);
+    else BL_LAUNCH(true, true, false, t.fwdh, hr, he);
     return hipGetLastError();
   }
   if (c.prec == FMM_SPLIT_FP32) {
@@ -1640,18 +1741,13 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
     return hipGetLastError();
   }
   if (c.ldstab) {
-    const HRound* nr = nullptr;
-    const HExp* ne = nullptr;
-    if (c.ldstab == 2)
-      hipLaunchKernelGGL((m2l_fwd_bl_kernel<true, false>), dim3(grid), dim3(kBlThreads), 0, s, w.items,
-                         w.count, w.counter, d_desc, M, L, t.fwdl[2], t.fwdl[3], t.fwdl[4], t.lds_off,
-                         t.touch, nr, nr, nr, ne, ne, ne);
-    else
-      hipLaunchKernelGGL((m2l_fwd_bl_kernel<false, false>), dim3(grid), dim3(kBlThreads), 0, s, w.items,
-                         w.count, w.counter, d_desc, M, L, t.fwdl[2], t.fwdl[3], t.fwdl[4], t.lds_off,
-                         t.touch, nr, nr, nr, ne, ne, ne);
+    if (c.ldstab == 2 && fuse) BL_LAUNCH(true, false, true, t.fwdl, hr0, he0);
+    else if (c.ldstab == 2) BL_LAUNCH(true, false, false, t.fwdl, hr0, he0);
+    else if (fuse) BL_LAUNCH(false, false, true, t.fwdl, hr0, he0);
+    else BL_LAUNCH(false, false, false, t.fwdl, hr0, he0);
     return hipGetLastError();
   }
+#undef BL_LAUNCH
 #define FWD_LAUNCH(W, PFV)                                                                         \
   hipLaunchKernelGGL((m2l_fwd_kernel<W, PFV>), dim3(grid), dim3(W * 64), 0, s, w.items, w.count,   \
                      w.counter, d_desc, M, L, t.fwd[2], t.fwd[3], t.fwd[4], t.lds_off, t.touch)

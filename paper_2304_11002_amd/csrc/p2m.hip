@@ -7,6 +7,7 @@
 // The paper approximates each leaf cell by a monopole at its centre (Sec. IV-C,
 // "Octo-Tiger"); that is the a = 0 case of these moments.
 #include "kernels.h"
+#include "p2m_common.h"
 
 namespace fmm {
 
@@ -21,23 +22,6 @@ static_assert(kNCell % kP2MThreads == 0, "cells per block");
 __device__ __forceinline__ bool in_window(int cell) {
   const unsigned y = (cell / kFrame) % kFrame - kWin0, z = cell / (kFrame * kFrame) - kWin0;
   return y < (unsigned)kWin && z < (unsigned)kWin;
-}
-
-template <int P>
-__device__ __forceinline__ void monomials(double ax, double ay, double az, double* out) {
-  double px[P + 1], py[P + 1], pz[P + 1];
-  px[0] = py[0] = pz[0] = 1.0;
-#pragma unroll
-  for (int i = 1; i <= P; ++i) {
-    px[i] = px[i - 1] * ax;
-    py[i] = py[i - 1] * ay;
-    pz[i] = pz[i - 1] * az;
-  }
-#pragma unroll
-  for (int c = 0; c < ncomp(P); ++c) {
-    const MI k = mi_of(c);
-    out[c] = px[k.x] * py[k.y] * pz[k.z] * (inv_fact(k.x) * inv_fact(k.y) * inv_fact(k.z));
-  }
 }
 
 template <int P>
@@ -60,12 +44,8 @@ __device__ void p2m_cell(const DevDesc& d, const double* __restrict__ pos,
   for (int c = 0; c < C; ++c) acc[c] = 0.0;
   const int64_t p0 = d.part_off + (int64_t)cell * ppc;
   for (int i = 0; i < ppc; ++i) {
-    const double m = mass[p0 + i];
     const double* y = pos + 3 * (p0 + i);
-    double mono[C];
-    monomials<P>(y[0] - cx, y[1] - cy, y[2] - cz, mono);
-#pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = __builtin_fma(m, mono[c], acc[c]);
+    p2m_accumulate<P>(mass[p0 + i], y[0] - cx, y[1] - cy, y[2] - cz, acc);
   }
 #pragma unroll
   for (int c = 0; c < C; ++c) out[(size_t)c * kNCell] = acc[c];
@@ -222,13 +202,8 @@ __global__ void __launch_bounds__(kT8) p2m8_kernel(const DevDesc* __restrict__ d
       for (int c = 0; c < C; ++c) acc[c] = 0.0;
       const double* y = s_pos + tid * kPosStride;
 #pragma unroll 2
-      for (int i = 0; i < kPpc8; ++i) {
-        const double m = s_mass[tid * kPpc8 + i];
-        double mono[C];
-        monomials<P>(y[3 * i] - cx, y[3 * i + 1] - cy, y[3 * i + 2] - cz, mono);
-#pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] = __builtin_fma(m, mono[c], acc[c]);
-      }
+      for (int i = 0; i < kPpc8; ++i)
+        p2m_accumulate<P>(s_mass[tid * kPpc8 + i], y[3 * i] - cx, y[3 * i + 1] - cy, y[3 * i + 2] - cz, acc);
 #pragma unroll
       for (int c = 0; c < C; ++c) out[(size_t)c * kNCell] = acc[c];
     }

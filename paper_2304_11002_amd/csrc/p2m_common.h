@@ -1,0 +1,187 @@
+// Leaf moments of one cell (Sec. IV-C, the leaves of the bottom-up pass of
+// Sec. VII-C), shared by the P2M kernels and by the matrix-core kernel that
+// computes each sub-grid's moments itself before its M2L.
+//
+//   M_k(j) = sum_i m_i a_i^k / k!,   a_i = y_i - c_j
+#pragma once
+
+#include "fmm_common.h"
+
+namespace fmm {
+
+// out[c] = a^k / k! for the graded multi-index k of component c
+template <int P>
+__device__ __forceinline__ void monomials(double ax, double ay, double az, double* out) {
+  double px[P + 1], py[P + 1], pz[P + 1];
+  px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+  for (int i = 1; i <= P; ++i) {
+    px[i] = px[i - 1] * ax;
+    py[i] = py[i - 1] * ay;
+    pz[i] = pz[i - 1] * az;
+  }
+#pragma unroll
+  for (int c = 0; c < ncomp(P); ++c) {
+    const MI k = mi_of(c);
+    out[c] = px[k.x] * py[k.y] * pz[k.z] * (inv_fact(k.x) * inv_fact(k.y) * inv_fact(k.z));
+  }
+}
+
+// acc[c - C0] += m a^k / k! for the components c in [C0, C1). The mass and the
+// factorials ride on the powers (xm_i = m ax^i / i!, yf_i = ay^i / i!,
+// zf_i = az^i / i!), so a component costs one product of an x and a y power
+// (shared by every kz) and one fma: 41 operations per particle for all 20
+// components at p = 3, against 89 with monomials(). Each component's value
+// does not depend on the range it is computed in.
+template <int P, int C0 = 0, int C1 = ncomp(P)>
+__device__ __forceinline__ void p2m_accumulate(double m, double ax, double ay, double az,
+                                               double* acc) {
+  constexpr int PO = C1 <= 1 ? 0 : order_of(C1 - 1);   // highest order needed
+  double xm[P + 1], yf[P + 1], zf[P + 1];
+  xm[0] = m;
+  yf[0] = zf[0] = 1.0;
+#pragma unroll
+  for (int i = 1; i <= PO; ++i) {
+    const double inv = 1.0 / i;   // exact for i = 1; folded at compile time
+    xm[i] = i == 1 ? xm[0] * ax : xm[i - 1] * (ax * inv);
+    yf[i] = i == 1 ? ay : yf[i - 1] * (ay * inv);
+    zf[i] = i == 1 ? az : zf[i - 1] * (az * inv);
+  }
+#pragma unroll
+  for (int c = C0; c < C1; ++c) {
+    const MI k = mi_of(c);
+    const double xy = k.y == 0 ? xm[k.x] : xm[k.x] * yf[k.y];
+    acc[c - C0] = k.z == 0 ? acc[c - C0] + xy : __builtin_fma(xy, zf[k.z], acc[c - C0]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One 512-thread workgroup computes the moments of a whole sub-grid's frame
+// rows (y, z) in [2, 22)^2 (all 24 cells of each row: they hold the reachable
+// window, the only cells M2L reads), 8 particles per cell, in steps of half a
+// z plane's rows (240 cells, contiguous in memory). A step's particles are
+// read with coalesced 16-byte loads and staged through LDS (cell stride padded
+// to 25 doubles); two register sets take turns, so the loads of step k + 2 are
+// in flight while step k's moments are computed and step k + 1's loads land.
+// Each cell is shared by two waves: even waves sum the components of orders
+// below p, odd waves those of order p, so a thread holds at most 20 sums and
+// two sets of 8 loads (this runs inside a kernel with registers of its own).
+// Cells of absent blocks get zero moments and their particles are not read
+// (their loads read the always present centre cell instead, and are dropped).
+// Needs 16-byte aligned particle blocks (even part_off) and kP2MRowsLds
+// doubles of LDS.
+// ---------------------------------------------------------------------------
+constexpr int kRowsPlane = kWin * kFrame;                          // 480 cells per z plane
+constexpr int kRowsStep = kRowsPlane / 2;                          // 240 cells per step
+constexpr int kRowsSteps = 2 * kWin;                               // 40
+constexpr int kRowsStride = 3 * 8 + 1;                             // LDS doubles per cell
+constexpr int kP2MRowsLds = kRowsStep * (kRowsStride + 8);         // 7920 doubles
+constexpr int kP2MRowsThreads = 512;
+
+template <int P, int C0, int C1>
+__device__ __forceinline__ void p2m_rows_cell(const DevDesc& d, double h, const double* s_pos,
+                                              const double* s_mass, int lc, int jx, int jy, int jz,
+                                              double* M) {
+  constexpr int CP = C1 - C0;
+  double acc[CP];
+#pragma unroll
+  for (int c = 0; c < CP; ++c) acc[c] = 0.0;
+  if (block_present(d.mask, jx, jy, jz)) {
+    const double cx = (jx + 0.5) * h, cy = (jy + 0.5) * h, cz = (jz + 0.5) * h;
+    const double* y = s_pos + lc * kRowsStride;
+#pragma unroll 1
+    for (int i = 0; i < 8; ++i)
+      p2m_accumulate<P, C0, C1>(s_mass[lc * 8 + i], y[3 * i] - cx, y[3 * i + 1] - cy, y[3 * i + 2] - cz, acc);
+  }
+  double* out = M + d.m_off + jx + kFrame * jy + kFrame * kFrame * jz;
+#pragma unroll
+  for (int c = 0; c < CP; ++c) out[(size_t)(C0 + c) * kNCell] = acc[c];
+}
+
+template <int P>
+__device__ __forceinline__ void p2m_window_rows(const DevDesc& d, const double* __restrict__ pos,
+                                                const double* __restrict__ mass, double* M,
+                                                double* lds) {
+  constexpr int NT = kP2MRowsThreads;
+  constexpr int NPC = kRowsStep * 12, NMC = kRowsStep * 4;   // 16-byte chunks per step
+  constexpr int NP = (NPC + NT - 1) / NT;                    // position loads per thread (6)
+  constexpr int NM = (NMC + NT - 1) / NT;                    // mass loads per thread (2)
+  static_assert(2 * kRowsStep <= NT && kRowsSteps % 2 == 0, "two threads per cell, steps in pairs");
+  double* s_pos = lds;
+  double* s_mass = lds + kRowsStep * kRowsStride;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lc = (wave >> 1) * 64 + (tid & 63);   // this thread's cell in the step
+  const bool high = wave & 1;                     // order p (odd waves) or the lower orders
+  const double h = ldexp(1.0, -d.log2_inv_h);
+  const bool full = d.mask == kFullMask;
+  const int centre = kBlock * (1 + kFrame + kFrame * kFrame);   // cell (8, 8, 8)
+  const double2* pcentre = reinterpret_cast<const double2*>(pos + 3 * (d.part_off + (int64_t)centre * 8));
+  const double2* mcentre = reinterpret_cast<const double2*>(mass + d.part_off + (int64_t)centre * 8);
+  // step s: z plane kWin0 + s / 2, its rows' cells [r0, r0 + 240) with r0 = (s % 2) * 240
+  auto issue = [&](int step, double2* rp, double2* rm) {
+    const int z = kWin0 + (step >> 1), r0 = (step & 1) * kRowsStep;
+    const int base = z * kFrame * kFrame + kWin0 * kFrame + r0;    // the step's first cell
+    const uint32_t pm = (d.mask >> (9 * (z / kBlock))) & 511u;     // the plane's 3 x 3 blocks
+    const double2* ps = reinterpret_cast<const double2*>(pos + 3 * (d.part_off + (int64_t)base * 8));
+    const double2* ms = reinterpret_cast<const double2*>(mass + d.part_off + (int64_t)base * 8);
+    int t = tid;
+    asm volatile("" : "+v"(t));   // recomputed per step, not kept live
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int v = t + i * NT, r = r0 + v / 12;
+      const bool on = v < NPC && (full || ((pm >> ((r % kFrame) / kBlock + 3 * ((kWin0 + r / kFrame) / kBlock))) & 1u));
+      const double2 x = *(on ? ps + v : pcentre);
+      rp[i] = on ? x : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+      const int v = t + i * NT, r = r0 + v / 4;
+      const bool on = v < NMC && (full || ((pm >> ((r % kFrame) / kBlock + 3 * ((kWin0 + r / kFrame) / kBlock))) & 1u));
+      const double2 x = *(on ? ms + v : mcentre);
+      rm[i] = on ? x : make_double2(0.0, 0.0);
+    }
+  };
+  // step's loads (landed in rp, rm) to LDS, the loads of step + 2 into the same
+  // registers, then step's moments
+  auto run = [&](int step, double2* rp, double2* rm) {
+    __syncthreads();   // earlier readers of the LDS buffer are done
+    int t = tid;
+    asm volatile("" : "+v"(t));
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int v = t + i * NT;
+      if (v < NPC) {
+        double* dst = s_pos + (v / 12) * kRowsStride + 2 * (v % 12);
+        dst[0] = rp[i].x;
+        dst[1] = rp[i].y;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+      const int v = t + i * NT;
+      if (v < NMC) {
+        s_mass[2 * v] = rm[i].x;
+        s_mass[2 * v + 1] = rm[i].y;
+      }
+    }
+    __syncthreads();
+    if (step + 2 < kRowsSteps) issue(step + 2, rp, rm);
+    if (lc < kRowsStep) {
+      const int r = (step & 1) * kRowsStep + lc;
+      const int jx = r % kFrame, jy = kWin0 + r / kFrame, jz = kWin0 + (step >> 1);
+      constexpr int CL = ncomp(P - 1);
+      if (high) p2m_rows_cell<P, CL, ncomp(P)>(d, h, s_pos, s_mass, lc, jx, jy, jz, M);
+      else p2m_rows_cell<P, 0, CL>(d, h, s_pos, s_mass, lc, jx, jy, jz, M);
+    }
+  };
+  double2 ap[NP], am[NM], bp[NP], bm[NM];
+  issue(0, ap, am);
+  issue(1, bp, bm);
+  for (int step = 0; step < kRowsSteps; step += 2) {
+    run(step, ap, am);
+    run(step + 1, bp, bm);
+  }
+}
+
+}  // namespace fmm

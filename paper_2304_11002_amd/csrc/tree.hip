@@ -32,6 +32,7 @@
 
 #include "kernels.h"
 #include "m2l_mfma.h"
+#include "p2m_common.h"
 
 namespace fmm {
 
@@ -103,14 +104,7 @@ __global__ void __launch_bounds__(256) p2m_grid_kernel(const double* __restrict_
   for (int c = 0; c < C; ++c) acc[c] = 0.0;
   for (int i = 0; i < ppc; ++i) {
     const int64_t pi = j * ppc + i;
-    double px[P + 1], py[P + 1], pz[P + 1];
-    powers<P>(pos[3 * pi] - cx, pos[3 * pi + 1] - cy, pos[3 * pi + 2] - cz, px, py, pz);
-    const double m = mass[pi];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const MI k = mi_of(c);
-      acc[c] = __builtin_fma(m, px[k.x] * py[k.y] * pz[k.z], acc[c]);
-    }
+    p2m_accumulate<P>(mass[pi], pos[3 * pi] - cx, pos[3 * pi + 1] - cy, pos[3 * pi + 2] - cz, acc);
   }
 #pragma unroll
   for (int c = 0; c < C; ++c) M[c * n3 + j] = acc[c];

@@ -22,7 +22,7 @@ FULL_MASK = (1 << 27) - 1
 
 EXPORTS = [
     "fmm_create", "fmm_destroy", "fmm_status_string", "fmm_last_error", "fmm_set_option",
-    "fmm_stencil", "fmm_pair_count", "fmm_p2m", "fmm_m2l", "fmm_m2l_backward",
+    "fmm_stencil", "fmm_pair_count", "fmm_p2m", "fmm_m2l", "fmm_p2m_m2l", "fmm_m2l_backward",
     "fmm_p2m_backward", "fmm_stencil_tables", "fmm_autotune", "fmm_evaluate",
     "fmm_tree_size", "fmm_tree_upward", "fmm_tree_m2l", "fmm_tree_downward", "fmm_tree_evaluate",
     "fmm_tree_solve",
@@ -69,6 +69,7 @@ def load_library(path=LIB_PATH):
         "fmm_pair_count": ([vp, i64, ctypes.POINTER(i64)], i32),
         "fmm_p2m": ([vp, vp, i64, vp, vp, i32, vp, vp], i32),
         "fmm_m2l": ([vp, vp, i64, vp, vp, i32, vp], i32),
+        "fmm_p2m_m2l": ([vp, vp, i64, vp, vp, i32, vp, vp, i32, vp], i32),
         "fmm_m2l_backward": ([vp, vp, i64, vp, vp, vp], i32),
         "fmm_p2m_backward": ([vp, vp, i64, vp, i32, vp, vp, vp], i32),
         "fmm_stencil_tables": ([vp, i32, vp, vp], i32),
@@ -227,6 +228,12 @@ class Context:
         pd, n = _desc_ptr(desc)
         self._run(self.lib.fmm_m2l(self.handle, pd, n, _ptr(M), _ptr(L), int(precision),
                                    self._s(stream, n)))
+
+    def p2m_m2l(self, desc, pos, mass, ppc, M, L, precision=FMM_FP64, stream=None):
+        """P2M over the rows holding the reachable window, then M2L, in one launch."""
+        pd, n = _desc_ptr(desc)
+        self._run(self.lib.fmm_p2m_m2l(self.handle, pd, n, _ptr(pos), _ptr(mass), int(ppc), _ptr(M),
+                                       _ptr(L), int(precision), self._s(stream, n)))
 
     def m2l_backward(self, desc, dL, dM, stream=None):
         pd, n = _desc_ptr(desc)

@@ -100,7 +100,14 @@ def test_pointer_and_option_validation(hctx):
                  lambda: hctx.evaluate(desc, 8, 8, 0, 8, 8),
                  lambda: hctx.evaluate(desc, 8, 8, 65, 8, 8),
                  lambda: hctx.evaluate(desc, 8, 8, 8, 8, None),
-                 lambda: hctx.evaluate(desc, 8, 8, 8, 12, 8)):
+                 lambda: hctx.evaluate(desc, 8, 8, 8, 12, 8),
+                 lambda: hctx.p2m_m2l(desc, 8, 8, 0, 8, 8),            # ppc = 0
+                 lambda: hctx.p2m_m2l(desc, 8, 8, 65, 8, 8),
+                 lambda: hctx.p2m_m2l(desc, 0, 8, 8, 8, 8),
+                 lambda: hctx.p2m_m2l(desc, 8, 0, 8, 8, 8),
+                 lambda: hctx.p2m_m2l(desc, 8, 8, 8, 12, 8),           # misaligned M
+                 lambda: hctx.p2m_m2l(desc, 8, 8, 8, 8, None),
+                 lambda: hctx.p2m_m2l(desc, 8, 8, 8, 8, 8, precision=7)):
         with pytest.raises(fmm.FMMError) as e:
             call()
         assert e.value.status == fmm.FMM_EINVAL
@@ -115,6 +122,13 @@ def test_host_only_context_reports_unsupported_after_checks(hctx, lib):
     with pytest.raises(fmm.FMMError) as e:
         hctx.evaluate(desc, 8, 8, 8, 8, 8)
     assert e.value.status == fmm.FMM_EUNSUPPORTED
+    with pytest.raises(fmm.FMMError) as e:
+        hctx.p2m_m2l(desc, 8, 8, 8, 8, 8, precision=fmm.FMM_FP64_HARMONIC)
+    assert e.value.status == fmm.FMM_EUNSUPPORTED
+    for field, value in (("p", 5), ("mask", 0)):
+        with pytest.raises(fmm.FMMError) as e:
+            hctx.p2m_m2l(_bad(desc, field, value), 8, 8, 8, 8, 8)
+        assert e.value.status == fmm.FMM_EINVAL
     n = ctypes.c_int64(0)
     assert lib.fmm_m2l(hctx.handle, None, 0, None, None, 0, None) == fmm.FMM_EUNSUPPORTED
     assert lib.fmm_m2l(hctx.handle, None, -1, None, None, 0, None) == fmm.FMM_EINVAL
@@ -132,6 +146,7 @@ def test_harmonic_precision_checks(hctx):
     hctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 1)
     try:
         for call in (lambda: hctx.m2l(desc, 8, 8, precision=fmm.FMM_FP64_HARMONIC),
+                     lambda: hctx.p2m_m2l(desc, 8, 8, 8, 8, 8, precision=fmm.FMM_FP64_HARMONIC),
                      lambda: hctx.m2l_backward(desc, 8, 8)):
             with pytest.raises(fmm.FMMError) as e:
                 call()

@@ -1,0 +1,185 @@
+"""GPU parity of the fused P2M + M2L entry point (fmm_p2m_m2l) through the C ABI.
+
+The single launch must give, bit for bit, what fmm_p2m over the rows holding
+the reachable window followed by fmm_m2l gives: the same L, the same moments
+in those rows, and no write to any other cell of M. It is checked in every
+form it runs in (harmonic, and the two float64 configurations with staged
+tables) on batches with more sub-grids than the GPU has compute units, where
+workgroups compute the next sub-grid's moments in the middle of the current
+one's M2L, and on uneven batches, where the next sub-grid's order, spacing and
+mask differ from the current one's. Sampled sub-grids are checked against the
+oracle as well, at the tolerance of the other parity tests, and the cases that
+run as two launches (ppc != 8, split precision, the reference kernel) against
+the two separate calls.
+"""
+import numpy as np
+import pytest
+
+import synth
+from paper_2304_11002_amd import fmm
+
+from _gpu_helpers import (descriptors, ensure_library, moment_abs_scale, oracle_subgrid,
+                          particles, split_views, to_dev)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+ROWS = np.zeros((24, 24, 24), bool)          # [z][y][x]: rows (y, z) in [2, 22)^2, every x
+ROWS[2:22, 2:22, :] = True
+HARM_CFG, FP64_CFGS = 7, (0, 1)               # staged-table configurations
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    ensure_library()
+    c = fmm.Context(0)
+    yield c
+    c.close()
+
+
+def separate(ctx, torch, desc, dpos, dmass, ppc, m_el, l_el, prec):
+    M = torch.full((m_el,), float("nan"), dtype=torch.float64, device="cuda")
+    L = torch.full((l_el,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.set_option(fmm.FMM_OPT_P2M_WINDOW, 1)
+    try:
+        ctx.p2m(desc, dpos, dmass, ppc, M)
+    finally:
+        ctx.set_option(fmm.FMM_OPT_P2M_WINDOW, 0)
+    ctx.m2l(desc, M, L, prec)
+    return M, L
+
+
+def fused(ctx, torch, desc, dpos, dmass, ppc, m_el, l_el, prec):
+    M = torch.full((m_el,), float("nan"), dtype=torch.float64, device="cuda")
+    L = torch.full((l_el,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.p2m_m2l(desc, dpos, dmass, ppc, M, L, prec)
+    return M, L
+
+
+def assert_same(desc, Ms, Ls, Mf, Lf, what):
+    assert torch_equal(Ls, Lf), "%s: L differs" % what
+    for b, (vs, vf) in enumerate(zip(split_views(Ms.cpu().numpy(), desc, "M"),
+                                     split_views(Mf.cpu().numpy(), desc, "M"))):
+        assert np.array_equal(vs[:, ROWS], vf[:, ROWS]), "%s: M rows of sub-grid %d differ" % (what, b)
+        assert np.isnan(vf[:, ~ROWS]).all(), "%s: M written outside the rows, sub-grid %d" % (what, b)
+
+
+def torch_equal(a, b):
+    import torch as t
+    return bool(t.equal(a, b))
+
+
+def run_forms(ctx, torch, w, idx, forms):
+    desc, m_el, l_el = descriptors(w, idx)
+    pos, mass = particles(w, idx)
+    dpos, dmass = to_dev(pos), to_dev(mass)
+    out = {}
+    for prec, cfg in forms:
+        ctx.set_option(fmm.FMM_OPT_TILE_CONFIG, cfg)
+        try:
+            Ms, Ls = separate(ctx, torch, desc, dpos, dmass, w.ppc, m_el, l_el, prec)
+            Mf, Lf = fused(ctx, torch, desc, dpos, dmass, w.ppc, m_el, l_el, prec)
+            torch.cuda.synchronize()
+        finally:
+            ctx.set_option(fmm.FMM_OPT_TILE_CONFIG, -1)
+        assert_same(desc, Ms, Ls, Mf, Lf, "prec %d cfg %d" % (prec, cfg))
+        out[(prec, cfg)] = (Mf, Lf)
+    return desc, pos, mass, out
+
+
+def test_fused_uneven_batch_matches_the_separate_calls(ctx, torch):
+    # 600 sub-grids, p in {2,3,4}, h in {1,1/2,1/4}, random masks: more items than
+    # compute units, and consecutive items of different orders
+    w = synth.config(3, nsub=600)
+    assert len(set(w.p.tolist())) == 3
+    forms = [(fmm.FMM_FP64_HARMONIC, HARM_CFG)] + [(fmm.FMM_FP64, c) for c in FP64_CFGS]
+    desc, pos, mass, out = run_forms(ctx, torch, w, range(600), forms)
+    # and against the oracle on sampled sub-grids of every order
+    Lh = out[(fmm.FMM_FP64_HARMONIC, HARM_CFG)][1].cpu().numpy()
+    Mh = out[(fmm.FMM_FP64_HARMONIC, HARM_CFG)][0].cpu().numpy()
+    picks = [int(np.flatnonzero(w.p == p)[k]) for p in (2, 3, 4) for k in (0, -1)]
+    Lv, Mv = split_views(Lh, desc, "L"), split_views(Mh, desc, "M")
+    for b in picks:
+        Mo, Lo, La = oracle_subgrid(w, b, pos[b], mass[b])
+        err = np.abs(Lv[b] - Lo)
+        assert (err <= TOL * La).all(), "L of sub-grid %d (p=%d): worst %.3g" % (
+            b, w.p[b], np.max(err / np.maximum(La, 1e-300)))
+        Ma = moment_abs_scale(pos[b], mass[b], int(w.p[b]), w.h(b), int(w.mask[b]))
+        assert (np.abs(Mv[b][:, ROWS] - Mo[:, ROWS]) <= 1e-13 * Ma[:, ROWS]).all()
+
+
+def test_fused_uniform_batch_against_the_oracle(ctx, torch):
+    # 300 uniform p = 3 sub-grids of the 4096 workload (more than the compute units)
+    w = synth.config(2, nsub=300)
+    forms = [(fmm.FMM_FP64_HARMONIC, HARM_CFG), (fmm.FMM_FP64, 0)]
+    desc, pos, mass, out = run_forms(ctx, torch, w, range(300), forms)
+    for (prec, cfg), (_, Lf) in out.items():
+        Lv = split_views(Lf.cpu().numpy(), desc, "L")
+        for b in (0, 171, 299):
+            _, Lo, La = oracle_subgrid(w, b, pos[b], mass[b])
+            err = np.abs(Lv[b] - Lo)
+            assert (err <= TOL * La).all(), "prec %d cfg %d sub-grid %d: worst %.3g" % (
+                prec, cfg, b, np.max(err / np.maximum(La, 1e-300)))
+
+
+def test_fused_small_batch_and_graph_replays(ctx, torch):
+    # fewer sub-grids than compute units (every item is a workgroup's first), then
+    # replays of the cached graph: plain launches give the same bits, and doubled
+    # masses give exactly doubled moments and L (a power of two scales exactly)
+    w = synth.config(3, nsub=5)
+    desc, m_el, l_el = descriptors(w, range(5))
+    pos, mass = particles(w, range(5))
+    dpos, dmass = to_dev(pos), to_dev(mass)
+    prec = fmm.FMM_FP64_HARMONIC
+    Ms, Ls = separate(ctx, torch, desc, dpos, dmass, 8, m_el, l_el, prec)
+    M = torch.empty(m_el, dtype=torch.float64, device="cuda")
+    L = torch.empty(l_el, dtype=torch.float64, device="cuda")
+    results = []
+    for rep in range(3):
+        M.fill_(float("nan"))
+        L.fill_(float("nan"))
+        ctx.p2m_m2l(desc, dpos, dmass, 8, M, L, prec)
+        torch.cuda.synchronize()
+        results.append((M.clone(), L.clone()))
+    for Mf, Lf in results:
+        assert_same(desc, Ms, Ls, Mf, Lf, "graph replay")
+    ctx.set_option(fmm.FMM_OPT_USE_GRAPH, 0)
+    try:
+        Mn, Ln = fused(ctx, torch, desc, dpos, dmass, 8, m_el, l_el, prec)
+    finally:
+        ctx.set_option(fmm.FMM_OPT_USE_GRAPH, 1)
+    torch.cuda.synchronize()
+    assert_same(desc, Ms, Ls, Mn, Ln, "plain launch")
+    dmass.mul_(2.0)
+    M.fill_(float("nan"))
+    ctx.p2m_m2l(desc, dpos, dmass, 8, M, L, prec)
+    torch.cuda.synchronize()
+    assert torch.equal(L, 2.0 * Ls)
+    assert torch.equal(torch.nan_to_num(M, 0.0), torch.nan_to_num(2.0 * results[0][0], 0.0))
+
+
+@pytest.mark.parametrize("case", ["ppc5", "split", "reference"])
+def test_fused_entry_point_two_launch_cases(ctx, torch, case):
+    # the cases without the single launch give what the two calls give
+    w = synth.config(3, nsub=6)
+    if case == "ppc5":
+        w.ppc = 5
+    desc, m_el, l_el = descriptors(w, range(6))
+    pos, mass = particles(w, range(6))
+    dpos, dmass = to_dev(pos), to_dev(mass)
+    prec = {"ppc5": fmm.FMM_FP64_HARMONIC, "split": fmm.FMM_SPLIT_FP32, "reference": fmm.FMM_FP64}[case]
+    if case == "reference":
+        ctx.set_option(fmm.FMM_OPT_M2L_KERNEL, 1)
+    try:
+        Ms, Ls = separate(ctx, torch, desc, dpos, dmass, w.ppc, m_el, l_el, prec)
+        Mf, Lf = fused(ctx, torch, desc, dpos, dmass, w.ppc, m_el, l_el, prec)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(fmm.FMM_OPT_M2L_KERNEL, 0)
+    assert_same(desc, Ms, Ls, Mf, Lf, case)
