@@ -10,8 +10,11 @@ moments, over the frame rows that hold the reachable 20^3 window: the cells M2L
 reads) then M2L (moments -> local coefficients of the 512 targets of every
 sub-grid) in float64, computed in the harmonic (traceless) form: (p+1)^2 = 16
 folded moment components against 16 local columns, then expanded to all 20.
-`value` is cell-pair interactions per second over the whole step. The dense
-20 x 20 form of the same M2L is timed on the same moments as an extra.
+Both run in one persistent launch (fmm_p2m_m2l), each workgroup computing a
+sub-grid's moments during the M2L of the sub-grid before it. `value` is
+cell-pair interactions per second over the whole step. The same step as two
+launches (P2M, then the M2L-only kernel) and the dense 20 x 20 form of the
+M2L are timed as extras.
 
 The same run also measures, each on its own batch: the split-precision M2L
 (float32 matrix cores, hi/lo products) on the step's moments, with its error
@@ -40,8 +43,9 @@ METRIC = "M2L cell-pair interactions/s FP64 vs split-FP32 (<=1e-10 rel); fwd+bwd
 FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
 FP32_PEAK_TFLOPS = 157.3    # MI355X dense FP32 matrix peak
 HBM_PEAK_GBS = 8000.0
-M2L_SRC = os.path.join(ROOT, "paper_2304_11002_amd", "csrc", "m2l_mfma.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_fwd_uniform4096_p3_traffic.txt")
+# the step's kernel: the M2L kernel source and the moment phase it includes
+STEP_SRCS = [os.path.join(ROOT, "paper_2304_11002_amd", "csrc", f) for f in ("m2l_mfma.hip", "p2m_common.h")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "p2m_m2l_fused_uniform4096_p3_traffic.txt")
 
 
 def log(*a):
@@ -287,7 +291,7 @@ def read_traffic(launch_pairs):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(M2L_SRC, "rb").read()).hexdigest()[:16]
+    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in STEP_SRCS)).hexdigest()[:16]
     if kv.get("kernel_source_sha256_16") != sha:
         return None
     try:
@@ -343,7 +347,7 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic"}
 
-    # ---------------- the step: P2M + FP64 M2L on 4096 uniform p=3 sub-grids
+    # ---------------- the step: P2M + FP64 M2L on 4096 uniform p=3 sub-grids, one launch
     w = synth.config(2)
     desc, m_el, l_el = fmm.make_descriptors(w.p, w.log2_inv_h, w.mask)
     pairs = fmm.pair_count(desc)
@@ -352,44 +356,67 @@ def main():
     L = torch.empty(l_el, dtype=torch.float64, device="cuda")
     ctx.p2m(desc, pos, mass, 8, M)
     tuned = ctx.autotune(desc, M, L, fmm.FMM_FP64_HARMONIC)    # configuration for this batch
-    ctx.m2l(desc, M, L, fmm.FMM_FP64_HARMONIC)                 # graph capture, untimed
+    ctx.p2m_m2l(desc, pos, mass, 8, M, L, fmm.FMM_FP64_HARMONIC)   # graph capture, untimed
 
     def step(ev, i):
         if ev: ev[0].record()
-        ctx.p2m(desc, pos, mass, 8, M)
+        ctx.p2m_m2l(desc, pos, mass, 8, M, L, fmm.FMM_FP64_HARMONIC)
         if ev: ev[1].record()
-        ctx.m2l(desc, M, L, fmm.FMM_FP64_HARMONIC)
-        if ev: ev[2].record()
 
-    wall, seg = timed(torch, step, K, W, marks=2)
+    wall, seg = timed(torch, step, K, W, marks=1)
     ms_step = wall / K * 1e3
-    p2m_ms, m2l_ms = seg[:, 0].mean(), seg[:, 1].mean()
+    fused_ms = seg[:, 0].mean()
     out["value"] = pairs / (wall / K)
     out["ms_per_step"] = ms_step
+    log("step %.3f ms (one launch, %.3f ms by events): %.4g pairs/s" % (ms_step, fused_ms, out["value"]))
+
+    # the same step as two launches: P2M, then the M2L-only kernel (same bits)
+    Lu = torch.empty_like(L)
+    ctx.m2l(desc, M, Lu, fmm.FMM_FP64_HARMONIC)                # graph capture, untimed
+
+    def step_two(ev, i):
+        if ev: ev[0].record()
+        ctx.p2m(desc, pos, mass, 8, M)
+        if ev: ev[1].record()
+        ctx.m2l(desc, M, Lu, fmm.FMM_FP64_HARMONIC)
+        if ev: ev[2].record()
+
+    wall_two, seg_two = timed(torch, step_two, K, W, marks=2)
+    p2m_ms, m2l_ms = seg_two[:, 0].mean(), seg_two[:, 1].mean()
+    assert bool(torch.equal(L, Lu)), "the one-launch step differs from P2M + M2L"
+    del Lu
     import torch.version as tv
     out["config"] = {"workload": "uniform_4096_p3", "subgrids": w.nsub, "p": 3, "components": 20,
                      "h": 1.0, "particles_per_cell": 8, "stencil_offsets": 892,
                      "pairs_per_step": pairs,
-                     "step": "P2M over the frame rows holding the reachable 20^3 window + M2L (float64, harmonic form)",
-                     "p2m_ms": float(p2m_ms), "m2l_ms": float(m2l_ms),
-                     "m2l_ms_median": float(np.median(seg[:, 1])), "m2l_ms_min": float(seg[:, 1].min()),
+                     "step": "P2M over the frame rows holding the reachable 20^3 window + M2L (float64, "
+                             "harmonic form), one persistent launch (fmm_p2m_m2l)",
+                     "step_kernel_ms": float(fused_ms),
+                     "two_launch_step": {"p2m_ms": float(p2m_ms), "m2l_ms": float(m2l_ms),
+                                         "step_ms": float(wall_two / K * 1e3),
+                                         "m2l_ms_median": float(np.median(seg_two[:, 1])),
+                                         "m2l_ms_min": float(seg_two[:, 1].min())},
                      "autotune_choice": tuned, "device": torch.cuda.get_device_name(0),
                      "hip": getattr(tv, "hip", None), "torch": torch.__version__}
-    log("step %.3f ms (P2M %.3f, M2L %.3f): %.4g pairs/s" % (ms_step, p2m_ms, m2l_ms, out["value"]))
+    log("two launches: %.3f ms (P2M %.3f, M2L %.3f)" % (wall_two / K * 1e3, p2m_ms, m2l_ms))
     fl_exec = pairs * harmonic_flops_per_pair(3)      # executed matrix-core flops
     fl_dense = pairs * flops_per_pair(3)              # the dense 2 C^2 form
-    achieved = fl_exec / (m2l_ms * 1e-3) / 1e12
+    achieved = fl_exec / (fused_ms * 1e-3) / 1e12
     traffic = read_traffic(pairs)
     out["roofline"] = {"bound": "mfma",
-                       "kernel": "m2l_fwd_bl_kernel<PIPE, HARM> (v_mfma_f64_4x4x4, harmonic form, "
-                                 "configuration %d)" % tuned,
+                       "kernel": "m2l_fwd_bl_kernel<PIPE, HARM, FUSE> (v_mfma_f64_4x4x4, harmonic form, "
+                                 "configuration %d, with the P2M moment phase inside)" % tuned,
                        "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                        "flops_per_launch": fl_exec, "flops_per_pair": harmonic_flops_per_pair(3),
-                       "fp64_dense_equivalent_tflops": fl_dense / (m2l_ms * 1e-3) / 1e12,
-                       "dense_flops_per_pair": flops_per_pair(3)}
-    log("M2L FP64 harmonic: %.2f executed TFLOP/s (%.1f%% of %.1f); %.2f TFLOP/s dense-equivalent"
-        % (achieved, 100 * achieved / FP64_PEAK_TFLOPS, FP64_PEAK_TFLOPS, fl_dense / (m2l_ms * 1e-3) / 1e12))
+                       "fp64_dense_equivalent_tflops": fl_dense / (fused_ms * 1e-3) / 1e12,
+                       "dense_flops_per_pair": flops_per_pair(3),
+                       "m2l_only_kernel": {"ms": float(m2l_ms),
+                                           "achieved": fl_exec / (m2l_ms * 1e-3) / 1e12,
+                                           "frac": fl_exec / (m2l_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}}
+    log("step kernel: %.2f executed TFLOP/s of M2L (%.1f%% of %.1f); M2L-only kernel %.2f (%.1f%%)"
+        % (achieved, 100 * achieved / FP64_PEAK_TFLOPS, FP64_PEAK_TFLOPS,
+           fl_exec / (m2l_ms * 1e-3) / 1e12, 100 * fl_exec / (m2l_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS))
 
     assert bool(torch.isfinite(L).all())
     out["parity"] = ("against the oracle in tests/test_gpu_fullsize.py (this workload, sampled sub-grids) "
@@ -490,8 +517,7 @@ def main():
 
         def step_fb(ev, i):
             if ev: ev[0].record()
-            ctx.p2m(desc=d5, pos=pos5, mass=mass5, ppc=8, M=M5)
-            ctx.m2l(d5, M5, L5, fmm.FMM_FP64_HARMONIC)
+            ctx.p2m_m2l(d5, pos5, mass5, 8, M5, L5, fmm.FMM_FP64_HARMONIC)
             if ev: ev[1].record()
             ctx.m2l_backward(d5, wt, dM5)      # dLoss/dL = w for loss = sum w . L
             ctx.p2m_backward(d5, pos5, 8, dM5, dm5)
@@ -504,7 +530,7 @@ def main():
         _, seg_fbd = timed(torch, step_fb, max(3, K // 2), 1, marks=2)
         bwd_dense_ms = seg_fbd[:, 1].mean()
         out["fwd_bwd"] = {"workload": "grad_2048_p3", "subgrids": w5.nsub, "pairs": pairs5,
-                          "forward": "P2M + M2L (harmonic form)",
+                          "forward": "P2M + M2L (harmonic form), one launch (fmm_p2m_m2l)",
                           "backward": "M2L adjoint (harmonic form) + P2M adjoint",
                           "bwd_ms_dense_adjoint": float(bwd_dense_ms),
                           "fwd_ms": float(fwd_ms), "bwd_ms": float(bwd_ms),
@@ -570,8 +596,7 @@ def main():
 
         def step_one(ev, i):
             if ev: ev[0].record()
-            ctx.p2m(d1, pos1, mass1, 8, M1)
-            ctx.m2l(d1, M1, L1, fmm.FMM_FP64_HARMONIC)
+            ctx.p2m_m2l(d1, pos1, mass1, 8, M1, L1, fmm.FMM_FP64_HARMONIC)
             if ev: ev[1].record()
 
         _, seg1 = timed(torch, step_one, K, W, marks=1)

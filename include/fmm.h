@@ -146,8 +146,9 @@ fmm_status fmm_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
  * FMM_OPT_P2M_WINDOW is set to. Each workgroup computes a sub-grid's
  * moments itself, during the M2L of the sub-grid before it, so the
  * HBM-bound moment work of some workgroups overlaps the matrix work of the
- * others. The single launch needs ppc = 8, 16-byte aligned pos and mass,
- * even part_off and a configuration with LDS-staged tables (every
+ * others. The single launch is used for batches of more sub-grids than the
+ * GPU has compute units, with ppc = 8, 16-byte aligned pos and mass, even
+ * part_off and a configuration with LDS-staged tables (every
  * FMM_FP64_HARMONIC configuration; FMM_FP64 configurations 0 and 1);
  * otherwise, and with FMM_OPT_M2L_KERNEL = 1, the call runs the two steps
  * one after the other, with the same results. */

@@ -751,7 +751,10 @@ fmm_status fmm_p2m_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, cons
   CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
   const int cfg = pick_config(ctx, e, prec);
   const bool aligned = ((reinterpret_cast<uintptr_t>(pos) | reinterpret_cast<uintptr_t>(mass)) & 15u) == 0;
-  if (ctx->m2l_kernel != 1 && ppc == 8 && e->part_even && aligned && mfma_config_fusable(cfg)) {
+  // one launch pays off once workgroups take several sub-grids (with at most one
+  // each, every moment phase runs at the start, on one workgroup per sub-grid)
+  if (ctx->m2l_kernel != 1 && ppc == 8 && e->part_even && aligned && mfma_config_fusable(cfg) &&
+      nsub > ctx->mfma.num_cu) {
     CHECK_OK(run_mfma(ctx, e, M, L, prec, cfg, s, pos, mass));
   } else {
     HIP_TRY(ctx, launch_p2m(e->d_desc, nsub, e->d_ids, e->count, pos, mass, ppc, M, e->part_even, true, s));

@@ -104,6 +104,15 @@ def test_uniform_4096_fp64_and_split(ctx, torch):
     torch.cuda.synchronize()
     assert torch.isfinite(Lh).all() and torch.equal(Lh, Lh2)
     check_sampled(w, desc, Lh, [0, 1, 2047, 4095])
+    # the step as the bench times it: one launch (fmm_p2m_m2l), replayed from its
+    # graph: the same moments in the rows and the same L, bit for bit
+    Mf = torch.full_like(M, float("nan"))
+    Lf = torch.empty_like(L)
+    for _ in range(2):
+        ctx.p2m_m2l(desc, pos, mass, 8, Mf, Lf, fmm.FMM_FP64_HARMONIC)
+    torch.cuda.synchronize()
+    assert torch.equal(Lf, Lh)
+    assert torch.equal(torch.nan_to_num(Mf, 0.0), torch.nan_to_num(Mw, 0.0))
 
 
 def test_uniform_4096_evaluate(ctx, torch):

@@ -128,13 +128,13 @@ def test_fused_uniform_batch_against_the_oracle(ctx, torch):
                 prec, cfg, b, np.max(err / np.maximum(La, 1e-300)))
 
 
-def test_fused_small_batch_and_graph_replays(ctx, torch):
-    # fewer sub-grids than compute units (every item is a workgroup's first), then
-    # replays of the cached graph: plain launches give the same bits, and doubled
-    # masses give exactly doubled moments and L (a power of two scales exactly)
-    w = synth.config(3, nsub=5)
-    desc, m_el, l_el = descriptors(w, range(5))
-    pos, mass = particles(w, range(5))
+def test_fused_graph_replays(ctx, torch):
+    # replays of the cached graph of the single launch: plain launches give the
+    # same bits, and doubled masses give exactly doubled moments and L (a power of
+    # two scales exactly)
+    w = synth.config(3, nsub=300)
+    desc, m_el, l_el = descriptors(w, range(300))
+    pos, mass = particles(w, range(300))
     dpos, dmass = to_dev(pos), to_dev(mass)
     prec = fmm.FMM_FP64_HARMONIC
     Ms, Ls = separate(ctx, torch, desc, dpos, dmass, 8, m_el, l_el, prec)
@@ -164,16 +164,20 @@ def test_fused_small_batch_and_graph_replays(ctx, torch):
     assert torch.equal(torch.nan_to_num(M, 0.0), torch.nan_to_num(2.0 * results[0][0], 0.0))
 
 
-@pytest.mark.parametrize("case", ["ppc5", "split", "reference"])
+@pytest.mark.parametrize("case", ["small", "ppc5", "split", "reference"])
 def test_fused_entry_point_two_launch_cases(ctx, torch, case):
-    # the cases without the single launch give what the two calls give
-    w = synth.config(3, nsub=6)
+    # the cases without the single launch give what the two calls give: a batch
+    # no larger than the compute-unit count, ppc != 8, split precision, the
+    # reference kernel (the others on 300 sub-grids)
+    n = 6 if case == "small" else 300
+    w = synth.config(3, nsub=n)
     if case == "ppc5":
         w.ppc = 5
-    desc, m_el, l_el = descriptors(w, range(6))
-    pos, mass = particles(w, range(6))
+    desc, m_el, l_el = descriptors(w, range(n))
+    pos, mass = particles(w, range(n))
     dpos, dmass = to_dev(pos), to_dev(mass)
-    prec = {"ppc5": fmm.FMM_FP64_HARMONIC, "split": fmm.FMM_SPLIT_FP32, "reference": fmm.FMM_FP64}[case]
+    prec = {"small": fmm.FMM_FP64_HARMONIC, "ppc5": fmm.FMM_FP64_HARMONIC, "split": fmm.FMM_SPLIT_FP32,
+            "reference": fmm.FMM_FP64}[case]
     if case == "reference":
         ctx.set_option(fmm.FMM_OPT_M2L_KERNEL, 1)
     try:
