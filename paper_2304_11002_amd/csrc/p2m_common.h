@@ -60,22 +60,25 @@ __device__ __forceinline__ void p2m_accumulate(double m, double ax, double ay, d
 // rows (y, z) in [2, 22)^2 (all 24 cells of each row: they hold the reachable
 // window, the only cells M2L reads), 8 particles per cell, in steps of half a
 // z plane's rows (240 cells, contiguous in memory). A step's particles are
-// read with coalesced 16-byte loads and staged through LDS (cell stride padded
-// to 25 doubles); two register sets take turns, so the loads of step k + 2 are
+// read with coalesced 16-byte loads and staged through LDS transposed, one row
+// of 241 doubles per particle coordinate or mass (so a wave's reads are
+// consecutive doubles); two register sets take turns, so the loads of step k + 2 are
 // in flight while step k's moments are computed and step k + 1's loads land.
 // Each cell is shared by two waves: even waves sum the components of orders
 // below p, odd waves those of order p, so a thread holds at most 20 sums and
 // two sets of 8 loads (this runs inside a kernel with registers of its own).
-// Cells of absent blocks get zero moments and their particles are not read
-// (their loads read the always present centre cell instead, and are dropped).
+// Cells of absent blocks get zero moments and their particles are not read:
+// their loads read the always present centre cell instead, and what lands is
+// never used. Every vector memory operation of the loop is unconditional, so
+// each wait covers exactly the loads it needs and not the set still in flight.
 // Needs 16-byte aligned particle blocks (even part_off) and kP2MRowsLds
 // doubles of LDS.
 // ---------------------------------------------------------------------------
 constexpr int kRowsPlane = kWin * kFrame;                          // 480 cells per z plane
 constexpr int kRowsStep = kRowsPlane / 2;                          // 240 cells per step
 constexpr int kRowsSteps = 2 * kWin;                               // 40
-constexpr int kRowsStride = 3 * 8 + 1;                             // LDS doubles per cell
-constexpr int kP2MRowsLds = kRowsStep * (kRowsStride + 8);         // 7920 doubles
+constexpr int kRowsLd = kRowsStep + 1;                             // LDS row: one value per cell
+constexpr int kP2MRowsLds = 32 * kRowsLd;                          // 24 coordinate + 8 mass rows
 constexpr int kP2MRowsThreads = 512;
 
 template <int P, int C0, int C1>
@@ -88,10 +91,11 @@ __device__ __forceinline__ void p2m_rows_cell(const DevDesc& d, double h, const 
   for (int c = 0; c < CP; ++c) acc[c] = 0.0;
   if (block_present(d.mask, jx, jy, jz)) {
     const double cx = (jx + 0.5) * h, cy = (jy + 0.5) * h, cz = (jz + 0.5) * h;
-    const double* y = s_pos + lc * kRowsStride;
+    const double* y = s_pos + lc;
 #pragma unroll 1
     for (int i = 0; i < 8; ++i)
-      p2m_accumulate<P, C0, C1>(s_mass[lc * 8 + i], y[3 * i] - cx, y[3 * i + 1] - cy, y[3 * i + 2] - cz, acc);
+      p2m_accumulate<P, C0, C1>(s_mass[i * kRowsLd + lc], y[(3 * i) * kRowsLd] - cx,
+                                y[(3 * i + 1) * kRowsLd] - cy, y[(3 * i + 2) * kRowsLd] - cz, acc);
   }
   double* out = M + d.m_off + jx + kFrame * jy + kFrame * kFrame * jz;
 #pragma unroll
@@ -107,8 +111,8 @@ __device__ __forceinline__ void p2m_window_rows(const DevDesc& d, const double* 
   constexpr int NP = (NPC + NT - 1) / NT;                    // position loads per thread (6)
   constexpr int NM = (NMC + NT - 1) / NT;                    // mass loads per thread (2)
   static_assert(2 * kRowsStep <= NT && kRowsSteps % 2 == 0, "two threads per cell, steps in pairs");
-  double* s_pos = lds;
-  double* s_mass = lds + kRowsStep * kRowsStride;
+  double* s_pos = lds;                  // [3 * particle + coordinate][cell]
+  double* s_mass = lds + 24 * kRowsLd;  // [particle][cell]
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lc = (wave >> 1) * 64 + (tid & 63);   // this thread's cell in the step
@@ -120,6 +124,7 @@ __device__ __forceinline__ void p2m_window_rows(const DevDesc& d, const double* 
   const double2* mcentre = reinterpret_cast<const double2*>(mass + d.part_off + (int64_t)centre * 8);
   // step s: z plane kWin0 + s / 2, its rows' cells [r0, r0 + 240) with r0 = (s % 2) * 240
   auto issue = [&](int step, double2* rp, double2* rm) {
+    step = min(step, kRowsSteps - 1);   // past the end: a harmless reload of the last step
     const int z = kWin0 + (step >> 1), r0 = (step & 1) * kRowsStep;
     const int base = z * kFrame * kFrame + kWin0 * kFrame + r0;    // the step's first cell
     const uint32_t pm = (d.mask >> (9 * (z / kBlock))) & 511u;     // the plane's 3 x 3 blocks
@@ -131,15 +136,13 @@ __device__ __forceinline__ void p2m_window_rows(const DevDesc& d, const double* 
     for (int i = 0; i < NP; ++i) {
       const int v = t + i * NT, r = r0 + v / 12;
       const bool on = v < NPC && (full || ((pm >> ((r % kFrame) / kBlock + 3 * ((kWin0 + r / kFrame) / kBlock))) & 1u));
-      const double2 x = *(on ? ps + v : pcentre);
-      rp[i] = on ? x : make_double2(0.0, 0.0);
+      rp[i] = *(on ? ps + v : pcentre);
     }
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
       const int v = t + i * NT, r = r0 + v / 4;
       const bool on = v < NMC && (full || ((pm >> ((r % kFrame) / kBlock + 3 * ((kWin0 + r / kFrame) / kBlock))) & 1u));
-      const double2 x = *(on ? ms + v : mcentre);
-      rm[i] = on ? x : make_double2(0.0, 0.0);
+      rm[i] = *(on ? ms + v : mcentre);
     }
   };
   // step's loads (landed in rp, rm) to LDS, the loads of step + 2 into the same
@@ -152,28 +155,30 @@ __device__ __forceinline__ void p2m_window_rows(const DevDesc& d, const double* 
     for (int i = 0; i < NP; ++i) {
       const int v = t + i * NT;
       if (v < NPC) {
-        double* dst = s_pos + (v / 12) * kRowsStride + 2 * (v % 12);
+        // chunk w of a cell holds its doubles 2w, 2w + 1 (x0 y0 z0 x1 ...): rows 2w, 2w + 1
+        double* dst = s_pos + 2 * (v % 12) * kRowsLd + v / 12;
         dst[0] = rp[i].x;
-        dst[1] = rp[i].y;
+        dst[kRowsLd] = rp[i].y;
       }
     }
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
       const int v = t + i * NT;
       if (v < NMC) {
-        s_mass[2 * v] = rm[i].x;
-        s_mass[2 * v + 1] = rm[i].y;
+        double* dst = s_mass + 2 * (v % 4) * kRowsLd + v / 4;
+        dst[0] = rm[i].x;
+        dst[kRowsLd] = rm[i].y;
       }
     }
     __syncthreads();
-    if (step + 2 < kRowsSteps) issue(step + 2, rp, rm);
-    if (lc < kRowsStep) {
-      const int r = (step & 1) * kRowsStep + lc;
-      const int jx = r % kFrame, jy = kWin0 + r / kFrame, jz = kWin0 + (step >> 1);
-      constexpr int CL = ncomp(P - 1);
-      if (high) p2m_rows_cell<P, CL, ncomp(P)>(d, h, s_pos, s_mass, lc, jx, jy, jz, M);
-      else p2m_rows_cell<P, 0, CL>(d, h, s_pos, s_mass, lc, jx, jy, jz, M);
-    }
+    issue(step + 2, rp, rm);
+    // lanes past the step's 240 cells repeat its last cell (same values, same address)
+    const int lcc = min(lc, kRowsStep - 1);
+    const int r = (step & 1) * kRowsStep + lcc;
+    const int jx = r % kFrame, jy = kWin0 + r / kFrame, jz = kWin0 + (step >> 1);
+    constexpr int CL = ncomp(P - 1);
+    if (high) p2m_rows_cell<P, CL, ncomp(P)>(d, h, s_pos, s_mass, lcc, jx, jy, jz, M);
+    else p2m_rows_cell<P, 0, CL>(d, h, s_pos, s_mass, lcc, jx, jy, jz, M);
   };
   double2 ap[NP], am[NM], bp[NP], bm[NM];
   issue(0, ap, am);
