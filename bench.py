@@ -519,8 +519,7 @@ def main():
             if ev: ev[0].record()
             ctx.p2m_m2l(d5, pos5, mass5, 8, M5, L5, fmm.FMM_FP64_HARMONIC)
             if ev: ev[1].record()
-            ctx.m2l_backward(d5, wt, dM5)      # dLoss/dL = w for loss = sum w . L
-            ctx.p2m_backward(d5, pos5, 8, dM5, dm5)
+            ctx.m2l_p2m_backward(d5, pos5, 8, wt, dM5, dm5)   # dLoss/dL = w for loss = sum w . L
             if ev: ev[2].record()
 
         ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 1)      # harmonic adjoint with the harmonic forward
@@ -531,7 +530,7 @@ def main():
         bwd_dense_ms = seg_fbd[:, 1].mean()
         out["fwd_bwd"] = {"workload": "grad_2048_p3", "subgrids": w5.nsub, "pairs": pairs5,
                           "forward": "P2M + M2L (harmonic form), one launch (fmm_p2m_m2l)",
-                          "backward": "M2L adjoint (harmonic form) + P2M adjoint",
+                          "backward": "M2L adjoint (harmonic form) + P2M adjoint, one launch (fmm_m2l_p2m_backward)",
                           "bwd_ms_dense_adjoint": float(bwd_dense_ms),
                           "fwd_ms": float(fwd_ms), "bwd_ms": float(bwd_ms),
                           "fwd_bwd_ms_per_batch": float(fwd_ms + bwd_ms),

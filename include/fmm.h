@@ -170,6 +170,19 @@ fmm_status fmm_p2m_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
                             const double* pos, int32_t ppc, const double* dM,
                             double* dmass, void* stream);
 
+/* Both adjoints in one persistent launch: dM as fmm_m2l_backward writes it
+ * and dmass as fmm_p2m_backward then computes from that dM, bit for bit.
+ * Each workgroup computes a sub-grid's mass gradients itself, during the
+ * M2L adjoint of the sub-grid after it, so the HBM-bound gradient work of
+ * some workgroups overlaps the matrix work of the others. The single launch
+ * is used for batches of more sub-grids than the GPU has compute units, with
+ * ppc = 8, 16-byte aligned pos and dmass and even part_off; otherwise, and
+ * with FMM_OPT_M2L_KERNEL = 1, the call runs the two adjoints one after the
+ * other, with the same results. FMM_OPT_ADJOINT_FORM applies. */
+fmm_status fmm_m2l_p2m_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
+                                const double* pos, int32_t ppc, const double* dL,
+                                double* dM, double* dmass, void* stream);
+
 /* Evaluation at the particles (row "near field and L2P"; the leaf cells of
  * the paper's Sec. IV-C interact as point masses): for every particle i of
  * the 512 target cells t of each sub-grid, with b = y_i - c_t,

@@ -787,6 +787,36 @@ fmm_status fmm_m2l_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
   return mark_used(ctx, e, s);
 }
 
+fmm_status fmm_m2l_p2m_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const double* pos,
+                                int32_t ppc, const double* dL, double* dM, double* dmass, void* stream) {
+  CHECK_OK(check_ctx(ctx));
+  CHECK_OK(check_desc(ctx, desc, nsub));
+  CHECK_OK(check_ppc(ctx, ppc));
+  CHECK_OK(check_ptr(ctx, pos, "pos", nsub));
+  CHECK_OK(check_ptr(ctx, dL, "dL", nsub));
+  CHECK_OK(check_ptr(ctx, dM, "dM", nsub));
+  CHECK_OK(check_ptr(ctx, dmass, "dmass", nsub));
+  if (ctx->adjoint_form == 1 && ctx->m2l_kernel == 1)
+    return set_err(ctx, FMM_EINVAL, "the reference kernel computes the dense adjoint only");
+  if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
+  if (nsub == 0) return FMM_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  DescEntry* e = nullptr;
+  CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
+  const bool aligned = ((reinterpret_cast<uintptr_t>(pos) | reinterpret_cast<uintptr_t>(dmass)) & 15u) == 0;
+  if (ctx->m2l_kernel != 1 && ppc == 8 && e->part_even && aligned && nsub > ctx->mfma.num_cu) {
+    HIP_TRY(ctx, launch_m2l_mfma_backward(ctx->mfma, e->work, e->d_desc, dL, dM, ctx->adjoint_form == 1, s,
+                                          pos, dmass));
+  } else {
+    if (ctx->m2l_kernel == 1) CHECK_OK(run_ref(ctx, e, true, dL, dM, s));
+    else HIP_TRY(ctx, launch_m2l_mfma_backward(ctx->mfma, e->work, e->d_desc, dL, dM, ctx->adjoint_form == 1, s));
+    HIP_TRY(ctx, launch_p2m_backward(e->d_desc, nsub, e->d_ids, e->count, pos, ppc, dM, dmass, e->part_even, s));
+  }
+  return mark_used(ctx, e, s);
+}
+
 fmm_status fmm_stencil_tables(fmm_ctx* ctx, int32_t p, double* out, void* stream) {
   CHECK_OK(check_ctx(ctx));
   if (p < 2 || p > kMaxP) return set_err(ctx, FMM_EINVAL, "p not in {2,3,4}");

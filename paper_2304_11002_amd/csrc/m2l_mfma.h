@@ -121,7 +121,11 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
                            hipStream_t s, const double* pos = nullptr,
                            const double* mass = nullptr);
 // harmonic: the harmonic form of the adjoint (equal to the dense one up to rounding)
+// pos, dmass (both or neither): the kernel also computes the mass gradients of
+// each sub-grid's dM (as launch_p2m_backward, 8 particles per cell, 16-byte
+// aligned particle blocks) into dmass
 hipError_t launch_m2l_mfma_backward(const MfmaTables& t, const WorkList& w, const DevDesc* d_desc,
-                                    const double* dL, double* dM, bool harmonic, hipStream_t s);
+                                    const double* dL, double* dM, bool harmonic, hipStream_t s,
+                                    const double* pos = nullptr, double* dmass = nullptr);
 
 }  // namespace fmm

@@ -263,6 +263,7 @@ constexpr int kBlThreads = 512;
 struct NoHook {
   __device__ bool wants(int, int) const { return false; }
   __device__ void run() const {}
+  __device__ void run(double*) const {}
 };
 // the moments of the next item, at the top of round (workgroup index mod rounds)
 template <class F>
@@ -973,13 +974,16 @@ constexpr int kMaxPairs = 512;
 // loop carries no branches.
 // HARM: the harmonic form; dL is folded to the (p+1)^2 harmonic columns, the
 // rounds accumulate folded output components and the write-out expands them.
-template <int P, bool FULL, bool HARM = false>
+// Hook: as for the forward kernel; here it runs after the barrier at the top of
+// round r, with the accumulators all zero, may use them as scratch, and they
+// are cleared again after it. The A operands are rebuilt from dL after it.
+template <int P, bool FULL, bool HARM = false, class Hook = NoHook>
 __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __restrict__ dL,
-                                            double* __restrict__ dM, const double* __restrict__ Bp,
+                                            double* dM, const double* __restrict__ Bp,
                                             int npairs, const int* s_gs,
                                             const uint32_t* __restrict__ ptouch, double* smem,
                                             const int* s_po, const HFold* __restrict__ hfold = nullptr,
-                                            const HOut* __restrict__ hout = nullptr) {
+                                            const HOut* __restrict__ hout = nullptr, Hook hook = Hook()) {
   constexpr int C = ncomp(P);
   constexpr int CR = HARM ? (P + 1) * (P + 1) : C;   // reduced components
   constexpr int KC = (CR + 3) / 4;    // dL component chunks of 4 (the reduction)
@@ -995,6 +999,7 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
   double a[TPW][KC];
   int obase[TPW];
   const double* src = dL + d.l_off;
+  auto load_a = [&]() {
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     const int x0 = (t & 1) * 4, y0 = (t >> 1) * 4;
@@ -1020,6 +1025,8 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
     obase[t] = (x0 + (lane >> 4) + 6) + kWin * (y0 + ((lane & 15) >> 2) + 6) + kWin * kWin * (wave + 6) +
                slot * kAccStride;
   }
+  };
+  load_a();
 
   for (int i = tid; i < 2 * kAccStride; i += kBwdThreads) smem[i] = 0.0;
 
@@ -1027,6 +1034,13 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
   double* out = dM + d.m_off;
   for (int r = 0; r < ROUNDS; ++r) {
     __syncthreads();
+    if (hook.wants(r, ROUNDS)) {
+      hook.run(smem);
+      __syncthreads();
+      for (int i = tid; i < 2 * kAccStride; i += kBwdThreads) smem[i] = 0.0;
+      __syncthreads();
+      load_a();
+    }
     // tables through a buffer resource: a per-pair scalar offset and this lane's
     // fixed byte offset, so no per-pair address registers (reads past the end of
     // the tables would return zeros)
@@ -1172,25 +1186,56 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
   }
 }
 
-template <bool HARM>
+// the mass gradients of an earlier item, at the top of round (workgroup index
+// mod rounds) of the current one
+template <class F>
+struct GradHook {
+  int prev;
+  F grads;
+  __device__ bool wants(int r, int rounds) const {
+    return prev >= 0 && r == (int)(blockIdx.x % (unsigned)rounds);
+  }
+  __device__ void run(double* lds) const { grads(prev, lds); }
+};
+
+// FUSE: the kernel also computes the mass gradients (the P2M adjoint of the
+// sub-grid's dM, 8 particles per cell). A workgroup computes them for its
+// previous item, whose dM it has written, at the top of round (workgroup index
+// mod rounds) of its current item, so that HBM-bound work overlaps the matrix
+// work of the other workgroups; its last item's follow after its loop.
+template <bool HARM, bool FUSE = false>
 __global__ void __launch_bounds__(kBwdThreads) m2l_bwd_kernel(
     const WorkItem* __restrict__ items, int count, unsigned* __restrict__ counter,
-    const DevDesc* __restrict__ desc, const double* __restrict__ dL, double* __restrict__ dM,
+    const DevDesc* __restrict__ desc, const double* __restrict__ dL, double* dM,
     const double* __restrict__ B2, const double* __restrict__ B3, const double* __restrict__ B4,
     const int4* __restrict__ pairs, int npairs, const int* __restrict__ gstart,
     const uint32_t* __restrict__ ptouch, const HFold* __restrict__ hf2, const HFold* __restrict__ hf3,
     const HFold* __restrict__ hf4, const HOut* __restrict__ ho2, const HOut* __restrict__ ho3,
-    const HOut* __restrict__ ho4) {
+    const HOut* __restrict__ ho4, const double* __restrict__ pos = nullptr,
+    double* __restrict__ dmass = nullptr) {
   __shared__ double smem[2 * kAccStride];
   __shared__ int s_po[2 * kMaxPairs];     // output offsets of each pair's two offsets
   __shared__ int s_gs[16];                // first pair of each dz group, and the end
   __shared__ int s_item;
+  static_assert(kP2MAdjRowsLds <= 2 * kAccStride && kBwdThreads == kP2MRowsThreads,
+                "the gradient phase fits the accumulator buffer and the workgroup");
   for (int i = threadIdx.x; i < npairs; i += blockDim.x) {
     const int4 o = pairs[i];
     s_po[2 * i] = o.x;
     s_po[2 * i + 1] = o.y;
   }
   if (threadIdx.x < 14) s_gs[threadIdx.x] = gstart[threadIdx.x];
+  // the mass gradients of item `it` (its dM complete), with `lds` as staging
+  auto grads = [&](int it, double* lds) __attribute__((always_inline)) {
+    const DevDesc dp = desc[items[it].sub];
+    switch (dp.p) {
+      case 2: p2m_adjoint_rows<2>(dp, pos, dM, dmass, lds); break;
+      case 3: p2m_adjoint_rows<3>(dp, pos, dM, dmass, lds); break;
+      case 4: p2m_adjoint_rows<4>(dp, pos, dM, dmass, lds); break;
+      default: break;
+    }
+  };
+  int prev = -1;
   // (LDS operations complete in order; the staged values are read after the
   // barrier at the top of the item loop)
   for (;;) {
@@ -1200,22 +1245,33 @@ __global__ void __launch_bounds__(kBwdThreads) m2l_bwd_kernel(
     if (item >= count) break;
     const DevDesc d = desc[items[item].sub];
     const bool full = d.mask == kFullMask;
+    const auto hook = [&]() {
+      if constexpr (FUSE) return GradHook<decltype(grads)>{prev, grads};
+      else return NoHook{};
+    }();
     switch (d.p) {
       case 2:
-        if (full) bwd_subgrid<2, true, HARM>(d, dL, dM, B2, npairs, s_gs, ptouch, smem, s_po, hf2, ho2);
-        else bwd_subgrid<2, false, HARM>(d, dL, dM, B2, npairs, s_gs, ptouch, smem, s_po, hf2, ho2);
+        if (full) bwd_subgrid<2, true, HARM>(d, dL, dM, B2, npairs, s_gs, ptouch, smem, s_po, hf2, ho2, hook);
+        else bwd_subgrid<2, false, HARM>(d, dL, dM, B2, npairs, s_gs, ptouch, smem, s_po, hf2, ho2, hook);
         break;
       case 3:
-        if (full) bwd_subgrid<3, true, HARM>(d, dL, dM, B3, npairs, s_gs, ptouch, smem, s_po, hf3, ho3);
-        else bwd_subgrid<3, false, HARM>(d, dL, dM, B3, npairs, s_gs, ptouch, smem, s_po, hf3, ho3);
+        if (full) bwd_subgrid<3, true, HARM>(d, dL, dM, B3, npairs, s_gs, ptouch, smem, s_po, hf3, ho3, hook);
+        else bwd_subgrid<3, false, HARM>(d, dL, dM, B3, npairs, s_gs, ptouch, smem, s_po, hf3, ho3, hook);
         break;
       case 4:
-        if (full) bwd_subgrid<4, true, HARM>(d, dL, dM, B4, npairs, s_gs, ptouch, smem, s_po, hf4, ho4);
-        else bwd_subgrid<4, false, HARM>(d, dL, dM, B4, npairs, s_gs, ptouch, smem, s_po, hf4, ho4);
+        if (full) bwd_subgrid<4, true, HARM>(d, dL, dM, B4, npairs, s_gs, ptouch, smem, s_po, hf4, ho4, hook);
+        else bwd_subgrid<4, false, HARM>(d, dL, dM, B4, npairs, s_gs, ptouch, smem, s_po, hf4, ho4, hook);
         break;
       default: break;
     }
     __syncthreads();
+    prev = item;
+  }
+  if constexpr (FUSE) {
+    if (prev >= 0) {
+      __syncthreads();
+      grads(prev, smem);
+    }
   }
 }
 
@@ -1761,22 +1817,27 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
 }
 
 hipError_t launch_m2l_mfma_backward(const MfmaTables& t, const WorkList& w, const DevDesc* d_desc,
-                                    const double* dL, double* dM, bool harmonic, hipStream_t s) {
+                                    const double* dL, double* dM, bool harmonic, hipStream_t s,
+                                    const double* pos, double* dmass) {
   if (w.count == 0) return hipSuccess;
+  if ((pos == nullptr) != (dmass == nullptr)) return hipErrorInvalidValue;
   const int grid = std::min(t.num_cu, w.count);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, w.counter);
-  if (harmonic) {
-    hipLaunchKernelGGL(m2l_bwd_kernel<true>, dim3(grid), dim3(kBwdThreads), 0, s, w.items, w.count,
-                       w.counter, d_desc, dL, dM, t.bwdh[2], t.bwdh[3], t.bwdh[4], t.pairs, t.npairs,
-                       t.gstart, t.ptouch, t.hfold[2], t.hfold[3], t.hfold[4], t.hout[2], t.hout[3],
-                       t.hout[4]);
-  } else {
-    const HFold* nf = nullptr;
-    const HOut* no = nullptr;
-    hipLaunchKernelGGL(m2l_bwd_kernel<false>, dim3(grid), dim3(kBwdThreads), 0, s, w.items, w.count,
-                       w.counter, d_desc, dL, dM, t.bwd[2], t.bwd[3], t.bwd[4], t.pairs, t.npairs,
-                       t.gstart, t.ptouch, nf, nf, nf, no, no, no);
-  }
+  const HFold* nf = nullptr;
+  const HOut* no = nullptr;
+#define BWD_LAUNCH(HARMV, FUSEV, B, HF0, HF1, HF2, HO0, HO1, HO2)                                  \
+  hipLaunchKernelGGL((m2l_bwd_kernel<HARMV, FUSEV>), dim3(grid), dim3(kBwdThreads), 0, s, w.items,  \
+                     w.count, w.counter, d_desc, dL, dM, B[2], B[3], B[4], t.pairs, t.npairs,       \
+                     t.gstart, t.ptouch, HF0, HF1, HF2, HO0, HO1, HO2, pos, dmass)
+  if (harmonic && pos)
+    BWD_LAUNCH(true, true, t.bwdh, t.hfold[2], t.hfold[3], t.hfold[4], t.hout[2], t.hout[3], t.hout[4]);
+  else if (harmonic)
+    BWD_LAUNCH(true, false, t.bwdh, t.hfold[2], t.hfold[3], t.hfold[4], t.hout[2], t.hout[3], t.hout[4]);
+  else if (pos)
+    BWD_LAUNCH(false, true, t.bwd, nf, nf, nf, no, no, no);
+  else
+    BWD_LAUNCH(false, false, t.bwd, nf, nf, nf, no, no, no);
+#undef BWD_LAUNCH
   return hipGetLastError();
 }
 

@@ -84,12 +84,7 @@ __device__ void p2m_bwd_cell(const DevDesc& d, const double* __restrict__ pos, i
   const double cx = (jx + 0.5) * h, cy = (jy + 0.5) * h, cz = (jz + 0.5) * h;
   for (int i = 0; i < ppc; ++i) {
     const double* y = pos + 3 * (p0 + i);
-    double mono[C];
-    monomials<P>(y[0] - cx, y[1] - cy, y[2] - cz, mono);
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < C; ++c) s = __builtin_fma(g[c], mono[c], s);
-    dmass[p0 + i] = s;
+    dmass[p0 + i] = monomial_dot<P>(g, y[0] - cx, y[1] - cy, y[2] - cz);
   }
 }
 
@@ -269,14 +264,8 @@ __global__ void __launch_bounds__(kT8) p2m8_bwd_kernel(const DevDesc* __restrict
       const double cx = (jx + 0.5) * h, cy = (jy + 0.5) * h, cz = (jz + 0.5) * h;
       const double* y = s_pos + tid * kPosStride;
 #pragma unroll 2
-      for (int i = 0; i < kPpc8; ++i) {
-        double mono[C];
-        monomials<P>(y[3 * i] - cx, y[3 * i + 1] - cy, y[3 * i + 2] - cz, mono);
-        double sum = 0.0;
-#pragma unroll
-        for (int c = 0; c < C; ++c) sum = __builtin_fma(g[c], mono[c], sum);
-        s_out[tid * (kPpc8 + 1) + i] = sum;
-      }
+      for (int i = 0; i < kPpc8; ++i)
+        s_out[tid * (kPpc8 + 1) + i] = monomial_dot<P>(g, y[3 * i] - cx, y[3 * i + 1] - cy, y[3 * i + 2] - cz);
     }
     __syncthreads();
     // coalesced write of the block's 128 x 8 gradients

@@ -9,9 +9,10 @@
 
 namespace fmm {
 
-// out[c] = a^k / k! for the graded multi-index k of component c
+// sum_c g[c] a^k / k!, in component order, each monomial a^k / k! formed as
+// (x^kx y^ky z^kz) / (kx! ky! kz!) and consumed at once
 template <int P>
-__device__ __forceinline__ void monomials(double ax, double ay, double az, double* out) {
+__device__ __forceinline__ double monomial_dot(const double* g, double ax, double ay, double az) {
   double px[P + 1], py[P + 1], pz[P + 1];
   px[0] = py[0] = pz[0] = 1.0;
 #pragma unroll
@@ -20,19 +21,21 @@ __device__ __forceinline__ void monomials(double ax, double ay, double az, doubl
     py[i] = py[i - 1] * ay;
     pz[i] = pz[i - 1] * az;
   }
+  double sum = 0.0;
 #pragma unroll
   for (int c = 0; c < ncomp(P); ++c) {
     const MI k = mi_of(c);
-    out[c] = px[k.x] * py[k.y] * pz[k.z] * (inv_fact(k.x) * inv_fact(k.y) * inv_fact(k.z));
+    sum = __builtin_fma(g[c], px[k.x] * py[k.y] * pz[k.z] * (inv_fact(k.x) * inv_fact(k.y) * inv_fact(k.z)), sum);
   }
+  return sum;
 }
 
 // acc[c - C0] += m a^k / k! for the components c in [C0, C1). The mass and the
 // factorials ride on the powers (xm_i = m ax^i / i!, yf_i = ay^i / i!,
 // zf_i = az^i / i!), so a component costs one product of an x and a y power
 // (shared by every kz) and one fma: 41 operations per particle for all 20
-// components at p = 3, against 89 with monomials(). Each component's value
-// does not depend on the range it is computed in.
+// components at p = 3, against 89 with monomial_dot's monomials. Each
+// component's value does not depend on the range it is computed in.
 template <int P, int C0 = 0, int C1 = ncomp(P)>
 __device__ __forceinline__ void p2m_accumulate(double m, double ax, double ay, double az,
                                                double* acc) {
@@ -186,6 +189,131 @@ __device__ __forceinline__ void p2m_window_rows(const DevDesc& d, const double* 
   for (int step = 0; step < kRowsSteps; step += 2) {
     run(step, ap, am);
     run(step + 1, bp, bm);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The adjoint of P2M with respect to the masses for one sub-grid, by one
+// 512-thread workgroup: dmass_i = sum_k dM_k(j) a_i^k / k!, for dM as the M2L
+// adjoint writes it (zero outside the reachable window). Cells outside the
+// frame rows (y, z) in [2, 22)^2 get zero gradients without any read; the
+// rows go in the same half-plane steps as p2m_window_rows, positions and dM
+// staged through LDS in rows of one value per cell, one register set of loads
+// in flight during a step's arithmetic. Two threads share a cell, four of its
+// particles each. Per particle the sum is monomial_dot<P>, as in the P2M
+// adjoint kernels, so the results are the same bits. Particles of absent blocks get 0 and are not
+// read. Needs 16-byte aligned particle blocks and kP2MAdjRowsLds doubles of LDS.
+// ---------------------------------------------------------------------------
+constexpr int kP2MAdjRowsLds = (24 + ncomp(kMaxP)) * kRowsLd;   // 14219 doubles
+
+template <int P>
+__device__ __forceinline__ void p2m_adjoint_rows(const DevDesc& d, const double* __restrict__ pos,
+                                                 const double* dM, double* __restrict__ dmass,
+                                                 double* lds) {
+  constexpr int C = ncomp(P);
+  constexpr int NT = kP2MRowsThreads;
+  constexpr int NPC = kRowsStep * 12;                  // 16-byte position chunks per step
+  constexpr int NGC = C * kRowsStep / 2;               // 16-byte dM chunks per step
+  constexpr int NP = (NPC + NT - 1) / NT, NG = (NGC + NT - 1) / NT;
+  static_assert(2 * kRowsStep <= NT && (24 + C) * kRowsLd <= kP2MAdjRowsLds, "layout");
+  double* s_pos = lds;                  // [3 * particle + coordinate][cell]
+  double* s_g = lds + 24 * kRowsLd;     // [component][cell]
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lc = (wave >> 1) * 64 + (tid & 63);   // this thread's cell in the step
+  const int half = wave & 1;                      // its particles 4 half .. 4 half + 3
+  const double h = ldexp(1.0, -d.log2_inv_h);
+  const bool full = d.mask == kFullMask;
+  double* dm = dmass + d.part_off;
+  // zeros for every particle outside the rows: planes z < 2 and z >= 22 whole,
+  // and in the others the two rows below and above [2, 22)
+  {
+    double2* dm2 = reinterpret_cast<double2*>(dm);
+    constexpr int kPlane2 = kFrame * kFrame * 4;    // double2 per z plane (8 particles a cell)
+    constexpr int kEdge2 = kWin0 * kFrame * 4;      // double2 of two rows
+    const double2 z2 = make_double2(0.0, 0.0);
+    for (int i = tid; i < kWin0 * kPlane2; i += NT) {
+      dm2[i] = z2;
+      dm2[(kWin0 + kWin) * kPlane2 + i] = z2;
+    }
+    for (int i = tid; i < kWin * 2 * kEdge2; i += NT) {
+      const int z = kWin0 + i / (2 * kEdge2), k = i % (2 * kEdge2);
+      dm2[z * kPlane2 + (k < kEdge2 ? k : kPlane2 - 2 * kEdge2 + k)] = z2;
+    }
+  }
+  const int centre = kBlock * (1 + kFrame + kFrame * kFrame);
+  const double2* pcentre = reinterpret_cast<const double2*>(pos + 3 * (d.part_off + (int64_t)centre * 8));
+  const double* gsrc = dM + d.m_off;
+  double2 rp[NP], rg[NG];
+  auto issue = [&](int step) {
+    step = min(step, kRowsSteps - 1);   // past the end: a harmless reload of the last step
+    const int z = kWin0 + (step >> 1), r0 = (step & 1) * kRowsStep;
+    const int base = z * kFrame * kFrame + kWin0 * kFrame + r0;
+    const uint32_t pm = (d.mask >> (9 * (z / kBlock))) & 511u;
+    const double2* ps = reinterpret_cast<const double2*>(pos + 3 * (d.part_off + (int64_t)base * 8));
+    int t = tid;
+    asm volatile("" : "+v"(t));
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int v = t + i * NT, r = r0 + v / 12;
+      const bool on = v < NPC && (full || ((pm >> ((r % kFrame) / kBlock + 3 * ((kWin0 + r / kFrame) / kBlock))) & 1u));
+      rp[i] = *(on ? ps + v : pcentre);
+    }
+    // dM of the step's cells: component c is kRowsStep contiguous doubles at base
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      const int v = min(t + i * NT, NGC - 1);
+      const int c = v / (kRowsStep / 2), w = v % (kRowsStep / 2);
+      rg[i] = reinterpret_cast<const double2*>(gsrc + (size_t)c * kNCell + base)[w];
+    }
+  };
+  issue(0);
+  for (int step = 0; step < kRowsSteps; ++step) {
+    __syncthreads();   // earlier readers of the LDS buffer are done
+    int t = tid;
+    asm volatile("" : "+v"(t));
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int v = t + i * NT;
+      if (v < NPC) {
+        double* dst = s_pos + 2 * (v % 12) * kRowsLd + v / 12;
+        dst[0] = rp[i].x;
+        dst[kRowsLd] = rp[i].y;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      const int v = t + i * NT;
+      if (v < NGC) {
+        const int c = v / (kRowsStep / 2), w = v % (kRowsStep / 2);
+        s_g[c * kRowsLd + 2 * w] = rg[i].x;
+        s_g[c * kRowsLd + 2 * w + 1] = rg[i].y;
+      }
+    }
+    __syncthreads();
+    issue(step + 1);
+    // lanes past the step's 240 cells repeat its last cell (same values, same address)
+    const int lcc = min(lc, kRowsStep - 1);
+    const int r = (step & 1) * kRowsStep + lcc;
+    const int jx = r % kFrame, jy = kWin0 + r / kFrame, jz = kWin0 + (step >> 1);
+    const int cell = jx + kFrame * jy + kFrame * kFrame * jz;
+    double res[4] = {0.0, 0.0, 0.0, 0.0};
+    if (block_present(d.mask, jx, jy, jz)) {
+      double g[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) g[c] = s_g[c * kRowsLd + lcc];
+      const double cx = (jx + 0.5) * h, cy = (jy + 0.5) * h, cz = (jz + 0.5) * h;
+      const double* y = s_pos + lcc;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pi = 4 * half + i;
+        res[i] = monomial_dot<P>(g, y[(3 * pi) * kRowsLd] - cx, y[(3 * pi + 1) * kRowsLd] - cy,
+                                 y[(3 * pi + 2) * kRowsLd] - cz);
+      }
+    }
+    double2* out = reinterpret_cast<double2*>(dm + (int64_t)cell * 8 + 4 * half);
+    out[0] = make_double2(res[0], res[1]);
+    out[1] = make_double2(res[2], res[3]);
   }
 }
 

@@ -22,7 +22,7 @@ FULL_MASK = (1 << 27) - 1
 
 EXPORTS = [
     "fmm_create", "fmm_destroy", "fmm_status_string", "fmm_last_error", "fmm_set_option",
-    "fmm_stencil", "fmm_pair_count", "fmm_p2m", "fmm_m2l", "fmm_p2m_m2l", "fmm_m2l_backward",
+    "fmm_stencil", "fmm_pair_count", "fmm_p2m", "fmm_m2l", "fmm_p2m_m2l", "fmm_m2l_backward", "fmm_m2l_p2m_backward",
     "fmm_p2m_backward", "fmm_stencil_tables", "fmm_autotune", "fmm_evaluate",
     "fmm_tree_size", "fmm_tree_upward", "fmm_tree_m2l", "fmm_tree_downward", "fmm_tree_evaluate",
     "fmm_tree_solve",
@@ -72,6 +72,7 @@ def load_library(path=LIB_PATH):
         "fmm_p2m_m2l": ([vp, vp, i64, vp, vp, i32, vp, vp, i32, vp], i32),
         "fmm_m2l_backward": ([vp, vp, i64, vp, vp, vp], i32),
         "fmm_p2m_backward": ([vp, vp, i64, vp, i32, vp, vp, vp], i32),
+        "fmm_m2l_p2m_backward": ([vp, vp, i64, vp, i32, vp, vp, vp, vp], i32),
         "fmm_stencil_tables": ([vp, i32, vp, vp], i32),
         "fmm_autotune": ([vp, vp, i64, vp, vp, i32, vp, ctypes.POINTER(i32)], i32),
         "fmm_evaluate": ([vp, vp, i64, vp, vp, i32, vp, vp, vp], i32),
@@ -239,6 +240,12 @@ class Context:
         pd, n = _desc_ptr(desc)
         self._run(self.lib.fmm_m2l_backward(self.handle, pd, n, _ptr(dL), _ptr(dM),
                                             self._s(stream, n)))
+
+    def m2l_p2m_backward(self, desc, pos, ppc, dL, dM, dmass, stream=None):
+        """M2L adjoint (dL -> dM) and P2M adjoint (dM -> dmass) in one launch."""
+        pd, n = _desc_ptr(desc)
+        self._run(self.lib.fmm_m2l_p2m_backward(self.handle, pd, n, _ptr(pos), int(ppc), _ptr(dL),
+                                                _ptr(dM), _ptr(dmass), self._s(stream, n)))
 
     def p2m_backward(self, desc, pos, ppc, dM, dmass, stream=None):
         pd, n = _desc_ptr(desc)

@@ -107,7 +107,12 @@ def test_pointer_and_option_validation(hctx):
                  lambda: hctx.p2m_m2l(desc, 8, 0, 8, 8, 8),
                  lambda: hctx.p2m_m2l(desc, 8, 8, 8, 12, 8),           # misaligned M
                  lambda: hctx.p2m_m2l(desc, 8, 8, 8, 8, None),
-                 lambda: hctx.p2m_m2l(desc, 8, 8, 8, 8, 8, precision=7)):
+                 lambda: hctx.p2m_m2l(desc, 8, 8, 8, 8, 8, precision=7),
+                 lambda: hctx.m2l_p2m_backward(desc, 8, 0, 8, 8, 8),       # ppc = 0
+                 lambda: hctx.m2l_p2m_backward(desc, 0, 8, 8, 8, 8),
+                 lambda: hctx.m2l_p2m_backward(desc, 8, 8, 0, 8, 8),
+                 lambda: hctx.m2l_p2m_backward(desc, 8, 8, 8, 12, 8),      # misaligned dM
+                 lambda: hctx.m2l_p2m_backward(desc, 8, 8, 8, 8, None)):
         with pytest.raises(fmm.FMMError) as e:
             call()
         assert e.value.status == fmm.FMM_EINVAL
@@ -124,6 +129,9 @@ def test_host_only_context_reports_unsupported_after_checks(hctx, lib):
     assert e.value.status == fmm.FMM_EUNSUPPORTED
     with pytest.raises(fmm.FMMError) as e:
         hctx.p2m_m2l(desc, 8, 8, 8, 8, 8, precision=fmm.FMM_FP64_HARMONIC)
+    assert e.value.status == fmm.FMM_EUNSUPPORTED
+    with pytest.raises(fmm.FMMError) as e:
+        hctx.m2l_p2m_backward(desc, 8, 8, 8, 8, 8)
     assert e.value.status == fmm.FMM_EUNSUPPORTED
     for field, value in (("p", 5), ("mask", 0)):
         with pytest.raises(fmm.FMMError) as e:
@@ -147,6 +155,7 @@ def test_harmonic_precision_checks(hctx):
     try:
         for call in (lambda: hctx.m2l(desc, 8, 8, precision=fmm.FMM_FP64_HARMONIC),
                      lambda: hctx.p2m_m2l(desc, 8, 8, 8, 8, 8, precision=fmm.FMM_FP64_HARMONIC),
+                     lambda: hctx.m2l_p2m_backward(desc, 8, 8, 8, 8, 8),
                      lambda: hctx.m2l_backward(desc, 8, 8)):
             with pytest.raises(fmm.FMMError) as e:
                 call()

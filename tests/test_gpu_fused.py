@@ -187,3 +187,73 @@ def test_fused_entry_point_two_launch_cases(ctx, torch, case):
     finally:
         ctx.set_option(fmm.FMM_OPT_M2L_KERNEL, 0)
     assert_same(desc, Ms, Ls, Mf, Lf, case)
+
+
+# ---------------------------------------------------------------------------
+# the adjoints in one launch (fmm_m2l_p2m_backward)
+# ---------------------------------------------------------------------------
+
+def backward_both(ctx, torch, desc, dpos, ppc, dL, m_el, n_part):
+    dM1 = torch.full((m_el,), float("nan"), dtype=torch.float64, device="cuda")
+    dm1 = torch.full((n_part,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.m2l_backward(desc, dL, dM1)
+    ctx.p2m_backward(desc, dpos, ppc, dM1, dm1)
+    dM2 = torch.full_like(dM1, float("nan"))
+    dm2 = torch.full_like(dm1, float("nan"))
+    ctx.m2l_p2m_backward(desc, dpos, ppc, dL, dM2, dm2)
+    torch.cuda.synchronize()
+    return dM1, dm1, dM2, dm2
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_fused_backward_matches_the_separate_calls(ctx, torch, form):
+    # 600 uneven sub-grids (every order, spacing and random masks), dense and
+    # harmonic adjoint: dM and the mass gradients bit for bit as the two calls,
+    # and sampled sub-grids of every order against the oracle
+    w = synth.config(3, nsub=600)
+    n = 600
+    desc, m_el, l_el = descriptors(w, range(n))
+    pos, mass = particles(w, range(n))
+    dpos = to_dev(pos)
+    W = np.random.default_rng(91).standard_normal(l_el)
+    ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, form)
+    try:
+        dM1, dm1, dM2, dm2 = backward_both(ctx, torch, desc, dpos, 8, to_dev(W), m_el, n * fmm.NCELL * 8)
+        # replayed graph-free launches of the same call give the same bits
+        dM3, dm3 = torch.empty_like(dM2), torch.empty_like(dm2)
+        ctx.m2l_p2m_backward(desc, dpos, 8, to_dev(W), dM3, dm3)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 0)
+    assert torch.equal(dM1, dM2) and torch.equal(dm1, dm2)
+    assert torch.equal(dM2, dM3) and torch.equal(dm2, dm3)
+    import oracle as O
+    Gv, Wv = split_views(dM2.cpu().numpy(), desc, "M"), split_views(W, desc, "L")
+    gm = dm2.cpu().numpy().reshape(n, fmm.NCELL, 8)
+    picks = [int(np.flatnonzero(w.p == p)[k]) for p in (2, 3, 4) for k in (0, -1)]
+    for b in picks:
+        p, h, mask = int(w.p[b]), w.h(b), int(w.mask[b])
+        Go, Ga = O.m2l_adjoint(Wv[b], p, h, mask), O.m2l_adjoint_abs(Wv[b], p, h, mask)
+        assert (np.abs(Gv[b] - Go) <= TOL * Ga).all(), "dM of sub-grid %d (p=%d)" % (b, p)
+        go = O.p2m_adjoint(pos[b], Go, p, h, mask)
+        c = O.cell_centres(h)[:, None, :]
+        gscale = O.p2m_adjoint(c + np.abs(pos[b] - c), Ga, p, h, mask)
+        assert (np.abs(gm[b] - go) <= TOL * gscale).all(), "dmass of sub-grid %d (p=%d)" % (b, p)
+
+
+@pytest.mark.parametrize("case", ["small", "ppc5", "reference"])
+def test_fused_backward_two_launch_cases(ctx, torch, case):
+    n = 6 if case == "small" else 300
+    w = synth.config(3, nsub=n)
+    if case == "ppc5":
+        w.ppc = 5
+    desc, m_el, l_el = descriptors(w, range(n))
+    pos, mass = particles(w, range(n))
+    W = to_dev(np.random.default_rng(5).standard_normal(l_el))
+    if case == "reference":
+        ctx.set_option(fmm.FMM_OPT_M2L_KERNEL, 1)
+    try:
+        dM1, dm1, dM2, dm2 = backward_both(ctx, torch, desc, to_dev(pos), w.ppc, W, m_el, n * fmm.NCELL * w.ppc)
+    finally:
+        ctx.set_option(fmm.FMM_OPT_M2L_KERNEL, 0)
+    assert torch.equal(dM1, dM2) and torch.equal(dm1, dm2)
