@@ -2,9 +2,9 @@
 
     L = gravity_local_expansion(ctx, desc, pos, mass)   # differentiable in mass
 
-Forward runs fmm_p2m and fmm_m2l; backward runs fmm_m2l_backward (adjoint
-M2L, dL -> dM) and fmm_p2m_backward (dM -> d mass). Positions are held
-fixed (no gradient). harmonic=True computes M2L and its adjoint in the
+Forward runs fmm_p2m_m2l (P2M and M2L, in one launch for large batches);
+backward runs fmm_m2l_p2m_backward (adjoint M2L, dL -> dM, and adjoint P2M,
+dM -> d mass, likewise). Positions are held fixed (no gradient). harmonic=True computes M2L and its adjoint in the
 harmonic (traceless) form, equal to the dense form up to rounding. Every
 step runs in the library's HIP kernels; torch supplies device memory and
 the stream.
@@ -20,8 +20,7 @@ class FMMGravity(torch.autograd.Function):
         M = torch.empty(m_elems, dtype=torch.float64, device=mass.device)
         L = torch.empty(l_elems, dtype=torch.float64, device=mass.device)
         mass_c = mass.contiguous()
-        handle.p2m(desc, pos, mass_c, ppc, M)
-        handle.m2l(desc, M, L, fmm.FMM_FP64_HARMONIC if harmonic else fmm.FMM_FP64)
+        handle.p2m_m2l(desc, pos, mass_c, ppc, M, L, fmm.FMM_FP64_HARMONIC if harmonic else fmm.FMM_FP64)
         actx.save_for_backward(pos)
         actx.handle, actx.desc, actx.ppc, actx.m_elems = handle, desc, ppc, m_elems
         actx.harmonic = harmonic
@@ -33,13 +32,12 @@ class FMMGravity(torch.autograd.Function):
         (pos,) = actx.saved_tensors
         gL = gL.contiguous()
         dM = torch.empty(actx.m_elems, dtype=torch.float64, device=gL.device)
+        dmass = torch.empty(actx.mass_shape, dtype=torch.float64, device=gL.device)
         actx.handle.set_option(fmm.FMM_OPT_ADJOINT_FORM, 1 if actx.harmonic else 0)
         try:
-            actx.handle.m2l_backward(actx.desc, gL, dM)
+            actx.handle.m2l_p2m_backward(actx.desc, pos, actx.ppc, gL, dM, dmass)
         finally:
             actx.handle.set_option(fmm.FMM_OPT_ADJOINT_FORM, 0)
-        dmass = torch.empty(actx.mass_shape, dtype=torch.float64, device=gL.device)
-        actx.handle.p2m_backward(actx.desc, pos, actx.ppc, dM, dmass)
         return dmass, None, None, None, None, None, None, None
 
 
