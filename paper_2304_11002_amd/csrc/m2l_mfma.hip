@@ -679,8 +679,14 @@ __global__ void __launch_bounds__(kBlThreads) m2l_fwd_bl_kernel(
           fwd_bl_subgrid<3, PIPE, false, HARM>(d, M, L, B3, lds_off, touch, smem, sB, s_off, hr3, he3, hook);
         break;
       case 4:
-        // (the p = 4 operand sets do not fit the registers of the pipelined loop)
-        fwd_bl_subgrid<4, false, false, HARM>(d, M, L, B4, lds_off, touch, smem, sB, s_off, hr4, he4, hook);
+        // the dense p = 4 operand sets (9 column groups) do not fit the registers
+        // of the pipelined loop; the harmonic ones (7) do
+        if (HARM && PIPE && full)
+          fwd_bl_subgrid<4, PIPE, true, HARM>(d, M, L, B4, lds_off, touch, smem, sB, s_off, hr4, he4, hook);
+        else if (HARM && PIPE)
+          fwd_bl_subgrid<4, PIPE, false, HARM>(d, M, L, B4, lds_off, touch, smem, sB, s_off, hr4, he4, hook);
+        else
+          fwd_bl_subgrid<4, false, false, HARM>(d, M, L, B4, lds_off, touch, smem, sB, s_off, hr4, he4, hook);
         break;
       default: break;
     }
