@@ -128,6 +128,22 @@ def test_fused_uniform_batch_against_the_oracle(ctx, torch):
                 prec, cfg, b, np.max(err / np.maximum(La, 1e-300)))
 
 
+@pytest.mark.parametrize("p", [2, 4])
+def test_fused_full_blocks_other_orders(ctx, torch, p):
+    # 300 sub-grids of one order with every neighbour present (the branch-free
+    # loops, and at p = 4 the harmonic form's pipelined one)
+    n = 300
+    w = synth.Workload("full_p%d" % p, 40 + p, np.full(n, p, np.int32), np.zeros(n, np.int32),
+                       np.full(n, synth.FULL_MASK, np.uint32))
+    forms = [(fmm.FMM_FP64_HARMONIC, HARM_CFG), (fmm.FMM_FP64, 0)]
+    desc, pos, mass, out = run_forms(ctx, torch, w, range(n), forms)
+    Lv = split_views(out[(fmm.FMM_FP64_HARMONIC, HARM_CFG)][1].cpu().numpy(), desc, "L")
+    for b in (0, n - 1):
+        _, Lo, La = oracle_subgrid(w, b, pos[b], mass[b])
+        err = np.abs(Lv[b] - Lo)
+        assert (err <= TOL * La).all(), "p=%d sub-grid %d: worst %.3g" % (p, b, np.max(err / np.maximum(La, 1e-300)))
+
+
 def test_fused_graph_replays(ctx, torch):
     # replays of the cached graph of the single launch: plain launches give the
     # same bits, and doubled masses give exactly doubled moments and L (a power of

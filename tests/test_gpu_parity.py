@@ -356,6 +356,17 @@ def test_harmonic_form_matches_oracle(ctx, torch):
         assert_close(Lg[b], Lo, La, TOL, "harmonic edge %d" % b)
 
 
+def test_harmonic_form_full_blocks_every_order(ctx, torch):
+    # every neighbour present (the branch-free loops), p = 2, 3, 4 at each spacing
+    w = synth.Workload("full", 23, np.array([2, 3, 4, 4], np.int32), np.array([1, 0, 0, 2], np.int32),
+                       np.full(4, synth.FULL_MASK, np.uint32))
+    desc, pos, mass, M, L = forward(ctx, torch, w, range(4), MFMA, prec=HARM)
+    Lg = split_views(L.cpu().numpy(), desc, "L")
+    for b in range(4):
+        _, Lo, La = oracle_subgrid(w, b, pos[b], mass[b])
+        assert_close(Lg[b], Lo, La, TOL, "harmonic full sub-grid %d (p=%d, h=%g)" % (b, w.p[b], w.h(b)))
+
+
 def test_harmonic_form_deterministic_graphs_and_autotune(ctx, torch):
     w = synth.config(3, nsub=5)
     _, _, _, M, L_plain = forward(ctx, torch, w, range(5), MFMA, prec=HARM, graph=0)
