@@ -654,12 +654,14 @@ static fmm_status run_ref(fmm_ctx* ctx, DescEntry* e, bool backward, const doubl
 }
 
 // Launch the persistent matrix-core kernel, through a cached graph if enabled.
-// pos, mass non-null: the fused P2M + M2L launch (launch_m2l_mfma's fused form).
+// pos, mass, Mw non-null: the fused P2M + M2L launch (launch_m2l_mfma's fused
+// form; Mw is M, writable).
 static fmm_status run_mfma(fmm_ctx* ctx, DescEntry* e, const double* M, double* L,
                            fmm_precision prec, int cfg, hipStream_t s,
-                           const double* pos = nullptr, const double* mass = nullptr) {
+                           const double* pos = nullptr, const double* mass = nullptr,
+                           double* Mw = nullptr) {
   if (!ctx->use_graph) {
-    HIP_TRY(ctx, launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, s, pos, mass));
+    HIP_TRY(ctx, launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, s, pos, mass, Mw));
     return FMM_OK;
   }
   uint64_t key = fnv1a(&e->hash, sizeof e->hash);
@@ -681,7 +683,7 @@ static fmm_status run_mfma(fmm_ctx* ctx, DescEntry* e, const double* M, double* 
     }
     GraphEntry g;
     HIP_TRY(ctx, hipStreamBeginCapture(ctx->internal, hipStreamCaptureModeThreadLocal));
-    hipError_t le = launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, ctx->internal, pos, mass);
+    hipError_t le = launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, ctx->internal, pos, mass, Mw);
     hipError_t ce = hipStreamEndCapture(ctx->internal, &g.graph);
     if (le != hipSuccess) return hip_err(ctx, le, "launch_m2l_mfma (capture)");
     if (ce != hipSuccess) return hip_err(ctx, ce, "hipStreamEndCapture");
@@ -755,7 +757,7 @@ fmm_status fmm_p2m_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, cons
   // each, every moment phase runs at the start, on one workgroup per sub-grid)
   if (ctx->m2l_kernel != 1 && ppc == 8 && e->part_even && aligned && mfma_config_fusable(cfg) &&
       nsub > ctx->mfma.num_cu) {
-    CHECK_OK(run_mfma(ctx, e, M, L, prec, cfg, s, pos, mass));
+    CHECK_OK(run_mfma(ctx, e, M, L, prec, cfg, s, pos, mass, M));
   } else {
     HIP_TRY(ctx, launch_p2m(e->d_desc, nsub, e->d_ids, e->count, pos, mass, ppc, M, e->part_even, true, s));
     if (ctx->m2l_kernel == 1) CHECK_OK(run_ref(ctx, e, false, M, L, s));

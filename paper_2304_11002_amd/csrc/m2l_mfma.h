@@ -110,16 +110,16 @@ int mfma_num_configs();
 bool mfma_config_supports(int cfg, fmm_precision prec);
 int mfma_default_config(fmm_precision prec);
 
-// pos, mass (both or neither): the fused form, for configurations where
-// mfma_config_fusable(cfg). The kernel first computes each sub-grid's moments
-// (frame rows holding the reachable window, 8 particles per cell, 16-byte
-// aligned particle blocks) into M, as launch_p2m with window = true writes them,
-// and then its M2L; M is then written, not only read.
+// pos, mass, Mw (all or none; Mw == M): the fused form, for configurations
+// where mfma_config_fusable(cfg). The kernel first computes each sub-grid's
+// moments (frame rows holding the reachable window, 8 particles per cell,
+// 16-byte aligned particle blocks) into M through Mw, as launch_p2m with
+// window = true writes them, and then its M2L.
 bool mfma_config_fusable(int cfg);
 hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc* d_desc,
                            const double* M, double* L, fmm_precision prec, int cfg,
                            hipStream_t s, const double* pos = nullptr,
-                           const double* mass = nullptr);
+                           const double* mass = nullptr, double* Mw = nullptr);
 // harmonic: the harmonic form of the adjoint (equal to the dense one up to rounding)
 // pos, dmass (both or neither): the kernel also computes the mass gradients of
 // each sub-grid's dM (as launch_p2m_backward, 8 particles per cell, 16-byte

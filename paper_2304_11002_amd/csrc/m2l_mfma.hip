@@ -621,7 +621,9 @@ __global__ void __launch_bounds__(kBlThreads) m2l_fwd_bl_kernel(
     const int* __restrict__ lds_off, const uint32_t* __restrict__ touch,
     const HRound* __restrict__ hr2, const HRound* __restrict__ hr3, const HRound* __restrict__ hr4,
     const HExp* __restrict__ he2, const HExp* __restrict__ he3, const HExp* __restrict__ he4,
-    const double* __restrict__ pos = nullptr, const double* __restrict__ mass = nullptr) {
+    const double* __restrict__ pos = nullptr, const double* __restrict__ mass = nullptr,
+    double* Mw = nullptr) {
+  // (FUSE: Mw is M, writable; the moment phase writes through it)
   __shared__ double2 smem[kWinCells];
   __shared__ double sB[2 * kBlChunkMax];
   __shared__ int4 s_off[kQuads];
@@ -635,7 +637,6 @@ __global__ void __launch_bounds__(kBlThreads) m2l_fwd_bl_kernel(
   // moments of item `it` into M (the window buffer is free whenever this runs)
   auto moments = [&](int it) __attribute__((always_inline)) {
     const DevDesc dn = desc[items[it].sub];
-    double* Mw = const_cast<double*>(M);
     double* lds = reinterpret_cast<double*>(smem);
     switch (dn.p) {
       case 2: p2m_window_rows<2>(dn, pos, mass, Mw, lds); break;
@@ -1773,11 +1774,11 @@ bool mfma_config_fusable(int cfg) { return cfg >= 0 && cfg < kNumConfigs && kCon
 
 hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc* d_desc,
                            const double* M, double* L, fmm_precision prec, int cfg,
-                           hipStream_t s, const double* pos, const double* mass) {
+                           hipStream_t s, const double* pos, const double* mass, double* Mw) {
   if (w.count == 0) return hipSuccess;
   if (!mfma_config_supports(cfg, prec)) return hipErrorInvalidValue;
   const bool fuse = pos != nullptr;
-  if (fuse && (!mfma_config_fusable(cfg) || mass == nullptr)) return hipErrorInvalidValue;
+  if (fuse && (!mfma_config_fusable(cfg) || mass == nullptr || Mw != M)) return hipErrorInvalidValue;
   const int grid = std::min(t.num_cu, w.count);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, w.counter);
   const Config& c = kConfigs[cfg];
@@ -1786,7 +1787,7 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
 #define BL_LAUNCH(PIPEV, HARMV, FUSEV, B, HR, HE)                                                    \
   hipLaunchKernelGGL((m2l_fwd_bl_kernel<PIPEV, HARMV, FUSEV>), dim3(grid), dim3(kBlThreads), 0, s,   \
                      w.items, w.count, w.counter, d_desc, M, L, B[2], B[3], B[4], t.lds_off, t.touch, \
-                     HR[0], HR[1], HR[2], HE[0], HE[1], HE[2], pos, mass)
+                     HR[0], HR[1], HR[2], HE[0], HE[1], HE[2], pos, mass, Mw)
   const HRound* hr[3] = {t.hround[2], t.hround[3], t.hround[4]};
   const HExp* he[3] = {t.hexp[2], t.hexp[3], t.hexp[4]};
   const HRound* hr0[3] = {nr, nr, nr};
