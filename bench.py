@@ -599,10 +599,19 @@ def main():
             if ev: ev[1].record()
 
         _, seg1 = timed(torch, step_one, K, W, marks=1)
+        # the same with the rounds of the sub-grid spread over workgroups
+        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 1)
+        try:
+            _, seg1s = timed(torch, step_one, K, W, marks=1)
+        finally:
+            ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 0)
         out["single_subgrid"] = {"workload": "single_subgrid_p3", "pairs": fmm.pair_count(d1),
                                  "step_ms_median": float(np.median(seg1[:, 0])),
-                                 "step_ms_min": float(seg1[:, 0].min())}
-        log("single sub-grid step %.3f ms (median)" % np.median(seg1[:, 0]))
+                                 "step_ms_min": float(seg1[:, 0].min()),
+                                 "round_split_step_ms_median": float(np.median(seg1s[:, 0])),
+                                 "round_split_step_ms_min": float(seg1s[:, 0].min())}
+        log("single sub-grid step %.3f ms (median), %.3f ms with the rounds split over workgroups"
+            % (np.median(seg1[:, 0]), np.median(seg1s[:, 0])))
         del pos1, mass1, M1, L1
 
         # ---------------- CPU baseline (the oracle on the host cores)

@@ -91,6 +91,12 @@ struct DescEntry {
   int* d_ids[kMaxP + 1] = {};     // reference kernels: sub-grids per order
   int count[kMaxP + 1] = {};
   WorkList work;                  // matrix-core kernels
+  // FMM_OPT_ROUND_SPLIT, per form (dense, harmonic): (sub-grid, round) list, the
+  // first slot of each sub-grid, and the rounds' sums; one allocation each
+  void* split_dev[2] = {};
+  WorkList split[2];
+  int* split_base[2] = {};
+  double* split_part[2] = {};
   bool part_even = true;          // every part_off even: particle blocks 16-byte aligned
   int tuned[3] = {-1, -1, -1};    // autotuned configuration per precision
   hipEvent_t ready = nullptr;     // upload finished
@@ -121,6 +127,7 @@ struct fmm_ctx {
   int tile_config = -1;
   int adjoint_form = 0;     // FMM_OPT_ADJOINT_FORM
   int p2m_window = 0;       // FMM_OPT_P2M_WINDOW
+  int round_split = 0;      // FMM_OPT_ROUND_SPLIT
 };
 
 namespace {
@@ -219,6 +226,8 @@ void free_entry(DescEntry* e) {
   if (e->last_launch) (void)hipEventSynchronize(e->last_launch);
   if (e->ready) (void)hipEventSynchronize(e->ready);
   if (e->dev) (void)hipFree(e->dev);
+  for (int f = 0; f < 2; ++f)
+    if (e->split_dev[f]) (void)hipFree(e->split_dev[f]);
   if (e->pinned) (void)hipHostFree(e->pinned);
   if (e->ready) (void)hipEventDestroy(e->ready);
   if (e->last_launch) (void)hipEventDestroy(e->last_launch);
@@ -425,6 +434,10 @@ fmm_status fmm_set_option(fmm_ctx* ctx, int32_t option, int64_t value) {
     case FMM_OPT_P2M_WINDOW:
       if (value != 0 && value != 1) return set_err(ctx, FMM_EINVAL, "FMM_OPT_P2M_WINDOW value not 0/1");
       ctx->p2m_window = (int)value;
+      return FMM_OK;
+    case FMM_OPT_ROUND_SPLIT:
+      if (value != 0 && value != 1) return set_err(ctx, FMM_EINVAL, "FMM_OPT_ROUND_SPLIT value not 0/1");
+      ctx->round_split = (int)value;
       return FMM_OK;
     case FMM_OPT_ADJOINT_FORM:
       if (value != 0 && value != 1) return set_err(ctx, FMM_EINVAL, "FMM_OPT_ADJOINT_FORM value not 0/1");
@@ -695,6 +708,44 @@ static fmm_status run_mfma(fmm_ctx* ctx, DescEntry* e, const double* M, double* 
   return FMM_OK;
 }
 
+// FMM_OPT_ROUND_SPLIT: the (sub-grid, round) list of the entry for this form,
+// built on first use, then the two launches
+static fmm_status run_split(fmm_ctx* ctx, DescEntry* e, const double* M, double* L, fmm_precision prec,
+                            int cfg, hipStream_t s) {
+  const int f = prec == FMM_FP64_HARMONIC ? 1 : 0;
+  const int64_t nsub = (int64_t)e->host.size();
+  if (!e->split_dev[f]) {
+    std::vector<WorkItem> items;
+    std::vector<int> base((size_t)nsub);
+    for (int64_t b = 0; b < nsub; ++b) {
+      base[(size_t)b] = (int)items.size();
+      for (int r = 0; r < m2l_rounds(e->host[(size_t)b].p, f == 1); ++r) items.push_back(WorkItem{(int32_t)b, r});
+    }
+    const size_t off_base = align_up(sizeof(WorkItem) * items.size(), 256);
+    const size_t off_counter = align_up(off_base + sizeof(int) * base.size(), 256);
+    const size_t off_part = align_up(off_counter + 256, 256);
+    const size_t bytes = off_part + sizeof(double) * items.size() * 35 * kNTarget;
+    void* dev = nullptr;
+    HIP_TRY(ctx, hipMalloc(&dev, bytes));
+    char* dp = static_cast<char*>(dev);
+    hipError_t ce = hipMemcpy(dp, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice);
+    if (ce == hipSuccess) ce = hipMemcpy(dp + off_base, base.data(), sizeof(int) * base.size(), hipMemcpyHostToDevice);
+    if (ce != hipSuccess) {
+      (void)hipFree(dev);
+      return hip_err(ctx, ce, "hipMemcpy (round split list)");
+    }
+    e->split_dev[f] = dev;
+    e->split[f].items = reinterpret_cast<const WorkItem*>(dp);
+    e->split[f].count = (int)items.size();
+    e->split[f].counter = reinterpret_cast<unsigned*>(dp + off_counter);
+    e->split_base[f] = reinterpret_cast<int*>(dp + off_base);
+    e->split_part[f] = reinterpret_cast<double*>(dp + off_part);
+  }
+  HIP_TRY(ctx, launch_m2l_round_split(ctx->mfma, e->split[f], e->d_desc, nsub, e->split_base[f], M, L,
+                                      e->split_part[f], prec, cfg, s));
+  return FMM_OK;
+}
+
 static int pick_config(const fmm_ctx* ctx, const DescEntry* e, fmm_precision prec) {
   if (ctx->tile_config >= 0) return ctx->tile_config;
   if (e && e->tuned[prec] >= 0) return e->tuned[prec];
@@ -723,7 +774,11 @@ fmm_status fmm_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const do
   if (ctx->m2l_kernel == 1) {
     CHECK_OK(run_ref(ctx, e, false, M, L, s));
   } else {
-    CHECK_OK(run_mfma(ctx, e, M, L, prec, pick_config(ctx, e, prec), s));
+    const int cfg = pick_config(ctx, e, prec);
+    if (ctx->round_split && nsub <= kMaxSplitSubgrids && mfma_config_fusable(cfg))
+      CHECK_OK(run_split(ctx, e, M, L, prec, cfg, s));
+    else
+      CHECK_OK(run_mfma(ctx, e, M, L, prec, cfg, s));
   }
   return mark_used(ctx, e, s);
 }
@@ -761,6 +816,8 @@ fmm_status fmm_p2m_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, cons
   } else {
     HIP_TRY(ctx, launch_p2m(e->d_desc, nsub, e->d_ids, e->count, pos, mass, ppc, M, e->part_even, true, s));
     if (ctx->m2l_kernel == 1) CHECK_OK(run_ref(ctx, e, false, M, L, s));
+    else if (ctx->round_split && nsub <= kMaxSplitSubgrids && mfma_config_fusable(cfg))
+      CHECK_OK(run_split(ctx, e, M, L, prec, cfg, s));
     else CHECK_OK(run_mfma(ctx, e, M, L, prec, cfg, s));
   }
   return mark_used(ctx, e, s);

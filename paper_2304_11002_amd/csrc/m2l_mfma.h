@@ -120,6 +120,18 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
                            const double* M, double* L, fmm_precision prec, int cfg,
                            hipStream_t s, const double* pos = nullptr,
                            const double* mass = nullptr, double* Mw = nullptr);
+// Round split (small batches): w lists (sub-grid, round) pairs, sub-grid-major,
+// WorkItem::cost holding the round; d_base[b] is the slot (list index) of
+// sub-grid b's first round; part holds kMaxSplitSlots slots of 35 x 512
+// doubles. The rounds' raw sums go to their slots, then each sub-grid's are
+// added in round order into L. Configurations with LDS-staged tables only.
+constexpr int kMaxSplitSubgrids = 32;
+constexpr int kMaxSplitSlots = kMaxSplitSubgrids * 18;   // 18 rounds: dense p = 4
+constexpr size_t kSplitPartBytes = (size_t)kMaxSplitSlots * 35 * 512 * sizeof(double);
+int m2l_rounds(int p, bool harmonic);
+hipError_t launch_m2l_round_split(const MfmaTables& t, const WorkList& w, const DevDesc* d_desc,
+                                  int64_t nsub, const int* d_base, const double* M, double* L,
+                                  double* part, fmm_precision prec, int cfg, hipStream_t s);
 // harmonic: the harmonic form of the adjoint (equal to the dense one up to rounding)
 // pos, dmass (both or neither): the kernel also computes the mass gradients of
 // each sub-grid's dM (as launch_p2m_backward, 8 particles per cell, 16-byte

@@ -276,7 +276,25 @@ struct MomentHook {
   __device__ void run() const { moments(next); }
 };
 
-template <int P, bool PIPE, bool FULL = false, bool HARM = false, class Hook = NoHook>
+// Rounds of one call: all of them, with L written; or one round, with the raw
+// sums of its products (unscaled, before any expansion) written to `part`
+// [column][target] for a later sum over rounds.
+struct AllRounds {
+  static constexpr bool kPartial = false;
+  __device__ int begin() const { return 0; }
+  __device__ int end(int rounds) const { return rounds; }
+  __device__ double* partial() const { return nullptr; }
+};
+struct OneRound {
+  static constexpr bool kPartial = true;
+  int r;
+  double* part;
+  __device__ int begin() const { return r; }
+  __device__ int end(int) const { return r + 1; }
+  __device__ double* partial() const { return part; }
+};
+
+template <int P, bool PIPE, bool FULL = false, bool HARM = false, class Hook = NoHook, class Range = AllRounds>
 __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* __restrict__ M,
                                                double* __restrict__ L,
                                                const double* __restrict__ Bl,
@@ -285,7 +303,7 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
                                                double* sB, const int4* s_off,
                                                const HRound* __restrict__ hround = nullptr,
                                                const HExp* __restrict__ hexp = nullptr,
-                                               Hook hook = Hook()) {
+                                               Hook hook = Hook(), Range range = Range()) {
   constexpr int C = ncomp(P);
   constexpr int CR = BlShape<P, HARM>::CR;
   constexpr int NG = BlShape<P, HARM>::NG;
@@ -321,7 +339,7 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
     const bool on = lane < QC && (tw[min(lane, QC - 1)] & d.mask) != 0;
     cl0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(__ballot(on) & 0xffffffffu));
   }
-  for (int r = 0; r < ROUNDS; ++r) {
+  for (int r = range.begin(); r < range.end(ROUNDS); ++r) {
     if (hook.wants(r, ROUNDS)) {
       double* park = L + d.l_off;
       const int pxi = lane >> 4, pyi = (lane & 15) >> 2, pj = lane & 3;
@@ -563,8 +581,19 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
     }
   }
 
-  double* out = L + d.l_off;
   const int xi = lane >> 4, yi = (lane & 15) >> 2, j = lane & 3;
+  if constexpr (Range::kPartial) {
+    double* part = range.partial();
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int tcell = ((t & 1) * 4 + xi) + kBlock * ((t >> 1) * 4 + yi) + kBlock * kBlock * wave;
+#pragma unroll
+      for (int g = 0; g < NG; ++g)
+        if (4 * g + j < CR) part[(size_t)(4 * g + j) * kNTarget + tcell] = acc[t][g];
+    }
+    return;
+  }
+  double* out = L + d.l_off;
   if constexpr (HARM) {
     // harmonic columns to LDS ([n'][target], over the window, which every wave
     // has finished reading), then each thread expands one target to all C
@@ -1283,6 +1312,120 @@ __global__ void __launch_bounds__(kBwdThreads) m2l_bwd_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Round split, for batches too small to fill the GPU: work items are (sub-grid,
+// round) pairs (WorkItem::cost holds the round), each writing its round's raw
+// sums to its own slot of `part`; m2l_round_sum_kernel then adds a sub-grid's
+// rounds in round order and scales (and, in the harmonic form, expands) them
+// into L. Same products as the whole-sub-grid kernel, summed in another order.
+// ---------------------------------------------------------------------------
+constexpr int kPartStride = 35 * kNTarget;    // doubles per slot: C (p = 4) x 512
+
+template <bool PIPE, bool HARM>
+__global__ void __launch_bounds__(kBlThreads) m2l_fwd_round_kernel(
+    const WorkItem* __restrict__ items, int count, unsigned* __restrict__ counter,
+    const DevDesc* __restrict__ desc, const double* __restrict__ M, double* __restrict__ part,
+    const double* __restrict__ B2, const double* __restrict__ B3, const double* __restrict__ B4,
+    const int* __restrict__ lds_off, const uint32_t* __restrict__ touch,
+    const HRound* __restrict__ hr2, const HRound* __restrict__ hr3, const HRound* __restrict__ hr4) {
+  __shared__ double2 smem[kWinCells];
+  __shared__ double sB[2 * kBlChunkMax];
+  __shared__ int4 s_off[kQuads];
+  __shared__ int s_item;
+  if (PIPE) {
+    const int4* off4 = reinterpret_cast<const int4*>(lds_off);
+    for (int i = threadIdx.x; i < kQuads; i += blockDim.x) s_off[i] = off4[i];
+  }
+  const HExp* ne = nullptr;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= count) break;
+    const DevDesc d = desc[items[item].sub];
+    const bool full = d.mask == kFullMask;
+    const OneRound rg{items[item].cost, part + (size_t)item * kPartStride};
+    const NoHook nh;
+    switch (d.p) {
+      case 2:
+        if (PIPE && full)
+          fwd_bl_subgrid<2, PIPE, true, HARM>(d, M, nullptr, B2, lds_off, touch, smem, sB, s_off, hr2, ne, nh, rg);
+        else
+          fwd_bl_subgrid<2, PIPE, false, HARM>(d, M, nullptr, B2, lds_off, touch, smem, sB, s_off, hr2, ne, nh, rg);
+        break;
+      case 3:
+        if (PIPE && full)
+          fwd_bl_subgrid<3, PIPE, true, HARM>(d, M, nullptr, B3, lds_off, touch, smem, sB, s_off, hr3, ne, nh, rg);
+        else
+          fwd_bl_subgrid<3, PIPE, false, HARM>(d, M, nullptr, B3, lds_off, touch, smem, sB, s_off, hr3, ne, nh, rg);
+        break;
+      case 4:
+        if (HARM && PIPE && full)
+          fwd_bl_subgrid<4, PIPE, true, HARM>(d, M, nullptr, B4, lds_off, touch, smem, sB, s_off, hr4, ne, nh, rg);
+        else if (HARM && PIPE)
+          fwd_bl_subgrid<4, PIPE, false, HARM>(d, M, nullptr, B4, lds_off, touch, smem, sB, s_off, hr4, ne, nh, rg);
+        else
+          fwd_bl_subgrid<4, false, false, HARM>(d, M, nullptr, B4, lds_off, touch, smem, sB, s_off, hr4, ne, nh, rg);
+        break;
+      default: break;
+    }
+    __syncthreads();
+  }
+}
+
+template <int P, bool HARM>
+__device__ __forceinline__ void round_sum(const DevDesc& d, const double* __restrict__ part, int base,
+                                          double* __restrict__ L, const HExp* __restrict__ hexp) {
+  constexpr int C = ncomp(P);
+  constexpr int CR = HARM ? (P + 1) * (P + 1) : C;
+  constexpr int ROUNDS = (CR + 1) / 2;
+  const int tid = threadIdx.x;
+  const int l2 = d.log2_inv_h;
+  double h[CR];
+#pragma unroll
+  for (int c = 0; c < CR; ++c) h[c] = 0.0;
+  for (int r = 0; r < ROUNDS; ++r) {
+    const double* src = part + (size_t)(base + r) * kPartStride + tid;
+#pragma unroll
+    for (int c = 0; c < CR; ++c) h[c] += src[(size_t)c * kNTarget];
+  }
+  double* out = L + d.l_off + tid;
+#pragma unroll
+  for (int n = 0; n < C; ++n) {
+    double v;
+    if constexpr (HARM) {
+      const HExp& e = hexp[n];
+      v = 0.0;
+      for (int u = 0; u < e.nterm; ++u) {
+        double hc = 0.0;
+#pragma unroll
+        for (int c = 0; c < CR; ++c) hc = c == e.col[u] ? h[c] : hc;
+        v = __builtin_fma(e.coef[u], hc, v);
+      }
+    } else {
+      v = h[n];
+    }
+    out[(size_t)n * kNTarget] = ldexp(v, l2 * (1 + order_of(n)));
+  }
+}
+
+// one workgroup per sub-grid, one thread per target cell; base[b]: the slot of
+// sub-grid b's first round (its rounds are consecutive slots)
+template <bool HARM>
+__global__ void __launch_bounds__(kNTarget) m2l_round_sum_kernel(
+    const DevDesc* __restrict__ desc, const int* __restrict__ base, const double* __restrict__ part,
+    double* __restrict__ L, const HExp* __restrict__ he2, const HExp* __restrict__ he3,
+    const HExp* __restrict__ he4) {
+  const int b = blockIdx.x;
+  const DevDesc d = desc[b];
+  switch (d.p) {
+    case 2: round_sum<2, HARM>(d, part, base[b], L, he2); break;
+    case 3: round_sum<3, HARM>(d, part, base[b], L, he3); break;
+    case 4: round_sum<4, HARM>(d, part, base[b], L, he4); break;
+    default: break;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // table packing
 // ---------------------------------------------------------------------------
 
@@ -1820,6 +1963,43 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
   else if (c.waves == 4) FWD_LAUNCH(4, false);
   else return hipErrorInvalidValue;
 #undef FWD_LAUNCH
+  return hipGetLastError();
+}
+
+int m2l_rounds(int p, bool harmonic) {
+  const int cr = harmonic ? (p + 1) * (p + 1) : ncomp(p);
+  return (cr + 1) / 2;
+}
+
+hipError_t launch_m2l_round_split(const MfmaTables& t, const WorkList& w, const DevDesc* d_desc,
+                                  int64_t nsub, const int* d_base, const double* M, double* L,
+                                  double* part, fmm_precision prec, int cfg, hipStream_t s) {
+  if (w.count == 0) return hipSuccess;
+  if (!mfma_config_supports(cfg, prec) || !mfma_config_fusable(cfg) ||
+      w.count > kMaxSplitSlots || nsub > kMaxSplitSubgrids)
+    return hipErrorInvalidValue;
+  const int grid = std::min(t.num_cu, w.count);
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, w.counter);
+  const Config& c = kConfigs[cfg];
+  const bool harm = c.prec == FMM_FP64_HARMONIC;
+  if (harm)
+    hipLaunchKernelGGL((m2l_fwd_round_kernel<true, true>), dim3(grid), dim3(kBlThreads), 0, s, w.items, w.count,
+                       w.counter, d_desc, M, part, t.fwdh[2], t.fwdh[3], t.fwdh[4], t.lds_off, t.touch,
+                       t.hround[2], t.hround[3], t.hround[4]);
+  else if (c.ldstab == 2)
+    hipLaunchKernelGGL((m2l_fwd_round_kernel<true, false>), dim3(grid), dim3(kBlThreads), 0, s, w.items, w.count,
+                       w.counter, d_desc, M, part, t.fwdl[2], t.fwdl[3], t.fwdl[4], t.lds_off, t.touch,
+                       nullptr, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((m2l_fwd_round_kernel<false, false>), dim3(grid), dim3(kBlThreads), 0, s, w.items, w.count,
+                       w.counter, d_desc, M, part, t.fwdl[2], t.fwdl[3], t.fwdl[4], t.lds_off, t.touch,
+                       nullptr, nullptr, nullptr);
+  if (harm)
+    hipLaunchKernelGGL((m2l_round_sum_kernel<true>), dim3((unsigned)nsub), dim3(kNTarget), 0, s, d_desc, d_base,
+                       part, L, t.hexp[2], t.hexp[3], t.hexp[4]);
+  else
+    hipLaunchKernelGGL((m2l_round_sum_kernel<false>), dim3((unsigned)nsub), dim3(kNTarget), 0, s, d_desc, d_base,
+                       part, L, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 

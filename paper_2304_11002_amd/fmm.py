@@ -16,6 +16,7 @@ FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_EUNSUPPORTED = 0, -1, -2, -3, -4
 FMM_FP64, FMM_SPLIT_FP32, FMM_FP64_HARMONIC = 0, 1, 2
 FMM_OPT_M2L_KERNEL, FMM_OPT_USE_GRAPH, FMM_OPT_TILE_CONFIG, FMM_OPT_ADJOINT_FORM = 1, 2, 3, 4
 FMM_OPT_P2M_WINDOW = 5
+FMM_OPT_ROUND_SPLIT = 6
 
 FRAME, NCELL, NTARGET = 24, 24 ** 3, 512
 FULL_MASK = (1 << 27) - 1

@@ -96,6 +96,7 @@ def test_pointer_and_option_validation(hctx):
                  lambda: hctx.set_option(fmm.FMM_OPT_USE_GRAPH, 2),
                  lambda: hctx.set_option(99, 0),
                  lambda: hctx.set_option(fmm.FMM_OPT_P2M_WINDOW, 2),
+                 lambda: hctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 2),
                  lambda: hctx.stencil_tables(5, 8),
                  lambda: hctx.evaluate(desc, 8, 8, 0, 8, 8),
                  lambda: hctx.evaluate(desc, 8, 8, 65, 8, 8),

@@ -464,3 +464,63 @@ def test_p2m_window_option(ctx, torch):
             torch.cuda.synchronize()
             assert torch.equal(L1, L2)
 
+
+
+@pytest.mark.parametrize("prec,cfg", [(HARM, 7), (fmm.FMM_FP64, 0), (fmm.FMM_FP64, 1)])
+def test_round_split_option(ctx, torch, prec, cfg):
+    # FMM_OPT_ROUND_SPLIT: one workgroup per (sub-grid, round), rounds added in
+    # order by a second kernel; mixed orders, spacings and masks, one full
+    # sub-grid; against the oracle and, up to rounding, the whole-sub-grid path.
+    # Above 32 sub-grids the option does not apply (bitwise the usual path).
+    w = synth.config(3, nsub=9)
+    desc, m_el, l_el = descriptors(w, range(9))
+    pos, mass = particles(w, range(9))
+    M = torch.empty(m_el, dtype=torch.float64, device="cuda")
+    ctx.p2m(desc, to_dev(pos), to_dev(mass), 8, M)
+    L0 = torch.empty(l_el, dtype=torch.float64, device="cuda")
+    L1 = torch.full((l_el,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.set_option(fmm.FMM_OPT_TILE_CONFIG, cfg)
+    try:
+        ctx.m2l(desc, M, L0, prec)
+        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 1)
+        ctx.m2l(desc, M, L1, prec)
+        L2 = torch.full_like(L1, float("nan"))
+        ctx.m2l(desc, M, L2, prec)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 0)
+        ctx.set_option(fmm.FMM_OPT_TILE_CONFIG, -1)
+    assert torch.equal(L1, L2)                       # deterministic
+    Lg, L0v = split_views(L1.cpu().numpy(), desc, "L"), split_views(L0.cpu().numpy(), desc, "L")
+    for b in range(9):
+        _, Lo, La = oracle_subgrid(w, b, pos[b], mass[b])
+        assert_close(Lg[b], Lo, La, TOL, "round split sub-grid %d (p=%d)" % (b, w.p[b]))
+        assert_close(Lg[b], L0v[b], La, 1e-13, "round split vs whole sub-grid %d" % b)
+    w1 = synth.config(1)
+    desc1, m1, l1 = descriptors(w1, [0])
+    p1, ms1 = particles(w1, [0])
+    M1 = torch.empty(m1, dtype=torch.float64, device="cuda")
+    ctx.p2m(desc1, to_dev(p1), to_dev(ms1), 8, M1)
+    L1s = torch.empty(l1, dtype=torch.float64, device="cuda")
+    ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 1)
+    try:
+        ctx.m2l(desc1, M1, L1s, prec)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 0)
+    _, Lo, La = oracle_subgrid(w1, 0, p1[0], ms1[0])
+    assert_close(L1s.cpu().numpy().reshape(Lo.shape), Lo, La, TOL, "round split single sub-grid")
+    w = synth.config(3, nsub=33)
+    desc, m_el, l_el = descriptors(w, range(33))
+    pos, mass = particles(w, range(33))
+    M = torch.empty(m_el, dtype=torch.float64, device="cuda")
+    ctx.p2m(desc, to_dev(pos), to_dev(mass), 8, M)
+    La_, Lb_ = torch.empty(l_el, dtype=torch.float64, device="cuda"), torch.empty(l_el, dtype=torch.float64, device="cuda")
+    ctx.m2l(desc, M, La_, prec)
+    ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 1)
+    try:
+        ctx.m2l(desc, M, Lb_, prec)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 0)
+    assert torch.equal(La_, Lb_)
