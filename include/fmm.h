@@ -99,12 +99,13 @@ typedef struct {
                                   (p+1)^2 harmonic columns, dM expanded from the folded components;
                                   equal to the dense adjoint up to rounding; MFMA kernel only) */
 #define FMM_OPT_ROUND_SPLIT 6  /* fmm_m2l (and the M2L of fmm_p2m_m2l when it runs as two
-                                  launches) on batches of at most 32 sub-grids, with a configuration
+                                  launches) on batches of at most 256 sub-grids, with a configuration
                                   with LDS-staged tables: 0 (default) one workgroup per sub-grid;
                                   1 one workgroup per (sub-grid, round of two moment components),
-                                  each round's sums added in round order by a second kernel (for
-                                  latency when a batch cannot fill the GPU; equal up to rounding;
-                                  device memory for the rounds' sums is held per descriptor set) */
+                                  each round's sums added in round order by a second kernel. For
+                                  batches that cannot fill the GPU, or whose longest sub-grid (p = 4)
+                                  would set the time; equal up to rounding; 140 KB of device memory
+                                  per (sub-grid, round) is held per descriptor set. */
 
 /* Create a context on HIP device `device`, or a host-only context with
  * device = -1 (argument checking and host queries only; compute calls then

@@ -125,7 +125,7 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
 // sub-grid b's first round; part holds kMaxSplitSlots slots of 35 x 512
 // doubles. The rounds' raw sums go to their slots, then each sub-grid's are
 // added in round order into L. Configurations with LDS-staged tables only.
-constexpr int kMaxSplitSubgrids = 32;
+constexpr int kMaxSplitSubgrids = 256;
 constexpr int kMaxSplitSlots = kMaxSplitSubgrids * 18;   // 18 rounds: dense p = 4
 constexpr size_t kSplitPartBytes = (size_t)kMaxSplitSlots * 35 * 512 * sizeof(double);
 int m2l_rounds(int p, bool harmonic);

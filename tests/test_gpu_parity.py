@@ -471,7 +471,7 @@ def test_round_split_option(ctx, torch, prec, cfg):
     # FMM_OPT_ROUND_SPLIT: one workgroup per (sub-grid, round), rounds added in
     # order by a second kernel; mixed orders, spacings and masks, one full
     # sub-grid; against the oracle and, up to rounding, the whole-sub-grid path.
-    # Above 32 sub-grids the option does not apply (bitwise the usual path).
+    # Above 256 sub-grids the option does not apply (bitwise the usual path).
     w = synth.config(3, nsub=9)
     desc, m_el, l_el = descriptors(w, range(9))
     pos, mass = particles(w, range(9))
@@ -510,9 +510,9 @@ def test_round_split_option(ctx, torch, prec, cfg):
         ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 0)
     _, Lo, La = oracle_subgrid(w1, 0, p1[0], ms1[0])
     assert_close(L1s.cpu().numpy().reshape(Lo.shape), Lo, La, TOL, "round split single sub-grid")
-    w = synth.config(3, nsub=33)
-    desc, m_el, l_el = descriptors(w, range(33))
-    pos, mass = particles(w, range(33))
+    w = synth.config(3, nsub=257)
+    desc, m_el, l_el = descriptors(w, range(257))
+    pos, mass = particles(w, range(257))
     M = torch.empty(m_el, dtype=torch.float64, device="cuda")
     ctx.p2m(desc, to_dev(pos), to_dev(mass), 8, M)
     La_, Lb_ = torch.empty(l_el, dtype=torch.float64, device="cuda"), torch.empty(l_el, dtype=torch.float64, device="cuda")
@@ -524,3 +524,32 @@ def test_round_split_option(ctx, torch, prec, cfg):
     finally:
         ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 0)
     assert torch.equal(La_, Lb_)
+
+
+def test_round_split_mid_size_uneven_batch(ctx, torch):
+    # 200 uneven sub-grids (thousands of round slots): the split path against the
+    # whole-sub-grid path everywhere (1e-12 of each component's largest |L| in
+    # the sub-grid) and against the oracle on sampled sub-grids of every order
+    n = 200
+    w = synth.config(3, nsub=n)
+    desc, m_el, l_el = descriptors(w, range(n))
+    pos, mass = particles(w, range(n))
+    M = torch.empty(m_el, dtype=torch.float64, device="cuda")
+    ctx.p2m(desc, to_dev(pos), to_dev(mass), 8, M)
+    L0 = torch.empty(l_el, dtype=torch.float64, device="cuda")
+    L1 = torch.full((l_el,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.m2l(desc, M, L0, HARM)
+    ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 1)
+    try:
+        ctx.m2l(desc, M, L1, HARM)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 0)
+    Lg, L0v = split_views(L1.cpu().numpy(), desc, "L"), split_views(L0.cpu().numpy(), desc, "L")
+    for b in range(n):
+        scale = np.abs(L0v[b]).reshape(L0v[b].shape[0], -1).max(axis=1)[:, None, None, None]
+        assert (np.abs(Lg[b] - L0v[b]) <= 1e-12 * scale).all(), "sub-grid %d" % b
+    for p in (2, 3, 4):
+        b = int(np.flatnonzero(w.p == p)[-1])
+        _, Lo, La = oracle_subgrid(w, b, pos[b], mass[b])
+        assert_close(Lg[b], Lo, La, TOL, "round split mid-size sub-grid %d (p=%d)" % (b, p))
