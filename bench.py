@@ -614,6 +614,34 @@ def main():
             % (np.median(seg1[:, 0]), np.median(seg1s[:, 0])))
         del pos1, mass1, M1, L1
 
+        # ---------------- a small uneven batch (128 sub-grids drawn like the uneven
+        # workload): M2L with one workgroup per sub-grid and with the rounds split
+        w128 = synth.config(3, nsub=128)
+        d128, m128, l128 = fmm.make_descriptors(w128.p, w128.log2_inv_h, w128.mask)
+        p128, ms128 = upload_batch(torch, w128)
+        M128 = torch.empty(m128, dtype=torch.float64, device="cuda")
+        L128 = torch.empty(l128, dtype=torch.float64, device="cuda")
+        ctx.p2m(d128, p128, ms128, 8, M128)
+
+        def step_small(ev, i):
+            if ev: ev[0].record()
+            ctx.m2l(d128, M128, L128, fmm.FMM_FP64_HARMONIC)
+            if ev: ev[1].record()
+
+        _, seg_sw = timed(torch, step_small, K, W, marks=1)
+        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 1)
+        try:
+            _, seg_ss = timed(torch, step_small, K, W, marks=1)
+        finally:
+            ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 0)
+        out["small_uneven_batch"] = {"workload": "uneven_128_mixed_p (p 1:2:1, random masks, three spacings)",
+                                     "pairs": fmm.pair_count(d128),
+                                     "form": "harmonic", "m2l_ms": float(np.median(seg_sw[:, 0])),
+                                     "round_split_m2l_ms": float(np.median(seg_ss[:, 0]))}
+        log("uneven 128: M2L %.3f ms, %.3f ms with the rounds split over workgroups"
+            % (np.median(seg_sw[:, 0]), np.median(seg_ss[:, 0])))
+        del p128, ms128, M128, L128
+
         # ---------------- CPU baseline (the oracle on the host cores)
         out["cpu_baseline"] = cpu_baseline(w.nsub, args.cpu_seconds)
         log("cpu_baseline %.4g pairs/s on %d cores" % (out["cpu_baseline"]["value"], out["cpu_baseline"]["cores"]))
