@@ -273,3 +273,29 @@ def test_fused_backward_two_launch_cases(ctx, torch, case):
     finally:
         ctx.set_option(fmm.FMM_OPT_M2L_KERNEL, 0)
     assert torch.equal(dM1, dM2) and torch.equal(dm1, dm2)
+
+
+# seeded compositions: batch size just above and well above the compute-unit
+# count, order mix, spacings and masks drawn per sub-grid (full blocks included)
+def _random_batch(seed, n):
+    rng = np.random.default_rng([seed, 1234])
+    p = rng.choice(np.array([2, 3, 4], np.int32), size=n, p=[0.3, 0.4, 0.3]).astype(np.int32)
+    lh = rng.integers(0, 3, n).astype(np.int32)
+    masks = np.array([synth.FULL_MASK if rng.random() < 0.3 else synth.random_mask(rng) for _ in range(n)],
+                     np.uint32)
+    return synth.Workload("sweep_%d" % seed, 60 + seed, p, lh, masks)
+
+
+@pytest.mark.parametrize("seed,n", [(1, 257), (2, 333), (3, 520)])
+def test_one_launch_sweep(ctx, torch, seed, n):
+    w = _random_batch(seed, n)
+    forms = [(fmm.FMM_FP64_HARMONIC, HARM_CFG), (fmm.FMM_FP64, 0)]
+    desc, pos, mass, out = run_forms(ctx, torch, w, range(n), forms)
+    W = to_dev(np.random.default_rng(seed).standard_normal(int(desc["l_off"][-1]) + 512 * fmm.ncomp(int(w.p[-1]))))
+    m_el = int(desc["m_off"][-1]) + fmm.NCELL * fmm.ncomp(int(w.p[-1]))
+    ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 1)
+    try:
+        dM1, dm1, dM2, dm2 = backward_both(ctx, torch, desc, to_dev(pos), 8, W, m_el, n * fmm.NCELL * 8)
+    finally:
+        ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 0)
+    assert torch.equal(dM1, dM2) and torch.equal(dm1, dm2)
