@@ -326,7 +326,7 @@ def main():
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "repeats": 3}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs its hot path on a single MI355X "
+        print("bench.py measures one GPU: the library runs its hot path on a single MI355X "
               "(sub-grids are independent, so a batch would shard by sub-grid across GPUs). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
