@@ -42,6 +42,10 @@
  *     returns FMM_EINVAL has touched neither the device nor the context's
  *     caches. HIP failures return FMM_EHIP; fmm_last_error() gives detail.
  *   - A context is not thread-safe: use one per host thread.
+ *   - Calls with the same descriptor set are ordered even on different
+ *     streams (each waits on the device for the previous one, since they
+ *     share that set's work-list counters); calls with different sets, and
+ *     the fmm_tree_* calls, may run concurrently.
  *   - Results are deterministic run to run: every output element is owned
  *     by one work item and summed in a fixed order.
  */

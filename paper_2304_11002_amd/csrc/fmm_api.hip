@@ -247,7 +247,10 @@ fmm_status get_desc(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, hipStre
     if (e->hash == h && e->host.size() == (size_t)nsub &&
         std::memcmp(e->host.data(), desc, nbytes) == 0) {
       e->last_use = ++ctx->clock;
-      HIP_TRY(ctx, hipStreamWaitEvent(stream, e->ready, 0));
+      // order after the previous call on this set, whatever its stream: calls
+      // share the set's work-list counters and round-split partials (the event
+      // was first recorded after the upload, so this also covers the upload)
+      HIP_TRY(ctx, hipStreamWaitEvent(stream, e->last_launch, 0));
       *out = e.get();
       return FMM_OK;
     }
@@ -309,6 +312,7 @@ fmm_status get_desc(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, hipStre
   HIP_TRY(ctx, hipEventCreateWithFlags(&e->last_launch, hipEventDisableTiming));
   HIP_TRY(ctx, hipMemcpyAsync(e->dev, e->pinned, e->bytes, hipMemcpyHostToDevice, stream));
   HIP_TRY(ctx, hipEventRecord(e->ready, stream));
+  HIP_TRY(ctx, hipEventRecord(e->last_launch, stream));
   *out = e.get();
   ctx->descs.push_back(std::move(e));
   return FMM_OK;

@@ -299,3 +299,39 @@ def test_one_launch_sweep(ctx, torch, seed, n):
     finally:
         ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 0)
     assert torch.equal(dM1, dM2) and torch.equal(dm1, dm2)
+
+
+def test_same_descriptor_set_on_two_streams(ctx, torch):
+    # calls with one descriptor set share its work-list counter: enqueued on two
+    # streams without host synchronisation, they must still give the results of
+    # the same calls made one after the other
+    n = 600
+    w = synth.config(2, nsub=n)
+    assert w.ppc == 8
+    desc, m_el, l_el = descriptors(w, range(n))
+    pos, mass = particles(w, range(n))
+    dpos = to_dev(pos)
+    dmass = [to_dev(mass), to_dev(mass * 0.75 + 0.125)]
+    prec = fmm.FMM_FP64_HARMONIC
+    want = [fused(ctx, torch, desc, dpos, dm, 8, m_el, l_el, prec) for dm in dmass]
+    want_m2l = []
+    for Mw, _ in want:
+        L = torch.full((l_el,), float("nan"), dtype=torch.float64, device="cuda")
+        ctx.m2l(desc, Mw, L, prec)
+        want_m2l.append(L)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [[torch.full((m_el,), float("nan"), dtype=torch.float64, device="cuda"),
+             torch.full((l_el,), float("nan"), dtype=torch.float64, device="cuda"),
+             torch.full((l_el,), float("nan"), dtype=torch.float64, device="cuda")] for _ in range(2)]
+    torch.cuda.synchronize()
+    for _ in range(3):
+        for i in (0, 1):
+            M, L, L2 = outs[i]
+            ctx.p2m_m2l(desc, dpos, dmass[i], 8, M, L, prec, streams[i])
+            ctx.m2l(desc, M, L2, prec, streams[i])
+    torch.cuda.synchronize()
+    for i in (0, 1):
+        M, L, L2 = outs[i]
+        assert torch.equal(L, want[i][1]), "stream %d: one-launch L differs" % i
+        assert torch.equal(L2, want_m2l[i]), "stream %d: M2L-only L differs" % i
+        assert torch.equal(L, L2), "stream %d: the two forms differ" % i
