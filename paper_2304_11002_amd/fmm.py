@@ -18,7 +18,7 @@ FMM_OPT_M2L_KERNEL, FMM_OPT_USE_GRAPH, FMM_OPT_TILE_CONFIG, FMM_OPT_ADJOINT_FORM
 FMM_OPT_P2M_WINDOW = 5
 FMM_OPT_ROUND_SPLIT = 6
 
-FRAME, NCELL, NTARGET = 24, 24 ** 3, 512
+FRAME, NCELL, NTARGET, NSTENCIL = 24, 24 ** 3, 512, 892
 FULL_MASK = (1 << 27) - 1
 
 EXPORTS = [
@@ -111,6 +111,46 @@ def _ptr(t):
     if isinstance(t, int):
         return t
     return t.data_ptr()
+
+
+def _ncomp(p):
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def _desc_extents(desc, ppc=None):
+    """float64 elements each ragged buffer must hold for these descriptors:
+    M and L up to the furthest block end, particles up to the furthest
+    sub-grid's last particle. None where the descriptors (or ppc) are not
+    valid: the library rejects those itself."""
+    if desc is None or len(desc) == 0:
+        return {}
+    p = desc["p"].astype(np.int64)
+    if p.min() < 2 or p.max() > 4:
+        return {}
+    C = _ncomp(p)
+    ext = {}
+    if (desc["m_off"] >= 0).all():
+        ext["M"] = int((desc["m_off"] + C * NCELL).max())
+    if (desc["l_off"] >= 0).all():
+        ext["L"] = int((desc["l_off"] + C * NTARGET).max())
+    if ppc is not None and 1 <= int(ppc) <= 64 and (desc["part_off"] >= 0).all():
+        last = int((desc["part_off"] + NCELL * int(ppc)).max())
+        ext["pos"], ext["mass"] = 3 * last, last
+        ext["out"] = 4 * NTARGET * int(ppc) * len(desc)
+    return ext
+
+
+def _tree_extents(tree):
+    t = (tree.p, tree.n, tree.ppc)
+    if not (2 <= t[0] <= 4 and t[1] in (8, 16, 32, 64, 128) and 1 <= t[2] <= 64):
+        return {}
+    cells = t[1] ** 3
+    ext = {"pos": 3 * cells * t[2], "mass": cells * t[2], "out": 4 * cells * t[2]}
+    try:
+        ext["M"] = ext["L"] = tree_size(tree)[1]
+    except FMMError:
+        pass
+    return ext
 
 
 def _stream(stream):
@@ -218,73 +258,115 @@ class Context:
     def _run(self, status):
         _check(status, self.handle)
 
+    def _buf(self, t, ext, kind, name):
+        """Address of a float64 buffer after the checks the C ABI cannot make
+        (element type, contiguity, device, size). Integers pass through as raw
+        addresses, which the caller vouches for."""
+        if t is None or isinstance(t, int):
+            return t
+        if str(t.dtype) != "torch.float64":
+            raise TypeError("%s must be float64, got %s" % (name, t.dtype))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        if self.device >= 0 and (not t.is_cuda or t.device.index != self.device):
+            raise ValueError("%s must be on cuda:%d, got %s" % (name, self.device, t.device))
+        need = ext.get(kind)
+        if need is not None and t.numel() < need:
+            raise ValueError("%s holds %d elements, the descriptors address %d" % (name, t.numel(), need))
+        return t.data_ptr()
+
     def set_option(self, option, value):
         self._run(self.lib.fmm_set_option(self.handle, option, int(value)))
 
     def p2m(self, desc, pos, mass, ppc, M, stream=None):
         pd, n = _desc_ptr(desc)
-        self._run(self.lib.fmm_p2m(self.handle, pd, n, _ptr(pos), _ptr(mass), int(ppc), _ptr(M),
+        e = _desc_extents(desc, ppc)
+        self._run(self.lib.fmm_p2m(self.handle, pd, n, self._buf(pos, e, "pos", "pos"),
+                                   self._buf(mass, e, "mass", "mass"), int(ppc), self._buf(M, e, "M", "M"),
                                    self._s(stream, n)))
 
     def m2l(self, desc, M, L, precision=FMM_FP64, stream=None):
         pd, n = _desc_ptr(desc)
-        self._run(self.lib.fmm_m2l(self.handle, pd, n, _ptr(M), _ptr(L), int(precision),
-                                   self._s(stream, n)))
+        e = _desc_extents(desc)
+        self._run(self.lib.fmm_m2l(self.handle, pd, n, self._buf(M, e, "M", "M"), self._buf(L, e, "L", "L"),
+                                   int(precision), self._s(stream, n)))
 
     def p2m_m2l(self, desc, pos, mass, ppc, M, L, precision=FMM_FP64, stream=None):
         """P2M over the rows holding the reachable window, then M2L, in one launch."""
         pd, n = _desc_ptr(desc)
-        self._run(self.lib.fmm_p2m_m2l(self.handle, pd, n, _ptr(pos), _ptr(mass), int(ppc), _ptr(M),
-                                       _ptr(L), int(precision), self._s(stream, n)))
+        e = _desc_extents(desc, ppc)
+        self._run(self.lib.fmm_p2m_m2l(self.handle, pd, n, self._buf(pos, e, "pos", "pos"),
+                                       self._buf(mass, e, "mass", "mass"), int(ppc), self._buf(M, e, "M", "M"),
+                                       self._buf(L, e, "L", "L"), int(precision), self._s(stream, n)))
 
     def m2l_backward(self, desc, dL, dM, stream=None):
         pd, n = _desc_ptr(desc)
-        self._run(self.lib.fmm_m2l_backward(self.handle, pd, n, _ptr(dL), _ptr(dM),
-                                            self._s(stream, n)))
+        e = _desc_extents(desc)
+        self._run(self.lib.fmm_m2l_backward(self.handle, pd, n, self._buf(dL, e, "L", "dL"),
+                                            self._buf(dM, e, "M", "dM"), self._s(stream, n)))
 
     def m2l_p2m_backward(self, desc, pos, ppc, dL, dM, dmass, stream=None):
         """M2L adjoint (dL -> dM) and P2M adjoint (dM -> dmass) in one launch."""
         pd, n = _desc_ptr(desc)
-        self._run(self.lib.fmm_m2l_p2m_backward(self.handle, pd, n, _ptr(pos), int(ppc), _ptr(dL),
-                                                _ptr(dM), _ptr(dmass), self._s(stream, n)))
+        e = _desc_extents(desc, ppc)
+        self._run(self.lib.fmm_m2l_p2m_backward(self.handle, pd, n, self._buf(pos, e, "pos", "pos"), int(ppc),
+                                                self._buf(dL, e, "L", "dL"), self._buf(dM, e, "M", "dM"),
+                                                self._buf(dmass, e, "mass", "dmass"), self._s(stream, n)))
 
     def p2m_backward(self, desc, pos, ppc, dM, dmass, stream=None):
         pd, n = _desc_ptr(desc)
-        self._run(self.lib.fmm_p2m_backward(self.handle, pd, n, _ptr(pos), int(ppc), _ptr(dM),
-                                            _ptr(dmass), self._s(stream, n)))
+        e = _desc_extents(desc, ppc)
+        self._run(self.lib.fmm_p2m_backward(self.handle, pd, n, self._buf(pos, e, "pos", "pos"), int(ppc),
+                                            self._buf(dM, e, "M", "dM"), self._buf(dmass, e, "mass", "dmass"),
+                                            self._s(stream, n)))
 
     def evaluate(self, desc, pos, mass, ppc, L, out, stream=None):
         """Near field + L2P: out [nsub, 4, 512, ppc] (phi, grad x, y, z)."""
         pd, n = _desc_ptr(desc)
-        self._run(self.lib.fmm_evaluate(self.handle, pd, n, _ptr(pos), _ptr(mass), int(ppc),
-                                        _ptr(L), _ptr(out), self._s(stream, n)))
+        e = _desc_extents(desc, ppc)
+        self._run(self.lib.fmm_evaluate(self.handle, pd, n, self._buf(pos, e, "pos", "pos"),
+                                        self._buf(mass, e, "mass", "mass"), int(ppc), self._buf(L, e, "L", "L"),
+                                        self._buf(out, e, "out", "out"), self._s(stream, n)))
 
     # multi-level iteration on a uniform octree (tree: a Tree)
     def tree_upward(self, tree, pos, mass, M, stream=None):
-        self._run(self.lib.fmm_tree_upward(self.handle, ctypes.byref(tree), _ptr(pos), _ptr(mass),
-                                           _ptr(M), self._s(stream, 1)))
+        e = _tree_extents(tree)
+        self._run(self.lib.fmm_tree_upward(self.handle, ctypes.byref(tree), self._buf(pos, e, "pos", "pos"),
+                                           self._buf(mass, e, "mass", "mass"), self._buf(M, e, "M", "M"),
+                                           self._s(stream, 1)))
 
     def tree_m2l(self, tree, M, L, stream=None):
-        self._run(self.lib.fmm_tree_m2l(self.handle, ctypes.byref(tree), _ptr(M), _ptr(L),
-                                        self._s(stream, 1)))
+        e = _tree_extents(tree)
+        self._run(self.lib.fmm_tree_m2l(self.handle, ctypes.byref(tree), self._buf(M, e, "M", "M"),
+                                        self._buf(L, e, "L", "L"), self._s(stream, 1)))
 
     def tree_downward(self, tree, L, stream=None):
-        self._run(self.lib.fmm_tree_downward(self.handle, ctypes.byref(tree), _ptr(L), self._s(stream, 1)))
+        e = _tree_extents(tree)
+        self._run(self.lib.fmm_tree_downward(self.handle, ctypes.byref(tree), self._buf(L, e, "L", "L"),
+                                             self._s(stream, 1)))
 
     def tree_evaluate(self, tree, pos, mass, L, out, stream=None):
-        self._run(self.lib.fmm_tree_evaluate(self.handle, ctypes.byref(tree), _ptr(pos), _ptr(mass),
-                                             _ptr(L), _ptr(out), self._s(stream, 1)))
+        e = _tree_extents(tree)
+        self._run(self.lib.fmm_tree_evaluate(self.handle, ctypes.byref(tree), self._buf(pos, e, "pos", "pos"),
+                                             self._buf(mass, e, "mass", "mass"), self._buf(L, e, "L", "L"),
+                                             self._buf(out, e, "out", "out"), self._s(stream, 1)))
 
     def tree_solve(self, tree, pos, mass, M, L, out, stream=None):
-        self._run(self.lib.fmm_tree_solve(self.handle, ctypes.byref(tree), _ptr(pos), _ptr(mass),
-                                          _ptr(M), _ptr(L), _ptr(out), self._s(stream, 1)))
+        e = _tree_extents(tree)
+        self._run(self.lib.fmm_tree_solve(self.handle, ctypes.byref(tree), self._buf(pos, e, "pos", "pos"),
+                                          self._buf(mass, e, "mass", "mass"), self._buf(M, e, "M", "M"),
+                                          self._buf(L, e, "L", "L"), self._buf(out, e, "out", "out"),
+                                          self._s(stream, 1)))
 
     def stencil_tables(self, p, out, stream=None):
-        self._run(self.lib.fmm_stencil_tables(self.handle, int(p), _ptr(out), self._s(stream, 1)))
+        e = {"out": NSTENCIL * _ncomp(int(p)) ** 2} if 2 <= int(p) <= 4 else {}
+        self._run(self.lib.fmm_stencil_tables(self.handle, int(p), self._buf(out, e, "out", "out"),
+                                              self._s(stream, 1)))
 
     def autotune(self, desc, M, L, precision=FMM_FP64, stream=None):
         pd, n = _desc_ptr(desc)
         chosen = ctypes.c_int32(-1)
-        self._run(self.lib.fmm_autotune(self.handle, pd, n, _ptr(M), _ptr(L), int(precision),
-                                        self._s(stream, n), ctypes.byref(chosen)))
+        e = _desc_extents(desc)
+        self._run(self.lib.fmm_autotune(self.handle, pd, n, self._buf(M, e, "M", "M"), self._buf(L, e, "L", "L"),
+                                        int(precision), self._s(stream, n), ctypes.byref(chosen)))
         return chosen.value

@@ -212,3 +212,44 @@ def test_tree_argument_checks(hctx, lib):
         assert e.value.status == fmm.FMM_EUNSUPPORTED
     assert lib.fmm_tree_size(None, None, None) == fmm.FMM_EINVAL
 
+
+
+def test_binding_checks_tensor_arguments(hctx):
+    # the C ABI takes plain pointers; the binding checks what it can about the
+    # tensors behind them (element type, contiguity, extent from the descriptors)
+    import torch
+    desc, m_el, l_el = fmm.make_descriptors([2, 3], [0, 1], [synth.FULL_MASK] * 2)
+    M = torch.zeros(m_el, dtype=torch.float64)
+    L = torch.zeros(l_el, dtype=torch.float64)
+    n_part = 2 * fmm.NCELL * 8
+    pos, mass = torch.zeros(3 * n_part, dtype=torch.float64), torch.zeros(n_part, dtype=torch.float64)
+    with pytest.raises(TypeError, match="float64"):
+        hctx.m2l(desc, M.float(), L)
+    with pytest.raises(ValueError, match="contiguous"):
+        hctx.m2l(desc, M, torch.zeros(2 * l_el, dtype=torch.float64)[::2])
+    with pytest.raises(ValueError, match="elements"):
+        hctx.m2l(desc, M[:-1], L)
+    with pytest.raises(ValueError, match="elements"):
+        hctx.m2l(desc, M, L[:-1])
+    with pytest.raises(ValueError, match="elements"):
+        hctx.p2m_m2l(desc, pos[:-3], mass, 8, M, L)
+    with pytest.raises(ValueError, match="elements"):
+        hctx.m2l_p2m_backward(desc, pos, 8, L, M, mass[:-1])
+    with pytest.raises(ValueError, match="elements"):
+        hctx.evaluate(desc, pos, mass, 8, L, torch.zeros(4 * 512 * 8 * 2 - 1, dtype=torch.float64))
+    tree = fmm.Tree(3, 8, 2, 0)
+    with pytest.raises(ValueError, match="elements"):
+        hctx.tree_solve(tree, torch.zeros(3 * 512 * 2 - 1, dtype=torch.float64),
+                        torch.zeros(512 * 2, dtype=torch.float64), M, L, L)
+    with pytest.raises(ValueError, match="elements"):
+        hctx.stencil_tables(3, torch.zeros(892 * 400 - 1, dtype=torch.float64))
+    # buffers of the right kind reach the library (a host-only context then declines)
+    for call in (lambda: hctx.m2l(desc, M, L), lambda: hctx.p2m_m2l(desc, pos, mass, 8, M, L),
+                 lambda: hctx.evaluate(desc, pos, mass, 8, L, torch.zeros(4 * 512 * 8 * 2, dtype=torch.float64))):
+        with pytest.raises(fmm.FMMError) as e:
+            call()
+        assert e.value.status == fmm.FMM_EUNSUPPORTED
+    # a descriptor the library rejects is reported by the library, not by the size check
+    with pytest.raises(fmm.FMMError) as e:
+        hctx.m2l(_bad(desc, "p", 5), M[:8], L[:8])
+    assert e.value.status == fmm.FMM_EINVAL
