@@ -335,3 +335,20 @@ def test_same_descriptor_set_on_two_streams(ctx, torch):
         assert torch.equal(L, want[i][1]), "stream %d: one-launch L differs" % i
         assert torch.equal(L2, want_m2l[i]), "stream %d: M2L-only L differs" % i
         assert torch.equal(L, L2), "stream %d: the two forms differ" % i
+
+
+def test_binding_rejects_host_and_short_buffers(ctx, torch):
+    # raised by the binding before the library is called: nothing is enqueued
+    w = synth.config(2, nsub=2)
+    desc, m_el, l_el = descriptors(w, range(2))
+    M = torch.zeros(m_el, dtype=torch.float64, device="cuda")
+    L = torch.zeros(l_el, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError, match="cuda:0"):
+        ctx.m2l(desc, M.cpu(), L)
+    with pytest.raises(ValueError, match="elements"):
+        ctx.m2l(desc, M, L[:-512])
+    with pytest.raises(TypeError, match="float64"):
+        ctx.m2l(desc, M, L.float())
+    ctx.m2l(desc, M, L)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(L) == 0      # zero moments give zero expansions
