@@ -7,6 +7,7 @@ direct Newtonian sum, the rigorous truncation bound, exact symmetries of the
 stencil and of the Laplace kernel, and the adjoint identities.
 """
 import os
+from itertools import product
 from math import factorial
 
 import numpy as np
@@ -271,24 +272,49 @@ def test_translation_invariance():
     assert np.all(np.abs(LA[:, 1:] - LB[:, :-1]) <= 1e-13 * La[:, 1:])
 
 
-def test_reflection_and_axis_swap_equivariance():
+def _cubic_map(A, ks, perm, signs):
+    """Apply the cubic symmetry (reflect axis i where signs[i] < 0, then new axis i =
+    old axis perm[i]) to a component-major field A [C][z][y][x]: cells move with the
+    map, component k picks up prod (-1)^k_i over reflected axes and is relabelled
+    k'_i = k_perm[i]."""
+    B = np.array(A, dtype=np.float64)
+    for ax in range(3):
+        if signs[ax] < 0:
+            B = np.flip(B, axis=3 - ax)
+            B = B * np.array([(-1.0) ** k[ax] for k in ks])[:, None, None, None]
+    # [C][z][y][x] -> axes in x, y, z order, permute, back
+    Bx = np.transpose(B, (0, 3, 2, 1))
+    Bx = np.transpose(Bx, (0,) + tuple(1 + q for q in perm))
+    B = np.transpose(Bx, (0, 3, 2, 1))
+    src_of = [ks.index(tuple(k[perm[i]] for i in range(3))) for k in ks]
+    out = np.empty_like(B)
+    for c, s in enumerate(src_of):
+        out[s] = B[c]
+    return out
+
+
+def test_cubic_group_equivariance():
+    # all 48 symmetries of the cube (6 axis permutations x 8 reflections) map the
+    # shell stencil to itself, so M2L commutes with each of them; they include the
+    # z reflection and the permutations that move z, not only x reflection and x<->y
+    from itertools import permutations
     p = 3
     ks = O.multi_indices(p)
-    C = len(ks)
-    M = _random_moments(5, C)
+    M = _random_moments(5, len(ks))
     L = O.m2l(M, p, 1.0)
     La = O.m2l_abs(M, p, 1.0)
-    # x-reflection: j_x -> 23 - j_x, moments pick up (-1)^kx
-    sx = np.array([(-1.0) ** k[0] for k in ks])
-    Mr = M[:, :, :, ::-1] * sx[:, None, None, None]
-    Lr = O.m2l(Mr, p, 1.0)
-    assert np.all(np.abs(Lr - L[:, :, :, ::-1] * sx[:, None, None, None]) <= 1e-13 * La[:, :, :, ::-1])
-    # swap x <-> y: component (a, b, c) <-> (b, a, c), axes [z][y][x] -> [z][x][y]
-    perm = [ks.index((k[1], k[0], k[2])) for k in ks]
-    Ms = np.transpose(M, (0, 1, 3, 2))[perm]
-    Ls = O.m2l(Ms, p, 1.0)
-    want = np.transpose(L, (0, 1, 3, 2))[perm]
-    assert np.all(np.abs(Ls - want) <= 1e-13 * np.transpose(La, (0, 1, 3, 2))[perm])
+    count = 0
+    for perm in permutations(range(3)):
+        for signs in product((1, -1), repeat=3):
+            Lg = O.m2l(_cubic_map(M, ks, perm, signs), p, 1.0)
+            want = _cubic_map(L, ks, perm, signs)
+            scale = np.abs(_cubic_map(La, ks, perm, signs))
+            assert np.all(np.abs(Lg - want) <= 1e-13 * scale), (perm, signs)
+            count += 1
+    assert count == 48
+    # the map itself is not trivial: a z reflection changes a generic field
+    assert not np.allclose(_cubic_map(M, ks, (0, 1, 2), (1, 1, -1)), M)
+    assert not np.allclose(_cubic_map(M, ks, (2, 1, 0), (1, 1, 1)), M)
 
 
 def test_local_expansion_is_traceless_and_ignores_trace_moments():
