@@ -37,7 +37,21 @@
  *     the library never frees caller memory and owns only what a context
  *     holds (stencil tables, work lists, captured graphs, tuning choices).
  *   - Compute calls are asynchronous on `stream` (a hipStream_t, NULL for
- *     the null stream) and never synchronise the device.
+ *     the null stream). The host waits, and memory is allocated, only in
+ *     these cases:
+ *       * the first call with a descriptor set the context does not hold
+ *         allocates device and pinned host memory for its copy and work
+ *         lists (hipMalloc, hipHostMalloc);
+ *       * when the context already holds 8 sets, that call first evicts the
+ *         least recently used one: the host waits for that set's last launch
+ *         and frees its memory and the graphs captured for it (graphs of the
+ *         other sets are kept);
+ *       * with FMM_OPT_USE_GRAPH, capturing a 17th graph first releases the
+ *         least recently used graph, after the host has waited for that
+ *         graph's last launch (on whatever stream it ran);
+ *       * the first FMM_OPT_ROUND_SPLIT call on a set allocates its round
+ *         list and round sums, held with the set;
+ *     fmm_create, fmm_destroy and fmm_autotune synchronise.
  *   - All argument checks run on the host before any HIP call: a call that
  *     returns FMM_EINVAL has touched neither the device nor the context's
  *     caches. HIP failures return FMM_EHIP; fmm_last_error() gives detail.
@@ -208,7 +222,9 @@ fmm_status fmm_m2l_p2m_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t n
  * not read). out is dense in descriptor order, float64
  * [nsub][4][512][ppc]: phi, then the x, y and z components of grad, each
  * [512 target cells][ppc], fully written. Two different particles of the
- * near cells at one position make that target's result inf or NaN.
+ * near cells closer than about 1e-19 (in the units of pos), coincident ones
+ * included, make that target's result inf or NaN: 1/r starts from a float32
+ * estimate taken from r^2 rounded to float32, which underflows there.
  * nsub <= 2^21 per call. */
 fmm_status fmm_evaluate(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
                         const double* pos, const double* mass, int32_t ppc,

@@ -33,11 +33,12 @@ class FMMGravity(torch.autograd.Function):
         gL = gL.contiguous()
         dM = torch.empty(actx.m_elems, dtype=torch.float64, device=gL.device)
         dmass = torch.empty(actx.mass_shape, dtype=torch.float64, device=gL.device)
+        prev = actx.handle.get_option(fmm.FMM_OPT_ADJOINT_FORM)
         actx.handle.set_option(fmm.FMM_OPT_ADJOINT_FORM, 1 if actx.harmonic else 0)
         try:
             actx.handle.m2l_p2m_backward(actx.desc, pos, actx.ppc, gL, dM, dmass)
         finally:
-            actx.handle.set_option(fmm.FMM_OPT_ADJOINT_FORM, 0)
+            actx.handle.set_option(fmm.FMM_OPT_ADJOINT_FORM, prev)
         return dmass, None, None, None, None, None, None, None
 
 

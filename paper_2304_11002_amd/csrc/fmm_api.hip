@@ -83,6 +83,7 @@ uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) 
 struct DescEntry {
   std::vector<fmm_subgrid> host;
   uint64_t hash = 0;
+  uint64_t id = 0;                // unique per upload (keys this set's graphs)
   uint64_t last_use = 0;
   void* dev = nullptr;            // one device allocation: descriptors, id lists, work list
   void* pinned = nullptr;         // pinned host copy of the same bytes
@@ -90,10 +91,12 @@ struct DescEntry {
   DevDesc* d_desc = nullptr;
   int* d_ids[kMaxP + 1] = {};     // reference kernels: sub-grids per order
   int count[kMaxP + 1] = {};
-  WorkList work;                  // matrix-core kernels
+  WorkList work;                  // matrix-core kernels, dense-form costs (C^2 per pair)
+  WorkList work_h;                // the same items ordered by harmonic-form costs ((p+1)^4)
   // FMM_OPT_ROUND_SPLIT, per form (dense, harmonic): (sub-grid, round) list, the
   // first slot of each sub-grid, and the rounds' sums; one allocation each
   void* split_dev[2] = {};
+  void* split_pinned[2] = {};     // host staging of the (sub-grid, round) list
   WorkList split[2];
   int* split_base[2] = {};
   double* split_part[2] = {};
@@ -106,6 +109,8 @@ struct DescEntry {
 struct GraphEntry {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;      // recorded after every launch of this graph
+  uint64_t owner = 0;             // DescEntry::id of the descriptor set it was captured for
   uint64_t last_use = 0;
 };
 
@@ -122,6 +127,7 @@ struct fmm_ctx {
   std::vector<std::unique_ptr<DescEntry>> descs;
   std::unordered_map<uint64_t, GraphEntry> graphs;
   uint64_t clock = 0;
+  uint64_t next_id = 0;
   int m2l_kernel = 0;                         // 0 auto, 1 reference, 2 matrix core
   int use_graph = 1;
   int tile_config = -1;
@@ -226,11 +232,22 @@ void free_entry(DescEntry* e) {
   if (e->last_launch) (void)hipEventSynchronize(e->last_launch);
   if (e->ready) (void)hipEventSynchronize(e->ready);
   if (e->dev) (void)hipFree(e->dev);
-  for (int f = 0; f < 2; ++f)
+  for (int f = 0; f < 2; ++f) {
     if (e->split_dev[f]) (void)hipFree(e->split_dev[f]);
+    if (e->split_pinned[f]) (void)hipHostFree(e->split_pinned[f]);
+  }
   if (e->pinned) (void)hipHostFree(e->pinned);
   if (e->ready) (void)hipEventDestroy(e->ready);
   if (e->last_launch) (void)hipEventDestroy(e->last_launch);
+}
+
+// Wait for the graph's last launch (on whatever stream it ran), then release it.
+void destroy_graph(GraphEntry& g) {
+  if (g.done) (void)hipEventSynchronize(g.done);
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  if (g.done) (void)hipEventDestroy(g.done);
+  g = GraphEntry{};
 }
 
 constexpr size_t kMaxDescEntries = 8;
@@ -258,18 +275,24 @@ fmm_status get_desc(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, hipStre
   if (ctx->descs.size() >= kMaxDescEntries) {
     auto it = std::min_element(ctx->descs.begin(), ctx->descs.end(),
                                [](const auto& a, const auto& b) { return a->last_use < b->last_use; });
-    // graphs refer to this entry's work list: drop them all (re-captured on demand)
-    for (auto& g : ctx->graphs) {
-      if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
-      if (g.second.graph) (void)hipGraphDestroy(g.second.graph);
+    // the graphs captured for this set refer to its work list: drop those (each
+    // waits for its own last launch); the other sets' graphs stay
+    const uint64_t owner = (*it)->id;
+    for (auto g = ctx->graphs.begin(); g != ctx->graphs.end();) {
+      if (g->second.owner == owner) {
+        destroy_graph(g->second);
+        g = ctx->graphs.erase(g);
+      } else {
+        ++g;
+      }
     }
-    ctx->graphs.clear();
     free_entry(it->get());
     ctx->descs.erase(it);
   }
   auto e = std::make_unique<DescEntry>();
   e->host.assign(desc, desc + nsub);
   e->hash = h;
+  e->id = ++ctx->next_id;
   e->last_use = ++ctx->clock;
   // layout: descriptors | ids per order | work list
   std::vector<int> ids[kMaxP + 1];
@@ -277,7 +300,8 @@ fmm_status get_desc(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, hipStre
     ids[desc[b].p].push_back((int)b);
     if (desc[b].part_off & 1) e->part_even = false;
   }
-  std::vector<WorkItem> items = build_work_list(desc, nsub);
+  std::vector<WorkItem> items = build_work_list(desc, nsub, false);
+  std::vector<WorkItem> items_h = build_work_list(desc, nsub, true);
   size_t off_desc = 0;
   size_t off = align_up(nbytes, 256);
   size_t off_ids[kMaxP + 1] = {};
@@ -287,7 +311,11 @@ fmm_status get_desc(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, hipStre
   }
   size_t off_work = off;
   off = align_up(off + sizeof(WorkItem) * items.size(), 256);
+  size_t off_work_h = off;
+  off = align_up(off + sizeof(WorkItem) * items_h.size(), 256);
   size_t off_counter = off;
+  off = align_up(off + 256, 256);
+  size_t off_counter_h = off;
   off = align_up(off + 256, 256);
   e->bytes = off;
   HIP_TRY(ctx, hipMalloc(&e->dev, e->bytes));
@@ -297,6 +325,7 @@ fmm_status get_desc(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, hipStre
   std::memcpy(hp + off_desc, desc, nbytes);
   for (int p = 2; p <= kMaxP; ++p) std::memcpy(hp + off_ids[p], ids[p].data(), sizeof(int) * ids[p].size());
   std::memcpy(hp + off_work, items.data(), sizeof(WorkItem) * items.size());
+  std::memcpy(hp + off_work_h, items_h.data(), sizeof(WorkItem) * items_h.size());
   char* dp = static_cast<char*>(e->dev);
   e->d_desc = reinterpret_cast<DevDesc*>(dp + off_desc);
   for (int p = 2; p <= kMaxP; ++p) {
@@ -308,6 +337,11 @@ fmm_status get_desc(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, hipStre
   e->work.counter = reinterpret_cast<unsigned*>(dp + off_counter);
   e->work.cost = 0;
   for (const auto& it : items) e->work.cost += it.cost;
+  e->work_h.items = reinterpret_cast<const WorkItem*>(dp + off_work_h);
+  e->work_h.count = (int)items_h.size();
+  e->work_h.counter = reinterpret_cast<unsigned*>(dp + off_counter_h);
+  e->work_h.cost = 0;
+  for (const auto& it : items_h) e->work_h.cost += it.cost;
   HIP_TRY(ctx, hipEventCreateWithFlags(&e->ready, hipEventDisableTiming));
   HIP_TRY(ctx, hipEventCreateWithFlags(&e->last_launch, hipEventDisableTiming));
   HIP_TRY(ctx, hipMemcpyAsync(e->dev, e->pinned, e->bytes, hipMemcpyHostToDevice, stream));
@@ -317,6 +351,9 @@ fmm_status get_desc(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, hipStre
   ctx->descs.push_back(std::move(e));
   return FMM_OK;
 }
+
+// the work list ordered by the costs of the form that runs
+const WorkList& work_for(const DescEntry* e, bool harmonic) { return harmonic ? e->work_h : e->work; }
 
 fmm_status mark_used(fmm_ctx* ctx, DescEntry* e, hipStream_t stream) {
   HIP_TRY(ctx, hipEventRecord(e->last_launch, stream));
@@ -407,10 +444,7 @@ fmm_status fmm_destroy(fmm_ctx* ctx) {
   if (!ctx->host_only) {
     DeviceGuard guard(ctx->device);
     (void)hipDeviceSynchronize();
-    for (auto& g : ctx->graphs) {
-      if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
-      if (g.second.graph) (void)hipGraphDestroy(g.second.graph);
-    }
+    for (auto& g : ctx->graphs) destroy_graph(g.second);
     for (auto& e : ctx->descs) free_entry(e.get());
     mfma_tables_destroy(&ctx->mfma);
     tree_tables_destroy(&ctx->tree);
@@ -677,11 +711,12 @@ static fmm_status run_mfma(fmm_ctx* ctx, DescEntry* e, const double* M, double* 
                            fmm_precision prec, int cfg, hipStream_t s,
                            const double* pos = nullptr, const double* mass = nullptr,
                            double* Mw = nullptr) {
+  const WorkList& wl = work_for(e, prec == FMM_FP64_HARMONIC);
   if (!ctx->use_graph) {
-    HIP_TRY(ctx, launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, s, pos, mass, Mw));
+    HIP_TRY(ctx, launch_m2l_mfma(ctx->mfma, wl, e->d_desc, M, L, prec, cfg, s, pos, mass, Mw));
     return FMM_OK;
   }
-  uint64_t key = fnv1a(&e->hash, sizeof e->hash);
+  uint64_t key = fnv1a(&e->id, sizeof e->id);
   key = fnv1a(&M, sizeof M, key);
   key = fnv1a(&L, sizeof L, key);
   key = fnv1a(&prec, sizeof prec, key);
@@ -691,24 +726,34 @@ static fmm_status run_mfma(fmm_ctx* ctx, DescEntry* e, const double* M, double* 
   auto it = ctx->graphs.find(key);
   if (it == ctx->graphs.end()) {
     if (ctx->graphs.size() >= kMaxGraphs) {
+      // the least recently used graph; its own last launch (on any stream) is
+      // waited for before it is released
       auto victim = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
                                      [](const auto& a, const auto& b) { return a.second.last_use < b.second.last_use; });
-      HIP_TRY(ctx, hipStreamSynchronize(s));
-      (void)hipGraphExecDestroy(victim->second.exec);
-      (void)hipGraphDestroy(victim->second.graph);
+      destroy_graph(victim->second);
       ctx->graphs.erase(victim);
     }
     GraphEntry g;
+    g.owner = e->id;
     HIP_TRY(ctx, hipStreamBeginCapture(ctx->internal, hipStreamCaptureModeThreadLocal));
-    hipError_t le = launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, ctx->internal, pos, mass, Mw);
+    hipError_t le = launch_m2l_mfma(ctx->mfma, wl, e->d_desc, M, L, prec, cfg, ctx->internal, pos, mass, Mw);
     hipError_t ce = hipStreamEndCapture(ctx->internal, &g.graph);
-    if (le != hipSuccess) return hip_err(ctx, le, "launch_m2l_mfma (capture)");
-    if (ce != hipSuccess) return hip_err(ctx, ce, "hipStreamEndCapture");
-    HIP_TRY(ctx, hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+      return le != hipSuccess ? hip_err(ctx, le, "launch_m2l_mfma (capture)")
+                              : hip_err(ctx, ce, "hipStreamEndCapture");
+    }
+    hipError_t ie = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    if (ie == hipSuccess) ie = hipEventCreateWithFlags(&g.done, hipEventDisableTiming);
+    if (ie != hipSuccess) {
+      destroy_graph(g);
+      return hip_err(ctx, ie, "hipGraphInstantiate");
+    }
     it = ctx->graphs.emplace(key, g).first;
   }
   it->second.last_use = ++ctx->clock;
   HIP_TRY(ctx, hipGraphLaunch(it->second.exec, s));
+  HIP_TRY(ctx, hipEventRecord(it->second.done, s));
   return FMM_OK;
 }
 
@@ -729,16 +774,28 @@ static fmm_status run_split(fmm_ctx* ctx, DescEntry* e, const double* M, double*
     const size_t off_counter = align_up(off_base + sizeof(int) * base.size(), 256);
     const size_t off_part = align_up(off_counter + 256, 256);
     const size_t bytes = off_part + sizeof(double) * items.size() * 35 * kNTarget;
+    // the list goes through pinned host memory, copied on the caller's stream
+    // (both allocations are held with the descriptor set)
     void* dev = nullptr;
+    void* pin = nullptr;
     HIP_TRY(ctx, hipMalloc(&dev, bytes));
+    hipError_t ae = hipHostMalloc(&pin, off_counter, hipHostMallocDefault);
+    if (ae != hipSuccess) {
+      (void)hipFree(dev);
+      return hip_err(ctx, ae, "hipHostMalloc (round split list)");
+    }
+    char* hp = static_cast<char*>(pin);
+    std::memcpy(hp, items.data(), sizeof(WorkItem) * items.size());
+    std::memcpy(hp + off_base, base.data(), sizeof(int) * base.size());
     char* dp = static_cast<char*>(dev);
-    hipError_t ce = hipMemcpy(dp, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice);
-    if (ce == hipSuccess) ce = hipMemcpy(dp + off_base, base.data(), sizeof(int) * base.size(), hipMemcpyHostToDevice);
+    hipError_t ce = hipMemcpyAsync(dp, hp, off_counter, hipMemcpyHostToDevice, s);
     if (ce != hipSuccess) {
       (void)hipFree(dev);
-      return hip_err(ctx, ce, "hipMemcpy (round split list)");
+      (void)hipHostFree(pin);
+      return hip_err(ctx, ce, "hipMemcpyAsync (round split list)");
     }
     e->split_dev[f] = dev;
+    e->split_pinned[f] = pin;
     e->split[f].items = reinterpret_cast<const WorkItem*>(dp);
     e->split[f].count = (int)items.size();
     e->split[f].counter = reinterpret_cast<unsigned*>(dp + off_counter);
@@ -845,7 +902,8 @@ fmm_status fmm_m2l_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
   if (ctx->m2l_kernel == 1) {
     CHECK_OK(run_ref(ctx, e, true, dL, dM, s));
   } else {
-    HIP_TRY(ctx, launch_m2l_mfma_backward(ctx->mfma, e->work, e->d_desc, dL, dM, ctx->adjoint_form == 1, s));
+    HIP_TRY(ctx, launch_m2l_mfma_backward(ctx->mfma, work_for(e, ctx->adjoint_form == 1), e->d_desc, dL, dM,
+                                          ctx->adjoint_form == 1, s));
   }
   return mark_used(ctx, e, s);
 }
@@ -870,11 +928,12 @@ fmm_status fmm_m2l_p2m_backward(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t n
   CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
   const bool aligned = ((reinterpret_cast<uintptr_t>(pos) | reinterpret_cast<uintptr_t>(dmass)) & 15u) == 0;
   if (ctx->m2l_kernel != 1 && ppc == 8 && e->part_even && aligned && nsub > ctx->mfma.num_cu) {
-    HIP_TRY(ctx, launch_m2l_mfma_backward(ctx->mfma, e->work, e->d_desc, dL, dM, ctx->adjoint_form == 1, s,
-                                          pos, dmass));
+    HIP_TRY(ctx, launch_m2l_mfma_backward(ctx->mfma, work_for(e, ctx->adjoint_form == 1), e->d_desc, dL, dM,
+                                          ctx->adjoint_form == 1, s, pos, dmass));
   } else {
     if (ctx->m2l_kernel == 1) CHECK_OK(run_ref(ctx, e, true, dL, dM, s));
-    else HIP_TRY(ctx, launch_m2l_mfma_backward(ctx->mfma, e->work, e->d_desc, dL, dM, ctx->adjoint_form == 1, s));
+    else HIP_TRY(ctx, launch_m2l_mfma_backward(ctx->mfma, work_for(e, ctx->adjoint_form == 1), e->d_desc, dL, dM,
+                                               ctx->adjoint_form == 1, s));
     HIP_TRY(ctx, launch_p2m_backward(e->d_desc, nsub, e->d_ids, e->count, pos, ppc, dM, dmass, e->part_even, s));
   }
   return mark_used(ctx, e, s);
@@ -919,11 +978,11 @@ fmm_status fmm_autotune(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, con
   for (int cfg = 0; cfg < mfma_num_configs(); ++cfg) {
     if (!mfma_config_supports(cfg, prec)) continue;
     // one warm-up launch, then the best of three
-    HIP_TRY(ctx, launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, s));
+    HIP_TRY(ctx, launch_m2l_mfma(ctx->mfma, work_for(e, prec == FMM_FP64_HARMONIC), e->d_desc, M, L, prec, cfg, s));
     float cfg_ms = 1e30f;
     for (int r = 0; r < 3; ++r) {
       HIP_TRY(ctx, hipEventRecord(t0, s));
-      HIP_TRY(ctx, launch_m2l_mfma(ctx->mfma, e->work, e->d_desc, M, L, prec, cfg, s));
+      HIP_TRY(ctx, launch_m2l_mfma(ctx->mfma, work_for(e, prec == FMM_FP64_HARMONIC), e->d_desc, M, L, prec, cfg, s));
       HIP_TRY(ctx, hipEventRecord(t1, s));
       HIP_TRY(ctx, hipEventSynchronize(t1));
       float ms = 0.f;

@@ -228,6 +228,7 @@ class Context:
             raise FMMError(st, self.lib.fmm_last_error(None).decode())
         self.handle = h
         self.device = device
+        self._options = {}
 
     def close(self):
         if self.handle:
@@ -275,8 +276,17 @@ class Context:
             raise ValueError("%s holds %d elements, the descriptors address %d" % (name, t.numel(), need))
         return t.data_ptr()
 
+    # the library's defaults (fmm.h), for get_option before any set_option
+    _OPTION_DEFAULTS = {FMM_OPT_M2L_KERNEL: 0, FMM_OPT_USE_GRAPH: 1, FMM_OPT_TILE_CONFIG: -1,
+                        FMM_OPT_ADJOINT_FORM: 0, FMM_OPT_P2M_WINDOW: 0, FMM_OPT_ROUND_SPLIT: 0}
+
     def set_option(self, option, value):
         self._run(self.lib.fmm_set_option(self.handle, option, int(value)))
+        self._options[option] = int(value)
+
+    def get_option(self, option):
+        """The value last set through this wrapper (the library keeps no getter)."""
+        return self._options.get(option, self._OPTION_DEFAULTS.get(option))
 
     def p2m(self, desc, pos, mass, ppc, M, stream=None):
         pd, n = _desc_ptr(desc)
