@@ -300,6 +300,124 @@ def read_traffic(launch_pairs):
         return None
 
 
+def bench_fwd_bwd(torch, fmm, ctx, K, W):
+    """Forward (P2M + M2L, one launch) and backward (M2L adjoint + P2M adjoint, one
+    launch) on the 2048-sub-grid gradient batch, harmonic forms, loss = sum w . L."""
+    w5 = synth.config(5)
+    d5, m5, l5 = fmm.make_descriptors(w5.p, w5.log2_inv_h, w5.mask)
+    pairs5 = fmm.pair_count(d5)
+    pos5, mass5 = upload_batch(torch, w5)
+    wt = torch.from_numpy(synth.loss_weights(w5.seed, w5.nsub)).to("cuda").reshape(-1)
+    M5 = torch.empty(m5, dtype=torch.float64, device="cuda")
+    L5 = torch.empty(l5, dtype=torch.float64, device="cuda")
+    dM5 = torch.empty_like(M5)
+    dm5 = torch.empty_like(mass5)
+
+    def step_fb(ev, i):
+        if ev: ev[0].record()
+        ctx.p2m_m2l(d5, pos5, mass5, 8, M5, L5, fmm.FMM_FP64_HARMONIC)
+        if ev: ev[1].record()
+        ctx.m2l_p2m_backward(d5, pos5, 8, wt, dM5, dm5)   # dLoss/dL = w for loss = sum w . L
+        if ev: ev[2].record()
+
+    prev = ctx.get_option(fmm.FMM_OPT_ADJOINT_FORM)
+    ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 1)      # harmonic adjoint with the harmonic forward
+    try:
+        wall_fb, seg_fb = timed(torch, step_fb, max(3, K // 2), W, marks=2)
+        fwd_ms, bwd_ms = seg_fb[:, 0].mean(), seg_fb[:, 1].mean()
+        ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 0)
+        _, seg_fbd = timed(torch, step_fb, max(3, K // 2), 1, marks=2)
+        bwd_dense_ms = seg_fbd[:, 1].mean()
+    finally:
+        ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, prev)
+    assert bool(torch.isfinite(dm5).all())
+    fl_h = pairs5 * harmonic_flops_per_pair(3)       # executed matrix flops, each direction
+    fl_d = pairs5 * flops_per_pair(3)
+    out = {"workload": "grad_2048_p3", "subgrids": w5.nsub, "pairs": pairs5,
+           "forward": "P2M + M2L (harmonic form), one launch (fmm_p2m_m2l)",
+           "backward": "M2L adjoint (harmonic form) + P2M adjoint, one launch (fmm_m2l_p2m_backward)",
+           "bwd_ms_dense_adjoint": float(bwd_dense_ms),
+           "fwd_ms": float(fwd_ms), "bwd_ms": float(bwd_ms),
+           "fwd_bwd_ms_per_batch": float(fwd_ms + bwd_ms),
+           "bwd_over_fwd": float(bwd_ms / fwd_ms),
+           "roofline": {"bound": "mfma", "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "flops_per_launch": fl_h, "flops_per_pair": harmonic_flops_per_pair(3),
+                        "fwd_achieved": fl_h / (fwd_ms * 1e-3) / 1e12,
+                        "fwd_frac": fl_h / (fwd_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                        "bwd_achieved": fl_h / (bwd_ms * 1e-3) / 1e12,
+                        "bwd_frac": fl_h / (bwd_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                        "bwd_dense_adjoint_frac": fl_d / (bwd_dense_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                        "note": "executed matrix flops of the M2L (or its adjoint) over the whole launch, "
+                                "which also holds the HBM-bound moment (or mass-gradient) phase"}}
+    log("fwd+bwd 2048: fwd %.3f ms (%.1f%%), bwd %.3f ms (%.1f%%)"
+        % (fwd_ms, 100 * out["roofline"]["fwd_frac"], bwd_ms, 100 * out["roofline"]["bwd_frac"]))
+    del pos5, mass5, wt, M5, L5, dM5, dm5
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_uneven(torch, fmm, ctx, K, W):
+    """The 6000-sub-grid uneven batch (mixed p, masks, spacings) in one persistent
+    launch, harmonic and dense forms, each with its autotuned configuration."""
+    w3 = synth.config(3)
+    d3, m3, l3 = fmm.make_descriptors(w3.p, w3.log2_inv_h, w3.mask)
+    pairs3 = fmm.pair_count(d3)
+    per = np.array([fmm.pair_count(d3[i:i + 1]) for i in range(w3.nsub)], dtype=np.float64)
+    fl3 = float(sum(per[i] * flops_per_pair(int(w3.p[i])) for i in range(w3.nsub)))
+    fl3h = float(sum(per[i] * harmonic_flops_per_pair(int(w3.p[i])) for i in range(w3.nsub)))
+    pos3, mass3 = upload_batch(torch, w3)
+    M3 = torch.empty(m3, dtype=torch.float64, device="cuda")
+    L3 = torch.empty(l3, dtype=torch.float64, device="cuda")
+    ctx.p2m(d3, pos3, mass3, 8, M3)
+    del pos3, mass3
+    torch.cuda.empty_cache()
+    chosen = ctx.autotune(d3, M3, L3, fmm.FMM_FP64)
+
+    def step_ud(ev, i):
+        if ev: ev[0].record()
+        ctx.m2l(d3, M3, L3)
+        if ev: ev[1].record()
+
+    _, seg_ud = timed(torch, step_ud, K, W, marks=1)
+    ms_ud = seg_ud[:, 0].mean()
+    L3d = L3.clone()
+    chosen_h = ctx.autotune(d3, M3, L3, fmm.FMM_FP64_HARMONIC)
+
+    def step_u(ev, i):
+        if ev: ev[0].record()
+        ctx.m2l(d3, M3, L3, fmm.FMM_FP64_HARMONIC)
+        if ev: ev[1].record()
+
+    wall_u, seg_u = timed(torch, step_u, K, W, marks=1)
+    ms_u = seg_u[:, 0].mean()
+    dev3 = rel_to_component_max(L3, L3d, d3, fmm)
+    assert dev3["max"] <= 1e-12, dev3
+    # per order: executed flops and the sub-grid count, for the tail estimate
+    by_p = {}
+    for p in (2, 3, 4):
+        sel = w3.p == p
+        by_p[str(p)] = {"subgrids": int(sel.sum()), "pairs": float(per[sel].sum()),
+                        "harmonic_flops": float(per[sel].sum() * harmonic_flops_per_pair(p))}
+    out = {"workload": "uneven_6000_mixed_p", "subgrids": w3.nsub, "pairs": pairs3,
+           "form": "harmonic", "m2l_ms": float(ms_u), "pairs_per_s": pairs3 / (ms_u * 1e-3),
+           "autotune_choice": chosen_h,
+           "roofline": {"bound": "mfma", "achieved": fl3h / (ms_u * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": fl3h / (ms_u * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                        "flops_per_launch": fl3h,
+                        "note": "executed-useful matrix flops: 2 (p+1)^4 per present pair"},
+           "dense_equivalent_tflops": fl3 / (ms_u * 1e-3) / 1e12,
+           "by_order": by_p,
+           "dense_m2l_ms": float(ms_ud), "dense_tflops": fl3 / (ms_ud * 1e-3) / 1e12,
+           "dense_frac": fl3 / (ms_ud * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+           "dense_autotune_choice": chosen, "harmonic_vs_dense": dev3,
+           "parity": "tests/test_gpu_fullsize.py::test_uneven_6000"}
+    log("uneven 6000: harmonic %.3f ms (%.4g pairs/s, %.1f%% executed), dense %.3f ms"
+        % (ms_u, pairs3 / (ms_u * 1e-3), 100 * out["roofline"]["frac"], ms_ud))
+    del M3, L3, L3d
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +430,10 @@ def main():
                     help="only the multi-level solve on 128^3 (for profiling)")
     ap.add_argument("--evaluate-only", action="store_true",
                     help="only the step and the evaluation at the particles (for profiling)")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="only the 6000-sub-grid uneven batch (for profiling)")
+    ap.add_argument("--fwd-bwd-only", action="store_true",
+                    help="only the 2048-sub-grid gradient batch (for profiling)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of this many GiB three times (counter calibration)")
     args = ap.parse_args()
@@ -341,6 +463,14 @@ def main():
     K, W = args.steps, args.warmup
     if args.tree_only:
         print(json.dumps({"tree": bench_tree(torch, fmm, ctx, K, W)}), flush=True)
+        ctx.close()
+        return
+    if args.uneven_only:
+        print(json.dumps({"uneven": bench_uneven(torch, fmm, ctx, K, W)}), flush=True)
+        ctx.close()
+        return
+    if args.fwd_bwd_only:
+        print(json.dumps({"fwd_bwd": bench_fwd_bwd(torch, fmm, ctx, K, W)}), flush=True)
         ctx.close()
         return
     out = {"metric": METRIC, "unit": "pairs/s", "n_gpus": 1, "steps": K, "warmup": W,
@@ -504,81 +634,8 @@ def main():
         torch.cuda.empty_cache()
 
     if not args.no_extras and not args.evaluate_only:
-        # ---------------- forward + backward on 2048 sub-grids
-        w5 = synth.config(5)
-        d5, m5, l5 = fmm.make_descriptors(w5.p, w5.log2_inv_h, w5.mask)
-        pairs5 = fmm.pair_count(d5)
-        pos5, mass5 = upload_batch(torch, w5)
-        wt = torch.from_numpy(synth.loss_weights(w5.seed, w5.nsub)).to("cuda").reshape(-1)
-        M5 = torch.empty(m5, dtype=torch.float64, device="cuda")
-        L5 = torch.empty(l5, dtype=torch.float64, device="cuda")
-        dM5 = torch.empty_like(M5)
-        dm5 = torch.empty_like(mass5)
-
-        def step_fb(ev, i):
-            if ev: ev[0].record()
-            ctx.p2m_m2l(d5, pos5, mass5, 8, M5, L5, fmm.FMM_FP64_HARMONIC)
-            if ev: ev[1].record()
-            ctx.m2l_p2m_backward(d5, pos5, 8, wt, dM5, dm5)   # dLoss/dL = w for loss = sum w . L
-            if ev: ev[2].record()
-
-        ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 1)      # harmonic adjoint with the harmonic forward
-        wall_fb, seg_fb = timed(torch, step_fb, max(3, K // 2), W, marks=2)
-        fwd_ms, bwd_ms = seg_fb[:, 0].mean(), seg_fb[:, 1].mean()
-        ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 0)
-        _, seg_fbd = timed(torch, step_fb, max(3, K // 2), 1, marks=2)
-        bwd_dense_ms = seg_fbd[:, 1].mean()
-        out["fwd_bwd"] = {"workload": "grad_2048_p3", "subgrids": w5.nsub, "pairs": pairs5,
-                          "forward": "P2M + M2L (harmonic form), one launch (fmm_p2m_m2l)",
-                          "backward": "M2L adjoint (harmonic form) + P2M adjoint, one launch (fmm_m2l_p2m_backward)",
-                          "bwd_ms_dense_adjoint": float(bwd_dense_ms),
-                          "fwd_ms": float(fwd_ms), "bwd_ms": float(bwd_ms),
-                          "fwd_bwd_ms_per_batch": float(fwd_ms + bwd_ms),
-                          "bwd_over_fwd": float(bwd_ms / fwd_ms)}
-        log("fwd+bwd 2048: fwd %.3f ms, bwd %.3f ms" % (fwd_ms, bwd_ms))
-        del pos5, mass5, wt, M5, L5, dM5, dm5
-        torch.cuda.empty_cache()
-
-        # ---------------- uneven batch in one persistent launch
-        w3 = synth.config(3)
-        d3, m3, l3 = fmm.make_descriptors(w3.p, w3.log2_inv_h, w3.mask)
-        pairs3 = fmm.pair_count(d3)
-        fl3 = float(sum(fmm.pair_count(d3[i:i + 1]) * flops_per_pair(int(w3.p[i])) for i in range(w3.nsub)))
-        pos3, mass3 = upload_batch(torch, w3)
-        M3 = torch.empty(m3, dtype=torch.float64, device="cuda")
-        L3 = torch.empty(l3, dtype=torch.float64, device="cuda")
-        ctx.p2m(d3, pos3, mass3, 8, M3)
-        chosen = ctx.autotune(d3, M3, L3, fmm.FMM_FP64)
-
-        def step_ud(ev, i):
-            if ev: ev[0].record()
-            ctx.m2l(d3, M3, L3)
-            if ev: ev[1].record()
-
-        _, seg_ud = timed(torch, step_ud, K, W, marks=1)
-        ms_ud = seg_ud[:, 0].mean()
-
-        def step_u(ev, i):
-            if ev: ev[0].record()
-            ctx.m2l(d3, M3, L3, fmm.FMM_FP64_HARMONIC)
-            if ev: ev[1].record()
-
-        wall_u, seg_u = timed(torch, step_u, K, W, marks=1)
-        ms_u = seg_u[:, 0].mean()
-
-        L3d = torch.empty_like(L3)
-        ctx.m2l(d3, M3, L3d)
-        dev3 = rel_to_component_max(L3, L3d, d3, fmm)
-        assert dev3["max"] <= 1e-12, dev3
-        out["uneven"] = {"workload": "uneven_6000_mixed_p", "subgrids": w3.nsub, "pairs": pairs3,
-                         "form": "harmonic", "m2l_ms": float(ms_u), "pairs_per_s": pairs3 / (ms_u * 1e-3),
-                         "dense_equivalent_tflops": fl3 / (ms_u * 1e-3) / 1e12,
-                         "dense_m2l_ms": float(ms_ud), "dense_tflops": fl3 / (ms_ud * 1e-3) / 1e12,
-                         "dense_autotune_choice": chosen, "harmonic_vs_dense": dev3,
-                         "parity": "tests/test_gpu_fullsize.py::test_uneven_6000"}
-        log("uneven 6000: harmonic %.3f ms (%.4g pairs/s), dense %.3f ms" % (ms_u, pairs3 / (ms_u * 1e-3), ms_ud))
-        del pos3, mass3, M3, L3
-        torch.cuda.empty_cache()
+        out["fwd_bwd"] = bench_fwd_bwd(torch, fmm, ctx, K, W)
+        out["uneven"] = bench_uneven(torch, fmm, ctx, K, W)
 
         # ---------------- the multi-level iteration on a 128^3 domain
         out["tree"] = bench_tree(torch, fmm, ctx, K, W)

@@ -352,3 +352,39 @@ def test_binding_rejects_host_and_short_buffers(ctx, torch):
     ctx.m2l(desc, M, L)
     torch.cuda.synchronize()
     assert torch.count_nonzero(L) == 0      # zero moments give zero expansions
+
+
+def test_cache_eviction_over_two_streams(ctx, torch):
+    # 12 descriptor sets (more than the 8 a context holds) and 24 distinct graphs
+    # (more than the 16 it keeps), enqueued alternately on two streams without
+    # host synchronisation: evicting a set drops only its own graphs, a released
+    # graph has finished its last launch, and every result equals, bit for bit,
+    # that of plain launches made one at a time on a fresh context
+    rng = np.random.default_rng(77)
+    sets = []
+    for i in range(12):
+        p = rng.integers(2, 5, size=3)
+        masks = [synth.random_mask(rng) for _ in range(3)]
+        desc, m_el, l_el = fmm.make_descriptors(p, rng.integers(0, 3, size=3), masks)
+        M = torch.from_numpy(rng.standard_normal(m_el)).to("cuda")
+        sets.append((desc, M, l_el))
+    prec = fmm.FMM_FP64_HARMONIC
+    with fmm.Context(0) as ref:
+        ref.set_option(fmm.FMM_OPT_USE_GRAPH, 0)
+        want = []
+        for desc, M, l_el in sets:
+            L = torch.full((l_el,), float("nan"), dtype=torch.float64, device="cuda")
+            ref.m2l(desc, M, L, prec)
+            torch.cuda.synchronize()
+            want.append(L)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [[torch.full((l_el,), float("nan"), dtype=torch.float64, device="cuda") for _, _, l_el in sets]
+            for _ in range(2)]
+    torch.cuda.synchronize()
+    for r in range(2):
+        for i, (desc, M, _) in enumerate(sets):
+            ctx.m2l(desc, M, outs[r][i], prec, streams[(i + r) % 2])
+    torch.cuda.synchronize()
+    for r in range(2):
+        for i in range(len(sets)):
+            assert torch.equal(outs[r][i], want[i]), "pass %d, set %d" % (r, i)
