@@ -21,6 +21,9 @@ the near field plus L2P at the finest level).
 
 Every floating-point step is plain NumPy float64 (float32 only in the
 split-precision emulation, which is an expectation model, not a reference).
+The exact-slice model (``m2l_exact_slice``) adds integer slice products,
+summed exactly in int64; it, too, is an expectation model of a reduced
+precision, pinned against the float64 M2L it approximates.
 """
 
 from .fmm import (  # noqa: F401
@@ -56,4 +59,11 @@ from .fmm import (  # noqa: F401
     direct_sum,
     m2l_split32_emulated,
     pair_count,
+    SLICE_BITS,
+    slice_prescale,
+    pow2_exponent,
+    slice_int8,
+    slice_pairs,
+    slice_tables,
+    m2l_exact_slice,
 )

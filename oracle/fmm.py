@@ -526,3 +526,131 @@ def m2l_split32_emulated(M, p, h, mask=FULL_MASK, offsets=None, block=64):
         L += acc.astype(np.float64)
     L *= (h ** (-1.0 - order))[:, None]
     return L.reshape(C, BLOCK, BLOCK, BLOCK)
+
+
+# ---------------------------------------------------------------------------
+# exact-slice (Ozaki-style) low-precision M2L: expectation model
+# ---------------------------------------------------------------------------
+#
+# The error-free splitting of Ozaki, Ogita, Oishi and Rump (2012), with int8
+# slices and exact integer accumulation as Ootomo, Ozaki and Yokota apply it
+# to matrix products on integer units: each float64 operand is scaled by a
+# power of two into (-1, 1) and cut into s signed 7-bit integer slices,
+#   X = sum_{i < s} x_i 2^(-7 (i + 1)) + r,  |x_i| <= 127,  |r| < 2^(-7 s);
+# slice products x_i y_j are summed exactly in integers, and only the pairs
+# with i + j <= s are kept (the rest weigh less than the truncation r).
+#
+# Applied to the harmonic form of M2L (the contraction over (d, k') of the
+# folded moments with the tables restricted to K'_p x K'_p):
+#   * the reduction runs over offsets and folded components together, so one
+#     power of two must scale a whole operand row or column: the moments of a
+#     sub-grid share one exponent e_A (after a fixed per-component prescale
+#     2^f_k' that evens out the components' ranges), and each table column n'
+#     has its own exponent e_B(n') over (d, k');
+#   * the prescale is compensated in the tables (2^-f_k' on row k'), so the
+#     products are unchanged;
+#   * f_k' comes from the geometric bound of a folded moment per unit of cell
+#     mass: with |a_i| <= h/2 per axis and the h^-|k| scaling, |M_k h^-|k|| <=
+#     m 2^-|k| / k!, so |Mh_k'| <= m b_k' with b_k' = sum_k |F[k, k']| 2^-|k| / k!
+#     and f_k' = -floor(log2 b_k').
+
+SLICE_BITS = 7
+
+
+def slice_prescale(p):
+    """f_k' for the folded components K'_p (see above); integers, 0 for order 0."""
+    ks = multi_indices(p)
+    F = harmonic_fold(p)
+    out = []
+    for c in range(F.shape[1]):
+        b = sum(abs(F[r, c]) * 0.5 ** sum(k) / (factorial(k[0]) * factorial(k[1]) * factorial(k[2]))
+                for r, k in enumerate(ks) if F[r, c] != 0)
+        out.append(-int(np.floor(np.log2(b))))
+    return np.array(out, dtype=np.int64)
+
+
+def pow2_exponent(x):
+    """e with x / 2^e in [1/2, 1) for x > 0 (frexp's exponent); 0 for x = 0."""
+    return int(np.frexp(float(x))[1]) if x > 0 else 0
+
+
+def slice_int8(X, s):
+    """s integer slices of X (every |X| < 1): X = sum_i S_i 2^(-7 (i+1)) + r,
+    S_i integers with |S_i| <= 127, |r| < 2^(-7 s). Truncation toward zero, so
+    every slice keeps the sign of X. Exact in float64 (power-of-two scalings
+    and integer parts)."""
+    X = np.asarray(X, dtype=np.float64)
+    assert np.all(np.abs(X) < 1.0)
+    out, Y = [], X.copy()
+    for _ in range(s):
+        Y = Y * 2.0 ** SLICE_BITS
+        q = np.trunc(Y)
+        out.append(q)
+        Y = Y - q
+    return out
+
+
+def slice_pairs(s):
+    """The kept slice products (i, j), i, j < s, i + j <= s, in the order they
+    are summed: by i, then j."""
+    return [(i, j) for i in range(s) for j in range(s) if i + j <= s]
+
+
+def slice_tables(p, offsets=None):
+    """Table operand of the exact-slice M2L at unit spacing: B[d][k'][n'] =
+    T_d[k'][n'] 2^-f_k' 2^-e_B(n') (harmonic rows and columns), and e_B."""
+    offsets = stencil() if offsets is None else offsets
+    ks = multi_indices(p)
+    hidx = [ks.index(k) for k in harmonic_indices(p)]
+    T = stencil_tensors(p, 1.0, offsets)[:, hidx][:, :, hidx]
+    Tf = T * 2.0 ** (-slice_prescale(p).astype(np.float64))[None, :, None]
+    eB = np.array([pow2_exponent(np.abs(Tf[:, :, n]).max()) for n in range(Tf.shape[2])])
+    return Tf * 2.0 ** (-eB.astype(np.float64))[None, None, :], eB
+
+
+def m2l_exact_slice(M, p, h, mask=FULL_MASK, slices=7, offsets=None, with_accumulators=False):
+    """Expectation model of the exact-slice M2L (harmonic form, int8 slices).
+
+    Steps: fold and h-scale the moments (Mh_k' = h^-|k'| sum_k F[k, k'] M_k);
+    prescale by 2^f_k'; one exponent e_A for the sub-grid (from the largest
+    |value| over the reachable window [2, 22)^3, the only cells M2L reads);
+    A = that / 2^e_A and B from slice_tables, both cut into
+    `slices` slices; for every kept pair (i, j) the integer sum
+    acc_ij[t][n'] = sum_{d, k'} A_i[k'](t + d) B_j[d][k'][n'] (exact);
+    Lh_n' = 2^(e_A + e_B(n')) sum_{(i, j)} 2^(-7 (i + j + 2)) acc_ij (float64, in
+    slice_pairs order); L = F Lh, scaled by h^(-1-|n|). Returns L [C, 8, 8, 8]
+    (and the accumulators {(i, j): int array [512, C']} if asked).
+    """
+    offsets = stencil() if offsets is None else offsets
+    ks = multi_indices(p)
+    hs = harmonic_indices(p)
+    Cp = len(hs)
+    F = harmonic_fold(p)
+    ordh = np.array([sum(k) for k in hs], dtype=np.float64)
+    Mh = np.tensordot(F.T, _masked(M, mask), axes=(1, 0)) * (h ** -ordh)[:, None, None, None]
+    # M2L reads only the reachable window [2, 22)^3 of the frame: the exponent
+    # comes from there, and the cells outside it are never sliced
+    Ms = np.zeros_like(Mh)
+    w = slice(2, 22)
+    Ms[:, w, w, w] = Mh[:, w, w, w] * 2.0 ** slice_prescale(p).astype(np.float64)[:, None, None, None]
+    eA = pow2_exponent(np.abs(Ms).max())
+    A = Ms * 2.0 ** -eA
+    B, eB = slice_tables(p, offsets)
+    As = slice_int8(A, slices)
+    Bs = slice_int8(B, slices)
+    lo = BLOCK
+    acc = {}
+    Lh = np.zeros((Cp, BLOCK ** 3))
+    for i, j in slice_pairs(slices):
+        Ai = As[i].astype(np.int64)
+        a = np.zeros((BLOCK ** 3, Cp), dtype=np.int64)
+        for d, Bd in zip(offsets, Bs[j].astype(np.int64)):
+            dx, dy, dz = d
+            win = Ai[:, lo + dz:lo + BLOCK + dz, lo + dy:lo + BLOCK + dy, lo + dx:lo + BLOCK + dx]
+            a += win.reshape(Cp, -1).T @ Bd
+        acc[(i, j)] = a
+        Lh += a.T.astype(np.float64) * 2.0 ** (-SLICE_BITS * (i + j + 2))
+    Lh *= 2.0 ** (eA + eB.astype(np.float64))[:, None]
+    L = (F @ Lh) * (h ** (-1.0 - np.array([sum(k) for k in ks], dtype=np.float64)))[:, None]
+    L = L.reshape(len(ks), BLOCK, BLOCK, BLOCK)
+    return (L, acc) if with_accumulators else L
