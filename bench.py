@@ -42,6 +42,7 @@ import synth  # noqa: E402
 METRIC = "M2L cell-pair interactions/s FP64 vs split-FP32 (<=1e-10 rel); fwd+bwd ms/batch"
 FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
 FP32_PEAK_TFLOPS = 157.3    # MI355X dense FP32 matrix peak
+INT8_PEAK_TOPS = 5000.0     # MI355X dense int8 matrix peak
 HBM_PEAK_GBS = 8000.0
 # the step's kernel: the M2L kernel source and the moment phase it includes
 STEP_SRCS = [os.path.join(ROOT, "paper_2304_11002_amd", "csrc", f) for f in ("m2l_mfma.hip", "p2m_common.h")]
@@ -418,6 +419,54 @@ def bench_uneven(torch, fmm, ctx, K, W):
     return out
 
 
+def slice_int8_ops(desc, slices):
+    """Executed int8 matrix operations (2 per multiply-add) of the exact-slice M2L:
+    per sub-grid 4 waves x 8 tiles x 223 offset quads x (kept slice pairs) instructions
+    of 16 x 16 x 64 multiply-adds (no quad of a full-mask sub-grid is skipped)."""
+    kept = sum(1 for i in range(slices) for j in range(slices) if i + j <= slices)
+    return len(desc) * 4 * 8 * 223 * kept * 16 * 16 * 64 * 2
+
+
+def bench_exact_slice(torch, fmm, ctx, desc, M, L_fp64, pairs, K, W, harmonic_ms):
+    """The exact-slice M2L (int8 matrix cores, exact int32 sums) on the same moments
+    as the step, at 6 and 7 slices; error against the float64 device result."""
+    out = {}
+    Lx = torch.empty_like(L_fp64)
+    prev = ctx.get_option(fmm.FMM_OPT_SLICES)
+    try:
+        for S in (7, 6):
+            ctx.set_option(fmm.FMM_OPT_SLICES, S)
+            ctx.m2l(desc, M, Lx, fmm.FMM_EXACT_SLICE)          # slice buffers allocated, untimed
+
+            def step_x(ev, i):
+                if ev: ev[0].record()
+                ctx.m2l(desc, M, Lx, fmm.FMM_EXACT_SLICE)
+                if ev: ev[1].record()
+
+            _, seg_x = timed(torch, step_x, K, W, marks=1)
+            ms_x = seg_x[:, 0].mean()
+            err = rel_to_component_max(Lx, L_fp64, desc, fmm)
+            ops = slice_int8_ops(desc, S)
+            out["slices_%d" % S] = {
+                "m2l_ms": float(ms_x), "pairs_per_s": pairs / (ms_x * 1e-3),
+                "speedup_vs_harmonic_fp64_m2l": float(harmonic_ms / ms_x),
+                "int8_ops_per_launch": ops,
+                "int8_tops_whole_call": ops / (ms_x * 1e-3) / 1e12,
+                "frac_of_int8_peak_whole_call": ops / (ms_x * 1e-3) / 1e12 / INT8_PEAK_TOPS,
+                "error_vs_fp64": dict(err, scale="largest |L| of the component in the sub-grid")}
+            log("exact-slice M2L, %d slices: %.3f ms (x%.2f vs harmonic FP64), %.0f int8 TOPS over the call, "
+                "max err %.3g of the component max" % (S, ms_x, harmonic_ms / ms_x, ops / (ms_x * 1e-3) / 1e12,
+                                                         err["max"]))
+    finally:
+        ctx.set_option(fmm.FMM_OPT_SLICES, prev)
+    out["what"] = ("fmm_m2l with FMM_EXACT_SLICE: slice_window_kernel (fold, exponent, int8 slices of the "
+                   "20^3 window per sub-grid) + m2l_fwd_slice_kernel (v_mfma_i32_16x16x64_i8, exact int32 "
+                   "sums, float64 across slice pairs)")
+    out["error_vs_oracle"] = "tests/test_gpu_slice.py, tests/test_gpu_fullsize.py (sampled sub-grids, vs Labs)"
+    del Lx
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,6 +483,8 @@ def main():
                     help="only the 6000-sub-grid uneven batch (for profiling)")
     ap.add_argument("--fwd-bwd-only", action="store_true",
                     help="only the 2048-sub-grid gradient batch (for profiling)")
+    ap.add_argument("--slice-only", action="store_true",
+                    help="only the step's moments and the exact-slice M2L (for profiling)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of this many GiB three times (counter calibration)")
     args = ap.parse_args()
@@ -486,6 +537,17 @@ def main():
     L = torch.empty(l_el, dtype=torch.float64, device="cuda")
     ctx.p2m(desc, pos, mass, 8, M)
     tuned = ctx.autotune(desc, M, L, fmm.FMM_FP64_HARMONIC)    # configuration for this batch
+    if args.slice_only:
+        def step_h(ev, i):
+            if ev: ev[0].record()
+            ctx.m2l(desc, M, L, fmm.FMM_FP64_HARMONIC)
+            if ev: ev[1].record()
+
+        _, seg_h = timed(torch, step_h, K, W, marks=1)
+        print(json.dumps({"exact_slice": bench_exact_slice(torch, fmm, ctx, desc, M, L, pairs, K, W,
+                                                           seg_h[:, 0].mean())}), flush=True)
+        ctx.close()
+        return
     ctx.p2m_m2l(desc, pos, mass, 8, M, L, fmm.FMM_FP64_HARMONIC)   # graph capture, untimed
 
     def step(ev, i):
@@ -598,6 +660,7 @@ def main():
             del Ls
         except fmm.FMMError as e:
             out["split_fp32"] = {"error": str(e)}
+        out["exact_slice"] = bench_exact_slice(torch, fmm, ctx, desc, M, L, pairs, K, W, m2l_ms)
     if not args.no_extras:
         # ---------------- evaluation at the particles (near field + L2P) from the step's L
         del M

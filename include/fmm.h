@@ -92,6 +92,20 @@ typedef int32_t fmm_precision;
                               and L is expanded back to all C components from its harmonic
                               ones (L_(a,b,c+2) = -L_(a+2,b,c) - L_(a,b+2,c)). Equal to
                               FMM_FP64 up to rounding; (p+1)^4 instead of C^2 products per pair */
+#define FMM_EXACT_SLICE   3 /* the harmonic form on int8 matrix cores with exact integer sums (the
+                              error-free splitting of Ozaki et al. with int8 slices): the folded
+                              moments of a sub-grid are scaled by a fixed per-component power of two
+                              (their geometric bound per unit cell mass) and one power of two for the
+                              sub-grid into (-1, 1), the tables restricted to the harmonic rows and
+                              columns by the inverse per-row factor and one power of two per column;
+                              both are cut into S signed 7-bit slices (FMM_OPT_SLICES, 6 to 8), and
+                              every slice product with i + j <= S is summed exactly in int32 over the
+                              offsets and components, then weighted by 2^-7(i+j+2) in float64.
+                              Error against the float64 M2L, relative to the absolute-value sum
+                              Labs: below 1e-13 at S = 7, 1e-11 at S = 6 (about 1e-14 and 2e-12
+                              measured). Orders 2 and 3 only (p = 4 returns FMM_EUNSUPPORTED);
+                              needs 128,000 S bytes of device memory per sub-grid for the slices,
+                              held with the descriptor set */
 
 /* One descriptor per sub-grid (host memory). */
 typedef struct {
@@ -116,6 +130,7 @@ typedef struct {
                                   transpose of the FMM_FP64_HARMONIC operator: dL folded to the
                                   (p+1)^2 harmonic columns, dM expanded from the folded components;
                                   equal to the dense adjoint up to rounding; MFMA kernel only) */
+#define FMM_OPT_SLICES      7  /* FMM_EXACT_SLICE: slices per operand S, 6, 7 (default) or 8 */
 #define FMM_OPT_ROUND_SPLIT 6  /* fmm_m2l (and the M2L of fmm_p2m_m2l when it runs as two
                                   launches) on batches of at most 256 sub-grids, with a configuration
                                   with LDS-staged tables: 0 (default) one workgroup per sub-grid;

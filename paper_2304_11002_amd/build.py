@@ -17,7 +17,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfmm.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["tables.hip", "p2m.hip", "m2l_ref.hip", "m2l_mfma.hip", "evaluate.hip", "tree.hip", "fmm_api.hip"]
+SOURCES = ["tables.hip", "p2m.hip", "m2l_ref.hip", "m2l_mfma.hip", "m2l_slice.hip", "evaluate.hip", "tree.hip",
+           "fmm_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -101,7 +101,10 @@ struct DescEntry {
   int* split_base[2] = {};
   double* split_part[2] = {};
   bool part_even = true;          // every part_off even: particle blocks 16-byte aligned
-  int tuned[3] = {-1, -1, -1};    // autotuned configuration per precision
+  int tuned[4] = {-1, -1, -1, -1};   // autotuned configuration per precision
+  // FMM_EXACT_SLICE: the sub-grids' slice planes and exponents (one allocation)
+  void* slice_dev = nullptr;
+  size_t slice_bytes = 0;
   hipEvent_t ready = nullptr;     // upload finished
   hipEvent_t last_launch = nullptr;
 };
@@ -123,6 +126,7 @@ struct fmm_ctx {
   double* d_D = nullptr;                      // [892][165] derivatives up to order 8
   double* d_T[kMaxP + 1] = {};                // canonical [892][C][C] per order
   MfmaTables mfma;                            // packed tables for the matrix-core kernels
+  SliceTables slice;                          // int8 table slices of FMM_EXACT_SLICE
   TreeTables tree;                            // interaction-list tables of the multi-level M2L
   std::vector<std::unique_ptr<DescEntry>> descs;
   std::unordered_map<uint64_t, GraphEntry> graphs;
@@ -134,6 +138,7 @@ struct fmm_ctx {
   int adjoint_form = 0;     // FMM_OPT_ADJOINT_FORM
   int p2m_window = 0;       // FMM_OPT_P2M_WINDOW
   int round_split = 0;      // FMM_OPT_ROUND_SPLIT
+  int slices = 7;           // FMM_OPT_SLICES
 };
 
 namespace {
@@ -205,6 +210,19 @@ fmm_status check_ppc(fmm_ctx* ctx, int32_t ppc) {
   return FMM_OK;
 }
 
+fmm_status check_precision(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, fmm_precision prec) {
+  if (prec != FMM_FP64 && prec != FMM_SPLIT_FP32 && prec != FMM_FP64_HARMONIC && prec != FMM_EXACT_SLICE)
+    return set_err(ctx, FMM_EINVAL, "unknown precision");
+  if (prec == FMM_EXACT_SLICE)
+    for (int64_t b = 0; b < nsub; ++b)
+      if (desc[b].p > 3) {
+        char buf[120];
+        snprintf(buf, sizeof buf, "FMM_EXACT_SLICE runs orders 2 and 3; desc[%lld].p = %d", (long long)b, desc[b].p);
+        return set_err(ctx, FMM_EUNSUPPORTED, buf);
+      }
+  return FMM_OK;
+}
+
 #define CHECK_OK(expr)                    \
   do {                                    \
     fmm_status s_ = (expr);               \
@@ -237,6 +255,7 @@ void free_entry(DescEntry* e) {
     if (e->split_pinned[f]) (void)hipHostFree(e->split_pinned[f]);
   }
   if (e->pinned) (void)hipHostFree(e->pinned);
+  if (e->slice_dev) (void)hipFree(e->slice_dev);
   if (e->ready) (void)hipEventDestroy(e->ready);
   if (e->last_launch) (void)hipEventDestroy(e->last_launch);
 }
@@ -432,6 +451,7 @@ fmm_status fmm_create(fmm_ctx** out, int32_t device) {
     CREATE_TRY(launch_build_tensors(c->d_D, kMaxOrderD, p, c->d_T[p], c->internal));
   }
   CREATE_TRY(mfma_tables_create(&c->mfma, c->d_T, c->d_stencil, c->internal));
+  CREATE_TRY(slice_tables_create(&c->slice, c->d_T, c->internal));
   CREATE_TRY(tree_tables_create(&c->tree, c->d_T, st.data(), (int)(st.size() / 3), c->internal));
   CREATE_TRY(hipStreamSynchronize(c->internal));
 #undef CREATE_TRY
@@ -447,6 +467,7 @@ fmm_status fmm_destroy(fmm_ctx* ctx) {
     for (auto& g : ctx->graphs) destroy_graph(g.second);
     for (auto& e : ctx->descs) free_entry(e.get());
     mfma_tables_destroy(&ctx->mfma);
+    slice_tables_destroy(&ctx->slice);
     tree_tables_destroy(&ctx->tree);
     for (int p = 0; p <= kMaxP; ++p)
       if (ctx->d_T[p]) (void)hipFree(ctx->d_T[p]);
@@ -476,6 +497,10 @@ fmm_status fmm_set_option(fmm_ctx* ctx, int32_t option, int64_t value) {
     case FMM_OPT_ROUND_SPLIT:
       if (value != 0 && value != 1) return set_err(ctx, FMM_EINVAL, "FMM_OPT_ROUND_SPLIT value not 0/1");
       ctx->round_split = (int)value;
+      return FMM_OK;
+    case FMM_OPT_SLICES:
+      if (value < kSliceMin || value > kSliceMax) return set_err(ctx, FMM_EINVAL, "FMM_OPT_SLICES value not in [6,8]");
+      ctx->slices = (int)value;
       return FMM_OK;
     case FMM_OPT_ADJOINT_FORM:
       if (value != 0 && value != 1) return set_err(ctx, FMM_EINVAL, "FMM_OPT_ADJOINT_FORM value not 0/1");
@@ -807,6 +832,40 @@ static fmm_status run_split(fmm_ctx* ctx, DescEntry* e, const double* M, double*
   return FMM_OK;
 }
 
+// FMM_EXACT_SLICE: the slice planes and exponents of the set (allocated on first
+// use, and again if more slices are asked for), then the two kernels
+static fmm_status run_slice(fmm_ctx* ctx, DescEntry* e, const double* M, double* L, hipStream_t s) {
+  const int64_t nsub = (int64_t)e->host.size();
+  const size_t planes = align_up((size_t)nsub * ctx->slices * kSlicePlane, 256);
+  const size_t bytes = planes + sizeof(int32_t) * (size_t)nsub;
+  if (e->slice_bytes < bytes) {
+    if (e->slice_dev) {
+      // the previous launches on this set read the old buffer
+      HIP_TRY(ctx, hipEventSynchronize(e->last_launch));
+      (void)hipFree(e->slice_dev);
+      e->slice_dev = nullptr;
+      e->slice_bytes = 0;
+    }
+    HIP_TRY(ctx, hipMalloc(&e->slice_dev, bytes));
+    e->slice_bytes = bytes;
+  }
+  int8_t* pl = static_cast<int8_t*>(e->slice_dev);
+  int32_t* ex = reinterpret_cast<int32_t*>(pl + planes);
+  HIP_TRY(ctx, launch_m2l_slice(ctx->mfma, ctx->slice, e->work_h, e->d_desc, nsub, M, L, ctx->slices, pl, ex, s));
+  return FMM_OK;
+}
+
+// The M2L of one call: reference kernel, exact slices, round split or the
+// persistent matrix-core kernel.
+static fmm_status run_m2l(fmm_ctx* ctx, DescEntry* e, const double* M, double* L, fmm_precision prec,
+                          int cfg, hipStream_t s) {
+  if (ctx->m2l_kernel == 1) return run_ref(ctx, e, false, M, L, s);
+  if (prec == FMM_EXACT_SLICE) return run_slice(ctx, e, M, L, s);
+  if (ctx->round_split && (int64_t)e->host.size() <= kMaxSplitSubgrids && mfma_config_fusable(cfg))
+    return run_split(ctx, e, M, L, prec, cfg, s);
+  return run_mfma(ctx, e, M, L, prec, cfg, s);
+}
+
 static int pick_config(const fmm_ctx* ctx, const DescEntry* e, fmm_precision prec) {
   if (ctx->tile_config >= 0) return ctx->tile_config;
   if (e && e->tuned[prec] >= 0) return e->tuned[prec];
@@ -819,8 +878,7 @@ fmm_status fmm_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const do
   CHECK_OK(check_desc(ctx, desc, nsub));
   CHECK_OK(check_ptr(ctx, M, "M", nsub));
   CHECK_OK(check_ptr(ctx, L, "L", nsub));
-  if (prec != FMM_FP64 && prec != FMM_SPLIT_FP32 && prec != FMM_FP64_HARMONIC)
-    return set_err(ctx, FMM_EINVAL, "unknown precision");
+  CHECK_OK(check_precision(ctx, desc, nsub, prec));
   if (prec != FMM_FP64 && ctx->m2l_kernel == 1)
     return set_err(ctx, FMM_EINVAL, "the reference kernel computes FMM_FP64 only");
   if (ctx->m2l_kernel != 1 && ctx->tile_config >= 0 && !mfma_config_supports(ctx->tile_config, prec))
@@ -832,15 +890,7 @@ fmm_status fmm_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const do
   HIP_TRY(ctx, guard.err);
   DescEntry* e = nullptr;
   CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
-  if (ctx->m2l_kernel == 1) {
-    CHECK_OK(run_ref(ctx, e, false, M, L, s));
-  } else {
-    const int cfg = pick_config(ctx, e, prec);
-    if (ctx->round_split && nsub <= kMaxSplitSubgrids && mfma_config_fusable(cfg))
-      CHECK_OK(run_split(ctx, e, M, L, prec, cfg, s));
-    else
-      CHECK_OK(run_mfma(ctx, e, M, L, prec, cfg, s));
-  }
+  CHECK_OK(run_m2l(ctx, e, M, L, prec, pick_config(ctx, e, prec), s));
   return mark_used(ctx, e, s);
 }
 
@@ -854,8 +904,7 @@ fmm_status fmm_p2m_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, cons
   CHECK_OK(check_ptr(ctx, mass, "mass", nsub));
   CHECK_OK(check_ptr(ctx, M, "M", nsub));
   CHECK_OK(check_ptr(ctx, L, "L", nsub));
-  if (prec != FMM_FP64 && prec != FMM_SPLIT_FP32 && prec != FMM_FP64_HARMONIC)
-    return set_err(ctx, FMM_EINVAL, "unknown precision");
+  CHECK_OK(check_precision(ctx, desc, nsub, prec));
   if (prec != FMM_FP64 && ctx->m2l_kernel == 1)
     return set_err(ctx, FMM_EINVAL, "the reference kernel computes FMM_FP64 only");
   if (ctx->m2l_kernel != 1 && ctx->tile_config >= 0 && !mfma_config_supports(ctx->tile_config, prec))
@@ -876,10 +925,7 @@ fmm_status fmm_p2m_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, cons
     CHECK_OK(run_mfma(ctx, e, M, L, prec, cfg, s, pos, mass, M));
   } else {
     HIP_TRY(ctx, launch_p2m(e->d_desc, nsub, e->d_ids, e->count, pos, mass, ppc, M, e->part_even, true, s));
-    if (ctx->m2l_kernel == 1) CHECK_OK(run_ref(ctx, e, false, M, L, s));
-    else if (ctx->round_split && nsub <= kMaxSplitSubgrids && mfma_config_fusable(cfg))
-      CHECK_OK(run_split(ctx, e, M, L, prec, cfg, s));
-    else CHECK_OK(run_mfma(ctx, e, M, L, prec, cfg, s));
+    CHECK_OK(run_m2l(ctx, e, M, L, prec, cfg, s));
   }
   return mark_used(ctx, e, s);
 }
@@ -958,8 +1004,7 @@ fmm_status fmm_autotune(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, con
   CHECK_OK(check_desc(ctx, desc, nsub));
   CHECK_OK(check_ptr(ctx, M, "M", nsub));
   CHECK_OK(check_ptr(ctx, L, "L", nsub));
-  if (prec != FMM_FP64 && prec != FMM_SPLIT_FP32 && prec != FMM_FP64_HARMONIC)
-    return set_err(ctx, FMM_EINVAL, "unknown precision");
+  CHECK_OK(check_precision(ctx, desc, nsub, prec));
   if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
   if (nsub == 0) {
     if (chosen) *chosen = pick_config(ctx, nullptr, prec);
@@ -970,6 +1015,12 @@ fmm_status fmm_autotune(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, con
   HIP_TRY(ctx, guard.err);
   DescEntry* e = nullptr;
   CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
+  if (prec == FMM_EXACT_SLICE) {
+    // one kernel: nothing to time
+    e->tuned[prec] = mfma_default_config(prec);
+    if (chosen) *chosen = e->tuned[prec];
+    return mark_used(ctx, e, s);
+  }
   hipEvent_t t0, t1;
   HIP_TRY(ctx, hipEventCreate(&t0));
   HIP_TRY(ctx, hipEventCreate(&t1));

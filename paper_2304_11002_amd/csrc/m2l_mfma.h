@@ -107,6 +107,40 @@ hipError_t mfma_tables_create(MfmaTables* t, double* const* d_T, const int* d_st
 // rounds' fold plans and of L's expansion are MfmaTables::hround / hexp.
 bool harmonic_plan_maps(int p, int32_t rowk[32], int32_t colk[32], int* nrounds);
 void mfma_tables_destroy(MfmaTables* t);
+// The harmonic form's round plan for order p (host copy of MfmaTables::hround[p]).
+bool harmonic_rounds_host(int p, std::vector<HRound>* rounds);
+
+// ---------------------------------------------------------------------------
+// Exact-slice (int8) M2L, harmonic form, orders 2 and 3 (m2l_slice.hip).
+//
+// The folded moments of a sub-grid (the round plan's order, 16 bytes per cell,
+// zero past (p+1)^2) are scaled by the fixed per-component prescale 2^f and
+// one exponent e_A per sub-grid into (-1, 1) and cut into S signed 7-bit
+// slices; the tables (restricted to the harmonic rows and columns, rows in
+// the same order, columns in the expansion's order) are scaled by 2^-f per row
+// and 2^-e_B(n') per column and cut likewise. Slice products with i + j <= S
+// are summed exactly in int32 on the matrix cores (v_mfma_i32_16x16x64_i8),
+// each round's sums added to float64 accumulators with their weights.
+constexpr int kSliceMax = 8;            // slices per operand, at most
+constexpr int kSliceMin = 6;
+constexpr int kSliceBytes = 16;         // folded components per cell (padded)
+constexpr int kSlicePlane = kWin * kWin * kWin * kSliceBytes;   // bytes per slice of one sub-grid
+struct SliceTables {
+  // per order p = 2, 3: [kSliceMax slices][quad][64 lanes][16 bytes]: lane l holds
+  // column n' = l % 16 of offset 4 quad + l / 16, byte b = folded row b
+  int8_t* B[kMaxP + 1] = {};
+  int32_t eB[kMaxP + 1][16] = {};       // column exponents
+  int32_t f[kMaxP + 1][16] = {};        // row (folded component) prescale, round-plan order
+};
+// Host: tables from the float64 tables d_T (copied to the host; synchronous).
+hipError_t slice_tables_create(SliceTables* st, double* const* d_T, hipStream_t s);
+void slice_tables_destroy(SliceTables* st);
+// planes: nsub x S slice planes (S x kSlicePlane bytes per sub-grid, in descriptor
+// order); expo: nsub ints. Every descriptor must have p <= 3. The first kernel
+// slices each sub-grid's window, the second runs the persistent M2L over w.
+hipError_t launch_m2l_slice(const MfmaTables& mt, const SliceTables& st, const WorkList& w,
+                            const DevDesc* d_desc, int64_t nsub, const double* M, double* L,
+                            int S, int8_t* planes, int32_t* expo, hipStream_t s);
 
 int mfma_num_configs();
 bool mfma_config_supports(int cfg, fmm_precision prec);

@@ -1599,7 +1599,8 @@ struct Config {
 constexpr Config kConfigs[] = {{2, 8, false, FMM_FP64}, {1, 8, false, FMM_FP64},
                                {0, 8, true, FMM_FP64},  {0, 8, false, FMM_FP64},
                                {0, 4, false, FMM_FP64}, {0, 4, true, FMM_FP64},
-                               {0, 8, false, FMM_SPLIT_FP32}, {2, 8, false, FMM_FP64_HARMONIC}};
+                               {0, 8, false, FMM_SPLIT_FP32}, {2, 8, false, FMM_FP64_HARMONIC},
+                               {0, 4, false, FMM_EXACT_SLICE}};
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
 }  // namespace
@@ -1777,6 +1778,13 @@ bool build_harmonic(int p, HostHarmonic* out) {
 
 }  // namespace
 
+bool harmonic_rounds_host(int p, std::vector<HRound>* rounds) {
+  HostHarmonic hh;
+  if (!build_harmonic(p, &hh)) return false;
+  *rounds = hh.rounds;
+  return true;
+}
+
 bool harmonic_plan_maps(int p, int32_t rowk[32], int32_t colk[32], int* nrounds) {
   HostHarmonic hh;
   if (!build_harmonic(p, &hh)) return false;
@@ -1921,7 +1929,8 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
                            const double* M, double* L, fmm_precision prec, int cfg,
                            hipStream_t s, const double* pos, const double* mass, double* Mw) {
   if (w.count == 0) return hipSuccess;
-  if (!mfma_config_supports(cfg, prec)) return hipErrorInvalidValue;
+  // (FMM_EXACT_SLICE runs through launch_m2l_slice)
+  if (!mfma_config_supports(cfg, prec) || prec == FMM_EXACT_SLICE) return hipErrorInvalidValue;
   const bool fuse = pos != nullptr;
   if (fuse && (!mfma_config_fusable(cfg) || mass == nullptr || Mw != M)) return hipErrorInvalidValue;
   const int grid = std::min(t.num_cu, w.count);

@@ -13,10 +13,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfmm.so")
 
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_EUNSUPPORTED = 0, -1, -2, -3, -4
-FMM_FP64, FMM_SPLIT_FP32, FMM_FP64_HARMONIC = 0, 1, 2
+FMM_FP64, FMM_SPLIT_FP32, FMM_FP64_HARMONIC, FMM_EXACT_SLICE = 0, 1, 2, 3
 FMM_OPT_M2L_KERNEL, FMM_OPT_USE_GRAPH, FMM_OPT_TILE_CONFIG, FMM_OPT_ADJOINT_FORM = 1, 2, 3, 4
 FMM_OPT_P2M_WINDOW = 5
 FMM_OPT_ROUND_SPLIT = 6
+FMM_OPT_SLICES = 7
 
 FRAME, NCELL, NTARGET, NSTENCIL = 24, 24 ** 3, 512, 892
 FULL_MASK = (1 << 27) - 1
@@ -278,7 +279,8 @@ class Context:
 
     # the library's defaults (fmm.h), for get_option before any set_option
     _OPTION_DEFAULTS = {FMM_OPT_M2L_KERNEL: 0, FMM_OPT_USE_GRAPH: 1, FMM_OPT_TILE_CONFIG: -1,
-                        FMM_OPT_ADJOINT_FORM: 0, FMM_OPT_P2M_WINDOW: 0, FMM_OPT_ROUND_SPLIT: 0}
+                        FMM_OPT_ADJOINT_FORM: 0, FMM_OPT_P2M_WINDOW: 0, FMM_OPT_ROUND_SPLIT: 0,
+                        FMM_OPT_SLICES: 7}
 
     def set_option(self, option, value):
         self._run(self.lib.fmm_set_option(self.handle, option, int(value)))

@@ -253,3 +253,21 @@ def test_binding_checks_tensor_arguments(hctx):
     with pytest.raises(fmm.FMMError) as e:
         hctx.m2l(_bad(desc, "p", 5), M[:8], L[:8])
     assert e.value.status == fmm.FMM_EINVAL
+
+
+def test_exact_slice_argument_checks():
+    # orders above 3 and slice counts outside [6, 8] are rejected on the host
+    with fmm.Context(-1) as c:
+        desc, m_el, l_el = fmm.make_descriptors([3, 4], [0, 0], [fmm.FULL_MASK] * 2)
+        with pytest.raises(fmm.FMMError) as ex:
+            c.m2l(desc, 256, 256, fmm.FMM_EXACT_SLICE)
+        assert ex.value.status == fmm.FMM_EUNSUPPORTED and "orders 2 and 3" in str(ex.value)
+        for bad in (5, 9):
+            with pytest.raises(fmm.FMMError) as ex:
+                c.set_option(fmm.FMM_OPT_SLICES, bad)
+            assert ex.value.status == fmm.FMM_EINVAL
+        c.set_option(fmm.FMM_OPT_SLICES, 6)
+        d3, _, _ = fmm.make_descriptors([3, 2], [0, 2], [fmm.FULL_MASK] * 2)
+        with pytest.raises(fmm.FMMError) as ex:
+            c.m2l(d3, 256, 256, fmm.FMM_EXACT_SLICE)
+        assert ex.value.status == fmm.FMM_EUNSUPPORTED and "host-only" in str(ex.value)
