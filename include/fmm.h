@@ -180,6 +180,29 @@ fmm_status fmm_p2m(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
 fmm_status fmm_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
                    const double* M, double* L, fmm_precision prec, void* stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation): fmm_m2l with the same
+ * kernels and results (the configuration fmm_m2l uses for a descriptor set it
+ * has not tuned: FMM_OPT_TILE_CONFIG, else the precision's default), with the
+ * descriptor copy, the work list and the work counter in a statically
+ * allocated device array instead of memory the context allocates per
+ * descriptor set. The array holds FMM_NOALLOC_MAX_SUBGRIDS sub-grids (about
+ * 0.8 MB) and exists once per device until the process ends. The call
+ * allocates nothing: it waits on the host for the previous fmm_m2l_noalloc
+ * call of this context to have copied its descriptors out of a pinned host
+ * buffer that fmm_create allocated, writes this call's descriptors and
+ * longest-first work list there, copies them to the array on `stream`, resets
+ * the counter with a kernel and launches the persistent matrix-core kernel
+ * (no graph). FMM_FP64, FMM_SPLIT_FP32 and FMM_FP64_HARMONIC; FMM_EXACT_SLICE
+ * and FMM_OPT_M2L_KERNEL = 1 return FMM_EUNSUPPORTED, nsub above
+ * FMM_NOALLOC_MAX_SUBGRIDS returns FMM_EINVAL. Every call on one device shares
+ * that device's array, whatever its context: calls that can overlap on one
+ * GPU (on other streams, or from other contexts) race and give wrong
+ * results; calls ordered on one stream do not. */
+#define FMM_NOALLOC_MAX_SUBGRIDS 16384
+fmm_status fmm_m2l_noalloc(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
+                           const double* M, double* L, fmm_precision prec, void* stream);
+
 /* P2M and M2L in one persistent launch. L is, bit for bit, what fmm_p2m
  * with FMM_OPT_P2M_WINDOW = 1 followed by fmm_m2l gives, and M receives
  * what that fmm_p2m writes: the moments of the frame rows holding the

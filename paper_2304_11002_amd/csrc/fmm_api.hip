@@ -14,6 +14,17 @@
 
 using namespace fmm;
 
+// Device memory of fmm_m2l_noalloc: descriptors, work list and work counter of
+// one call, at most FMM_NOALLOC_MAX_SUBGRIDS sub-grids. One copy per device,
+// held until the process ends; every call on a device shares it. Host code
+// never passes this name to a kernel or a copy: fmm_create looks up each
+// device's address of it (fmm_ctx::noalloc_dev) and that address is used.
+constexpr size_t kNoAllocDescBytes = sizeof(fmm_subgrid) * FMM_NOALLOC_MAX_SUBGRIDS;
+constexpr size_t kNoAllocWorkOff = (kNoAllocDescBytes + 255) / 256 * 256;
+constexpr size_t kNoAllocCounterOff = (kNoAllocWorkOff + sizeof(WorkItem) * FMM_NOALLOC_MAX_SUBGRIDS + 255) / 256 * 256;
+constexpr size_t kNoAllocBytes = kNoAllocCounterOff + 256;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
 
 thread_local std::string g_create_error;
@@ -139,6 +150,11 @@ struct fmm_ctx {
   int p2m_window = 0;       // FMM_OPT_P2M_WINDOW
   int round_split = 0;      // FMM_OPT_ROUND_SPLIT
   int slices = 7;           // FMM_OPT_SLICES
+  // fmm_m2l_noalloc: this device's address of the static array, a pinned host
+  // copy of its descriptor and work-list part, and the event after its upload
+  unsigned char* noalloc_dev = nullptr;
+  unsigned char* noalloc_host = nullptr;
+  hipEvent_t noalloc_uploaded = nullptr;
 };
 
 namespace {
@@ -453,6 +469,11 @@ fmm_status fmm_create(fmm_ctx** out, int32_t device) {
   CREATE_TRY(mfma_tables_create(&c->mfma, c->d_T, c->d_stencil, c->internal));
   CREATE_TRY(slice_tables_create(&c->slice, c->d_T, c->internal));
   CREATE_TRY(tree_tables_create(&c->tree, c->d_T, st.data(), (int)(st.size() / 3), c->internal));
+  // fmm_m2l_noalloc: the device's address of the static array (the device is current)
+  CREATE_TRY(hipGetSymbolAddress(reinterpret_cast<void**>(&c->noalloc_dev), HIP_SYMBOL(scratch)));
+  CREATE_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->noalloc_host), kNoAllocCounterOff, hipHostMallocDefault));
+  CREATE_TRY(hipEventCreateWithFlags(&c->noalloc_uploaded, hipEventDisableTiming));
+  fill_work_list(nullptr, 0, false, nullptr);   // the work-list builder's tables, set up once
   CREATE_TRY(hipStreamSynchronize(c->internal));
 #undef CREATE_TRY
   *out = ctx.release();
@@ -473,6 +494,8 @@ fmm_status fmm_destroy(fmm_ctx* ctx) {
       if (ctx->d_T[p]) (void)hipFree(ctx->d_T[p]);
     if (ctx->d_D) (void)hipFree(ctx->d_D);
     if (ctx->d_stencil) (void)hipFree(ctx->d_stencil);
+    if (ctx->noalloc_host) (void)hipHostFree(ctx->noalloc_host);
+    if (ctx->noalloc_uploaded) (void)hipEventDestroy(ctx->noalloc_uploaded);
     if (ctx->internal) (void)hipStreamDestroy(ctx->internal);
   }
   delete ctx;
@@ -892,6 +915,43 @@ fmm_status fmm_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const do
   CHECK_OK(get_desc(ctx, desc, nsub, s, &e));
   CHECK_OK(run_m2l(ctx, e, M, L, prec, pick_config(ctx, e, prec), s));
   return mark_used(ctx, e, s);
+}
+
+fmm_status fmm_m2l_noalloc(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const double* M,
+                           double* L, fmm_precision prec, void* stream) {
+  CHECK_OK(check_ctx(ctx));
+  CHECK_OK(check_desc(ctx, desc, nsub));
+  CHECK_OK(check_ptr(ctx, M, "M", nsub));
+  CHECK_OK(check_ptr(ctx, L, "L", nsub));
+  CHECK_OK(check_precision(ctx, desc, nsub, prec));
+  if (nsub > FMM_NOALLOC_MAX_SUBGRIDS)
+    return set_err(ctx, FMM_EINVAL, "fmm_m2l_noalloc: nsub exceeds FMM_NOALLOC_MAX_SUBGRIDS (16384)");
+  if (prec == FMM_EXACT_SLICE)
+    return set_err(ctx, FMM_EUNSUPPORTED, "fmm_m2l_noalloc: FMM_EXACT_SLICE needs slice buffers (use fmm_m2l)");
+  if (ctx->m2l_kernel == 1)
+    return set_err(ctx, FMM_EUNSUPPORTED, "fmm_m2l_noalloc runs the matrix-core kernels only");
+  if (ctx->tile_config >= 0 && !mfma_config_supports(ctx->tile_config, prec))
+    return set_err(ctx, FMM_EINVAL, "FMM_OPT_TILE_CONFIG selects a configuration of the other precision");
+  if (ctx->host_only) return set_err(ctx, FMM_EUNSUPPORTED, "host-only context");
+  if (nsub == 0) return FMM_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(ctx, guard.err);
+  // the pinned copy is rewritten only after the previous call's upload out of it
+  HIP_TRY(ctx, hipEventSynchronize(ctx->noalloc_uploaded));
+  unsigned char* hp = ctx->noalloc_host;
+  std::memcpy(hp, desc, sizeof(fmm_subgrid) * (size_t)nsub);
+  fill_work_list(desc, nsub, prec == FMM_FP64_HARMONIC, reinterpret_cast<WorkItem*>(hp + kNoAllocWorkOff));
+  const size_t used = kNoAllocWorkOff + sizeof(WorkItem) * (size_t)nsub;
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->noalloc_dev, hp, used, hipMemcpyHostToDevice, s));
+  HIP_TRY(ctx, hipEventRecord(ctx->noalloc_uploaded, s));
+  WorkList wl;
+  wl.items = reinterpret_cast<const WorkItem*>(ctx->noalloc_dev + kNoAllocWorkOff);
+  wl.count = (int)nsub;
+  wl.counter = reinterpret_cast<unsigned*>(ctx->noalloc_dev + kNoAllocCounterOff);   // reset by the launch
+  HIP_TRY(ctx, launch_m2l_mfma(ctx->mfma, wl, reinterpret_cast<const DevDesc*>(ctx->noalloc_dev), M, L, prec,
+                               pick_config(ctx, nullptr, prec), s));
+  return FMM_OK;
 }
 
 fmm_status fmm_p2m_m2l(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, const double* pos,

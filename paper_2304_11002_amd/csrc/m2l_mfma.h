@@ -25,6 +25,9 @@ struct WorkList {
 // products: C^2 x present pairs for the dense form, (p+1)^4 x present pairs for
 // the harmonic form (harmonic = true), whose p = 4 : p = 3 ratio is 2.44, not 3.06.
 std::vector<WorkItem> build_work_list(const fmm_subgrid* desc, int64_t nsub, bool harmonic = false);
+// The same list written into out[0 .. nsub) and ordered in place (no allocation):
+// longest first, equal costs by descriptor index.
+void fill_work_list(const fmm_subgrid* desc, int64_t nsub, bool harmonic, WorkItem* out);
 
 constexpr int kQuads = kNStencil / 4;   // offsets are consumed four at a time
 static_assert(kNStencil % 4 == 0, "offset quads");

@@ -1605,19 +1605,24 @@ constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
 }  // namespace
 
-std::vector<WorkItem> build_work_list(const fmm_subgrid* desc, int64_t nsub, bool harmonic) {
+void fill_work_list(const fmm_subgrid* desc, int64_t nsub, bool harmonic, WorkItem* out) {
   static const std::vector<int> st = host_stencil();
-  std::vector<WorkItem> items((size_t)nsub);
   for (int64_t b = 0; b < nsub; ++b) {
     const int p = desc[b].p;
     const int64_t per_pair = harmonic ? (int64_t)(p + 1) * (p + 1) * (p + 1) * (p + 1)
                                       : (int64_t)ncomp(p) * ncomp(p);
     const int64_t pairs = block_pair_count(desc[b].mask, st);
-    items[b].sub = (int32_t)b;
-    items[b].cost = (int32_t)(per_pair * pairs / 4096);
+    out[b].sub = (int32_t)b;
+    out[b].cost = (int32_t)(per_pair * pairs / 4096);
   }
-  std::stable_sort(items.begin(), items.end(),
-                   [](const WorkItem& a, const WorkItem& b) { return a.cost > b.cost; });
+  std::sort(out, out + nsub, [](const WorkItem& a, const WorkItem& b) {
+    return a.cost != b.cost ? a.cost > b.cost : a.sub < b.sub;
+  });
+}
+
+std::vector<WorkItem> build_work_list(const fmm_subgrid* desc, int64_t nsub, bool harmonic) {
+  std::vector<WorkItem> items((size_t)nsub);
+  fill_work_list(desc, nsub, harmonic, items.data());
   return items;
 }
 

@@ -20,11 +20,13 @@ FMM_OPT_ROUND_SPLIT = 6
 FMM_OPT_SLICES = 7
 
 FRAME, NCELL, NTARGET, NSTENCIL = 24, 24 ** 3, 512, 892
+NOALLOC_MAX_SUBGRIDS = 16384
 FULL_MASK = (1 << 27) - 1
 
 EXPORTS = [
     "fmm_create", "fmm_destroy", "fmm_status_string", "fmm_last_error", "fmm_set_option",
-    "fmm_stencil", "fmm_pair_count", "fmm_p2m", "fmm_m2l", "fmm_p2m_m2l", "fmm_m2l_backward", "fmm_m2l_p2m_backward",
+    "fmm_stencil", "fmm_pair_count", "fmm_p2m", "fmm_m2l", "fmm_m2l_noalloc", "fmm_p2m_m2l",
+    "fmm_m2l_backward", "fmm_m2l_p2m_backward",
     "fmm_p2m_backward", "fmm_stencil_tables", "fmm_autotune", "fmm_evaluate",
     "fmm_tree_size", "fmm_tree_upward", "fmm_tree_m2l", "fmm_tree_downward", "fmm_tree_evaluate",
     "fmm_tree_solve",
@@ -71,6 +73,7 @@ def load_library(path=LIB_PATH):
         "fmm_pair_count": ([vp, i64, ctypes.POINTER(i64)], i32),
         "fmm_p2m": ([vp, vp, i64, vp, vp, i32, vp, vp], i32),
         "fmm_m2l": ([vp, vp, i64, vp, vp, i32, vp], i32),
+        "fmm_m2l_noalloc": ([vp, vp, i64, vp, vp, i32, vp], i32),
         "fmm_p2m_m2l": ([vp, vp, i64, vp, vp, i32, vp, vp, i32, vp], i32),
         "fmm_m2l_backward": ([vp, vp, i64, vp, vp, vp], i32),
         "fmm_p2m_backward": ([vp, vp, i64, vp, i32, vp, vp, vp], i32),
@@ -302,6 +305,14 @@ class Context:
         e = _desc_extents(desc)
         self._run(self.lib.fmm_m2l(self.handle, pd, n, self._buf(M, e, "M", "M"), self._buf(L, e, "L", "L"),
                                    int(precision), self._s(stream, n)))
+
+    def m2l_noalloc(self, desc, M, L, precision=FMM_FP64, stream=None):
+        """fmm_m2l_noalloc: M2L with no allocation (static device array, at most
+        NOALLOC_MAX_SUBGRIDS sub-grids; overlapping calls on one GPU race)."""
+        pd, n = _desc_ptr(desc)
+        e = _desc_extents(desc)
+        self._run(self.lib.fmm_m2l_noalloc(self.handle, pd, n, self._buf(M, e, "M", "M"),
+                                           self._buf(L, e, "L", "L"), int(precision), self._s(stream, n)))
 
     def p2m_m2l(self, desc, pos, mass, ppc, M, L, precision=FMM_FP64, stream=None):
         """P2M over the rows holding the reachable window, then M2L, in one launch."""
