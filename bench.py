@@ -321,6 +321,8 @@ def bench_fwd_bwd(torch, fmm, ctx, K, W):
         ctx.m2l_p2m_backward(d5, pos5, 8, wt, dM5, dm5)   # dLoss/dL = w for loss = sum w . L
         if ev: ev[2].record()
 
+    ctx.p2m(d5, pos5, mass5, 8, M5)
+    tuned5 = ctx.autotune(d5, M5, L5, fmm.FMM_FP64_HARMONIC)
     prev = ctx.get_option(fmm.FMM_OPT_ADJOINT_FORM)
     ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 1)      # harmonic adjoint with the harmonic forward
     try:
@@ -341,6 +343,7 @@ def bench_fwd_bwd(torch, fmm, ctx, K, W):
            "fwd_ms": float(fwd_ms), "bwd_ms": float(bwd_ms),
            "fwd_bwd_ms_per_batch": float(fwd_ms + bwd_ms),
            "bwd_over_fwd": float(bwd_ms / fwd_ms),
+           "forward_autotune_choice": tuned5,
            "roofline": {"bound": "mfma", "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "flops_per_launch": fl_h, "flops_per_pair": harmonic_flops_per_pair(3),
                         "fwd_achieved": fl_h / (fwd_ms * 1e-3) / 1e12,

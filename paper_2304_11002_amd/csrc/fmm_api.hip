@@ -460,7 +460,8 @@ fmm_status fmm_create(fmm_ctx** out, int32_t device) {
   CREATE_TRY(hipMalloc(&c->d_stencil, st.size() * sizeof(int)));
   CREATE_TRY(hipMemcpyAsync(c->d_stencil, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice, c->internal));
   CREATE_TRY(hipMalloc(&c->d_D, sizeof(double) * kNStencil * ncomp(kMaxOrderD)));
-  CREATE_TRY(launch_gen_tables(c->d_stencil, kMaxOrderD, c->d_D, c->internal));
+  const std::vector<double> hD = host_derivative_tables(st.data(), kNStencil, kMaxOrderD);
+  CREATE_TRY(hipMemcpyAsync(c->d_D, hD.data(), sizeof(double) * hD.size(), hipMemcpyHostToDevice, c->internal));
   for (int p = 2; p <= kMaxP; ++p) {
     const int C = ncomp(p);
     CREATE_TRY(hipMalloc(&c->d_T[p], sizeof(double) * kNStencil * C * C));

@@ -1,12 +1,16 @@
 // Host-side launchers of the device kernels (one translation unit each).
 #pragma once
 
+#include <vector>
+
 #include "fmm_common.h"
 
 namespace fmm {
 
 // tables.hip
-hipError_t launch_gen_tables(const int* d_stencil, int order_d, double* d_D, hipStream_t s);
+// Host: D_m(-d) for the ns offsets d of `stencil` ([ns][3]) and |m| <= order, [ns][ncomp(order)],
+// each within one unit in the last place of the exact value.
+std::vector<double> host_derivative_tables(const int* stencil, int ns, int order);
 hipError_t launch_build_tensors(const double* d_D, int order_d, int p, double* d_T, hipStream_t s);
 
 // p2m.hip

@@ -231,13 +231,16 @@ __global__ void __launch_bounds__(WAVES * 64) m2l_fwd_kernel(
 
 constexpr int kBlChunkMax = 12 * 5 * 32;             // doubles per chunk buffer
 // HARM: the harmonic form, (p+1)^2 folded components instead of C
-template <int P, bool HARM = false>
+// QDIV: chunks of 1/QDIV of the default length (an autotuner candidate)
+template <int P, bool HARM = false, int QDIV = 1>
 struct BlShape {
   static constexpr int CR = HARM ? (P + 1) * (P + 1) : ncomp(P);   // reduced components
   static constexpr int NG = (CR + 3) / 4;
   // quads per staged chunk (even: a full chunk ends on the second operand set)
-  static constexpr int QC = HARM ? (kBlChunkMax / (NG * 32)) & ~1 : (P == 4 ? 6 : 12);
+  static constexpr int QC0 = HARM ? (kBlChunkMax / (NG * 32)) & ~1 : (P == 4 ? 6 : 12);
+  static constexpr int QC = (QC0 / QDIV) & ~1;
   static constexpr int CHUNK = QC * NG * 32;         // doubles per chunk buffer
+  static_assert(QC >= 2, "chunk length");
 };
 static_assert(BlShape<2>::CHUNK <= kBlChunkMax && BlShape<3>::CHUNK <= kBlChunkMax &&
               BlShape<4>::CHUNK <= kBlChunkMax && BlShape<2, true>::CHUNK <= kBlChunkMax &&
@@ -294,7 +297,8 @@ struct OneRound {
   __device__ double* partial() const { return part; }
 };
 
-template <int P, bool PIPE, bool FULL = false, bool HARM = false, class Hook = NoHook, class Range = AllRounds>
+template <int P, bool PIPE, bool FULL = false, bool HARM = false, class Hook = NoHook, class Range = AllRounds,
+          int QDIV = 1>
 __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* __restrict__ M,
                                                double* __restrict__ L,
                                                const double* __restrict__ Bl,
@@ -305,14 +309,14 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
                                                const HExp* __restrict__ hexp = nullptr,
                                                Hook hook = Hook(), Range range = Range()) {
   constexpr int C = ncomp(P);
-  constexpr int CR = BlShape<P, HARM>::CR;
-  constexpr int NG = BlShape<P, HARM>::NG;
-  constexpr int QC = BlShape<P, HARM>::QC;
-  constexpr int CH2 = BlShape<P, HARM>::CHUNK / 2;    // double2 per chunk
+  constexpr int CR = BlShape<P, HARM, QDIV>::CR;
+  constexpr int NG = BlShape<P, HARM, QDIV>::NG;
+  constexpr int QC = BlShape<P, HARM, QDIV>::QC;
+  constexpr int CH2 = BlShape<P, HARM, QDIV>::CHUNK / 2;    // double2 per chunk
   constexpr int ROUNDS = (CR + 1) / 2;
   constexpr int TPW = 4, NT = kBlThreads;
   constexpr int NCHUNK = (kQuads + QC - 1) / QC;
-  static_assert((CH2 + NT - 1) / NT == 2, "two staged table values per thread");
+  static_assert((CH2 + NT - 1) / NT <= 2, "at most two staged table values per thread");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // target plane
   const int kk = lane >> 4, ci = lane & 15;
@@ -642,7 +646,7 @@ __device__ __forceinline__ void fwd_bl_subgrid(const DevDesc& d, const double* _
 // phase while the others keep the matrix cores busy. Only the first item's
 // moments are computed before any M2L. The moments are written and read by the
 // same workgroup, with barriers between.
-template <bool PIPE, bool HARM = false, bool FUSE = false>
+template <bool PIPE, bool HARM = false, bool FUSE = false, int QDIV = 1>
 __global__ void __launch_bounds__(kBlThreads) m2l_fwd_bl_kernel(
     const WorkItem* __restrict__ items, int count, unsigned* __restrict__ counter,
     const DevDesc* __restrict__ desc, const double* M, double* __restrict__ L,
@@ -698,25 +702,32 @@ __global__ void __launch_bounds__(kBlThreads) m2l_fwd_bl_kernel(
     switch (d.p) {
       case 2:
         if (PIPE && full)
-          fwd_bl_subgrid<2, PIPE, true, HARM>(d, M, L, B2, lds_off, touch, smem, sB, s_off, hr2, he2, hook);
+          fwd_bl_subgrid<2, PIPE, true, HARM, std::remove_cv_t<decltype(hook)>, AllRounds, QDIV>(d, M, L, B2, lds_off, touch, smem, sB,
+                                                                              s_off, hr2, he2, hook);
         else
-          fwd_bl_subgrid<2, PIPE, false, HARM>(d, M, L, B2, lds_off, touch, smem, sB, s_off, hr2, he2, hook);
+          fwd_bl_subgrid<2, PIPE, false, HARM, std::remove_cv_t<decltype(hook)>, AllRounds, QDIV>(d, M, L, B2, lds_off, touch, smem, sB,
+                                                                              s_off, hr2, he2, hook);
         break;
       case 3:
         if (PIPE && full)
-          fwd_bl_subgrid<3, PIPE, true, HARM>(d, M, L, B3, lds_off, touch, smem, sB, s_off, hr3, he3, hook);
+          fwd_bl_subgrid<3, PIPE, true, HARM, std::remove_cv_t<decltype(hook)>, AllRounds, QDIV>(d, M, L, B3, lds_off, touch, smem, sB,
+                                                                              s_off, hr3, he3, hook);
         else
-          fwd_bl_subgrid<3, PIPE, false, HARM>(d, M, L, B3, lds_off, touch, smem, sB, s_off, hr3, he3, hook);
+          fwd_bl_subgrid<3, PIPE, false, HARM, std::remove_cv_t<decltype(hook)>, AllRounds, QDIV>(d, M, L, B3, lds_off, touch, smem, sB,
+                                                                              s_off, hr3, he3, hook);
         break;
       case 4:
         // the dense p = 4 operand sets (9 column groups) do not fit the registers
         // of the pipelined loop; the harmonic ones (7) do
         if (HARM && PIPE && full)
-          fwd_bl_subgrid<4, PIPE, true, HARM>(d, M, L, B4, lds_off, touch, smem, sB, s_off, hr4, he4, hook);
+          fwd_bl_subgrid<4, PIPE, true, HARM, std::remove_cv_t<decltype(hook)>, AllRounds, QDIV>(d, M, L, B4, lds_off, touch, smem, sB,
+                                                                               s_off, hr4, he4, hook);
         else if (HARM && PIPE)
-          fwd_bl_subgrid<4, PIPE, false, HARM>(d, M, L, B4, lds_off, touch, smem, sB, s_off, hr4, he4, hook);
+          fwd_bl_subgrid<4, PIPE, false, HARM, std::remove_cv_t<decltype(hook)>, AllRounds, QDIV>(d, M, L, B4, lds_off, touch, smem, sB,
+                                                                                s_off, hr4, he4, hook);
         else
-          fwd_bl_subgrid<4, false, false, HARM>(d, M, L, B4, lds_off, touch, smem, sB, s_off, hr4, he4, hook);
+          fwd_bl_subgrid<4, false, false, HARM, std::remove_cv_t<decltype(hook)>, AllRounds, QDIV>(d, M, L, B4, lds_off, touch, smem, sB,
+                                                                                s_off, hr4, he4, hook);
         break;
       default: break;
     }
@@ -1595,12 +1606,14 @@ struct Config {
   bool prefetch;    // table operands of the next offset quad loaded one quad ahead
                     // (not at p = 4 with 8 waves: the registers would spill)
   fmm_precision prec;
+  int qdiv = 1;     // LDS-staged tables: chunks of 1/qdiv of the default length
 };
 constexpr Config kConfigs[] = {{2, 8, false, FMM_FP64}, {1, 8, false, FMM_FP64},
                                {0, 8, true, FMM_FP64},  {0, 8, false, FMM_FP64},
                                {0, 4, false, FMM_FP64}, {0, 4, true, FMM_FP64},
                                {0, 8, false, FMM_SPLIT_FP32}, {2, 8, false, FMM_FP64_HARMONIC},
-                               {0, 4, false, FMM_EXACT_SLICE}};
+                               {0, 4, false, FMM_EXACT_SLICE},
+                               {1, 8, false, FMM_FP64_HARMONIC}, {2, 8, false, FMM_FP64_HARMONIC, 2}};
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
 }  // namespace
@@ -1943,8 +1956,8 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
   const Config& c = kConfigs[cfg];
   const HRound* nr = nullptr;
   const HExp* ne = nullptr;
-#define BL_LAUNCH(PIPEV, HARMV, FUSEV, B, HR, HE)                                                    \
-  hipLaunchKernelGGL((m2l_fwd_bl_kernel<PIPEV, HARMV, FUSEV>), dim3(grid), dim3(kBlThreads), 0, s,   \
+#define BL_LAUNCH(PIPEV, HARMV, FUSEV, B, HR, HE, ...)                                                    \
+  hipLaunchKernelGGL((m2l_fwd_bl_kernel<PIPEV, HARMV, FUSEV, ##__VA_ARGS__>), dim3(grid), dim3(kBlThreads), 0, s,   \
                      w.items, w.count, w.counter, d_desc, M, L, B[2], B[3], B[4], t.lds_off, t.touch, \
                      HR[0], HR[1], HR[2], HE[0], HE[1], HE[2], pos, mass, Mw)
   const HRound* hr[3] = {t.hround[2], t.hround[3], t.hround[4]};
@@ -1952,7 +1965,11 @@ hipError_t launch_m2l_mfma(const MfmaTables& t, const WorkList& w, const DevDesc
   const HRound* hr0[3] = {nr, nr, nr};
   const HExp* he0[3] = {ne, ne, ne};
   if (c.prec == FMM_FP64_HARMONIC) {
-    if (fuse) BL_LAUNCH(true, true, true, t.fwdh, hr, he);
+    if (c.ldstab == 1 && fuse) BL_LAUNCH(false, true, true, t.fwdh, hr, he);
+    else if (c.ldstab == 1) BL_LAUNCH(false, true, false, t.fwdh, hr, he);
+    else if (c.qdiv == 2 && fuse) BL_LAUNCH(true, true, true, t.fwdh, hr, he, 2);
+    else if (c.qdiv == 2) BL_LAUNCH(true, true, false, t.fwdh, hr, he, 2);
+    else if (fuse) BL_LAUNCH(true, true, true, t.fwdh, hr, he);
     else BL_LAUNCH(true, true, false, t.fwdh, hr, he);
     return hipGetLastError();
   }

@@ -168,17 +168,25 @@ __device__ __forceinline__ void slice_pass(const v4i* __restrict__ win, const v4
   for (int j = 0; j < NJP; ++j)
 #pragma unroll
     for (int t = 0; t < 8; ++t) acc[j][t] = v4i{0, 0, 0, 0};
-  // two operand sets: the reads of quad q + 1 are issued before the products of
-  // quad q (unconditionally, with the quad index clamped, so every path into the
-  // products sees the same outstanding reads)
-  v4i a0[8], a1[8], b0[NJP], b1[NJP];
-  auto load = [&](v4i(&da)[8], v4i(&db)[NJP], int q) __attribute__((always_inline)) {
-    const int off = s_off[4 * q + g];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) da[t] = win[abase[t] + off];
+  // Software pipeline (one wave per SIMD, so nothing else hides latency): the
+  // table operands, from L2, are loaded four quads ahead into a ring of four
+  // sets (each set reloaded right after its products are issued); the window
+  // operands, from LDS, one quad ahead into two sets; the window offsets two
+  // quads ahead. Loads are unconditional, with the
+  // quad index clamped to the last quad, so every path into the products sees the
+  // same outstanding loads; operands loaded past the last quad are never used.
+  v4i a0[8], a1[8], b0[NJP], b1[NJP], b2[NJP], b3[NJP];
+  int o0, o1;   // window offsets (this lane's offset of the quad) of the next two quads
+  auto ldB = [&](v4i(&db)[NJP], int q) __attribute__((always_inline)) {
+    q = min(q, kQuadsS - 1);
 #pragma unroll
     for (int j = 0; j < NJP; ++j) db[j] = Bt[((size_t)(J0 + j) * kQuadsS + q) * 64 + lane];
   };
+  auto ldA = [&](v4i(&da)[8], int off) __attribute__((always_inline)) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) da[t] = win[abase[t] + off];
+  };
+  auto ldO = [&](int q) __attribute__((always_inline)) { return s_off[4 * min(q, kQuadsS - 1) + g]; };
   auto mma = [&](const v4i(&sa)[8], const v4i(&sb)[NJP]) __attribute__((always_inline)) {
 #pragma unroll
     for (int j = 0; j < NJP; ++j)
@@ -186,16 +194,37 @@ __device__ __forceinline__ void slice_pass(const v4i* __restrict__ win, const v4
       for (int t = 0; t < 8; ++t) acc[j][t] = mfma_i8(sa[t], sb[j], acc[j][t]);
   };
   auto is_live = [&](int q) { return (live[q >> 6] >> (q & 63)) & 1ull; };
-  static_assert(kQuadsS % 2 == 1, "pairs of quads, then the last one");
-  load(a0, b0, 0);
-#pragma unroll 1
-  for (int q = 0; q + 1 < kQuadsS; q += 2) {
-    load(a1, b1, q + 1);
-    if (FULL || is_live(q)) mma(a0, b0);
-    load(a0, b0, q + 2);
-    if (FULL || is_live(q + 1)) mma(a1, b1);
+  // one step: the window operands of quad Q + 1 go to DA (its offset o0 was read
+  // a step ago), the offset of quad Q + 3 is read, quad Q's products run from
+  // (SA, SB), and SB, free again, takes the table operands of quad Q + 4
+#define SL_STEP(SA, SB, DA, Q)                  \
+  {                                             \
+    ldA(DA, o0);                                \
+    o0 = o1;                                    \
+    o1 = ldO((Q) + 3);                          \
+    if (FULL || is_live(Q)) mma(SA, SB);        \
+    ldB(SB, (Q) + 4);                           \
   }
-  if (FULL || is_live(kQuadsS - 1)) mma(a0, b0);
+  static_assert(kQuadsS % 4 == 3, "groups of four quads, then three");
+  // prologue: window operands of quad 0, offsets of quads 1 and 2, tables of quads 0-3
+  ldA(a0, ldO(0));
+  o0 = ldO(1);
+  o1 = ldO(2);
+  ldB(b0, 0);
+  ldB(b1, 1);
+  ldB(b2, 2);
+  ldB(b3, 3);
+#pragma unroll 1
+  for (int q = 0; q + 4 < kQuadsS; q += 4) {
+    SL_STEP(a0, b0, a1, q);
+    SL_STEP(a1, b1, a0, q + 1);
+    SL_STEP(a0, b2, a1, q + 2);
+    SL_STEP(a1, b3, a0, q + 3);
+  }
+  SL_STEP(a0, b0, a1, kQuadsS - 3);
+  SL_STEP(a1, b1, a0, kQuadsS - 2);
+  SL_STEP(a0, b2, a1, kQuadsS - 1);
+#undef SL_STEP
 #pragma unroll
   for (int j = 0; j < NJP; ++j) {
     const double wgt = ldexp(1.0, -7 * (I + J0 + j + 2));
