@@ -113,6 +113,21 @@ def test_uniform_4096_fp64_and_split(ctx, torch):
     torch.cuda.synchronize()
     assert torch.equal(Lf, Lh)
     assert torch.equal(torch.nan_to_num(Mf, 0.0), torch.nan_to_num(Mw, 0.0))
+    # the exact-slice M2L as the bench times it (the window-row moments), at 7 and 6
+    # slices: 1e-12 and 1e-11 of Labs on sampled sub-grids, deterministic
+    for slices, tol in ((7, 1e-12), (6, 1e-11)):
+        ctx.set_option(fmm.FMM_OPT_SLICES, slices)
+        try:
+            Lx = torch.full_like(L, float("nan"))
+            Lx2 = torch.full_like(L, float("nan"))
+            ctx.m2l(desc, Mw, Lx, fmm.FMM_EXACT_SLICE)
+            ctx.m2l(desc, Mw, Lx2, fmm.FMM_EXACT_SLICE)
+            torch.cuda.synchronize()
+        finally:
+            ctx.set_option(fmm.FMM_OPT_SLICES, 7)
+        assert torch.isfinite(Lx).all() and torch.equal(Lx, Lx2)
+        worst = check_sampled(w, desc, Lx, [0, 1, 2047, 4095], tol)
+        print("exact slices, %d slices: max |dL|/Labs %.3g on sampled sub-grids" % (slices, worst))
 
 
 def test_uniform_4096_evaluate(ctx, torch):
