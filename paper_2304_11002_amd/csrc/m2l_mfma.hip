@@ -23,6 +23,7 @@
 //   B: lane l -> block (l%16)/4, col l%4, k l/16
 //   D: lane l -> block (l%16)/4, col l%4, row l/16 (so: cell 4*((l%16)/4) + l/16)
 #include <algorithm>
+#include <functional>
 #include <type_traits>
 
 #include "kernels.h"
@@ -1014,7 +1015,11 @@ __global__ void __launch_bounds__(512) m2l_fwd_split_kernel(
 
 constexpr int kBwdWaves = 8;
 constexpr int kBwdThreads = kBwdWaves * 64;
-constexpr int kAccStride = kWinCells + 16;     // component stride of the LDS accumulators
+// component stride of the LDS accumulators: odd, so that the two components a
+// lane pair adds (lanes 2i and 2i + 1) fall in different banks; an even stride
+// doubles the LDS cycles of every add (measured: 16.2 against 8.3 cycles for a
+// 64-lane ds_add_f64 in this kernel's address pattern)
+constexpr int kAccStride = kWinCells + 17;
 constexpr int kMaxPairs = 512;
 
 // FULL: every neighbour block is present, so no pair is skipped and the pair
@@ -1029,7 +1034,7 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
                                             double* dM, const double* __restrict__ Bp,
                                             int npairs, const int* s_gs,
                                             const uint32_t* __restrict__ ptouch, double* smem,
-                                            const int* s_po, const HFold* __restrict__ hfold = nullptr,
+                                            const int4* __restrict__ pairs, const HFold* __restrict__ hfold = nullptr,
                                             const HOut* __restrict__ hout = nullptr, Hook hook = Hook()) {
   constexpr int C = ncomp(P);
   constexpr int CR = HARM ? (P + 1) * (P + 1) : C;   // reduced components
@@ -1077,7 +1082,13 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
 
   for (int i = tid; i < 2 * kAccStride; i += kBwdThreads) smem[i] = 0.0;
 
-  const uint32_t* tw = ptouch + wave * npairs;
+  // the pairs' output offsets (this lane's half) and, per target plane, the
+  // blocks each pair writes, through buffer resources like the tables: waits for
+  // them are waits on the vector memory counter, never on the LDS adds
+  const __amdgpu_buffer_rsrc_t prs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<int4*>(pairs), (short)0, npairs * 16, 0x00020000);
+  const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint32_t*>(ptouch + wave * npairs), (short)0, npairs * 4, 0x00020000);
   double* out = dM + d.m_off;
   for (int r = 0; r < ROUNDS; ++r) {
     __syncthreads();
@@ -1095,32 +1106,32 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
         const_cast<double*>(Bp), (short)0, ROUNDS * npairs * KC * 16 * (int)sizeof(double), 0x00020000);
     const int sbase = r * npairs * KC * 16 * (int)sizeof(double);
     const int vboff = (kk * 4 + j) * (int)sizeof(double);
-    // Three sets (tables, offsets, products, output offset) rotate over the
+    // Three sets (tables, touch mask, products, output offset) rotate over the
     // pairs: at pair q the set of pair q - 1, whose products are issued, takes
-    // the tables of pair q + 2, and a set's products are added into LDS just
-    // before the set is multiplied again. After a barrier the sets hold zeros,
-    // so those adds change nothing.
+    // the tables of pair q + 2 and the output offset of pair q - 1, and a set's
+    // products are added into LDS (at that offset) just before the set is
+    // multiplied again. Each offset is thus used two pairs after its load and
+    // never copied, so no wait on a load younger than the tables in use. After
+    // a barrier the sets hold zeros, so those adds change nothing.
     double b0[KC], b1[KC], b2[KC], acc0[TPW], acc1[TPW], acc2[TPW];
-    int o0, o1, o2;              // this lane's output offset of the set's pair
+    int f0, f1, f2;              // this lane's output offset of the set's pending products
     uint32_t tm0 = 0, tm1 = 0, tm2 = 0;
-    int ad0 = 0, ad1 = 0, ad2 = 0;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) acc0[t] = acc1[t] = acc2[t] = 0.0;
-    // (offsets are read from LDS, whose operations complete in order, so waiting
-    // for one does not wait for the adds issued after it)
-#define BW_LOAD(BS, OS, TS, Q)                                                      \
+#define BW_OFFSET(Q) ((int)__builtin_amdgcn_raw_buffer_load_b32(prs, half * 4, max((Q), 0) * 16, 0))
+#define BW_LOAD(BS, FS, TS, Q)                                                      \
   {                                                                                 \
     const int q_ = (Q);                                                             \
     const int so_ = sbase + q_ * KC * 16 * (int)sizeof(double);                     \
     _Pragma("unroll") for (int kc = 0; kc < KC; ++kc)                               \
       BS[kc] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(     \
                    brs, vboff + kc * 16 * (int)sizeof(double), so_, 0));            \
-    OS = s_po[2 * q_ + half];                                                       \
-    if (!FULL) TS = tw[q_];                                                         \
+    if (!FULL) TS = __builtin_amdgcn_raw_buffer_load_b32(trs, 0, q_ * 4, 0);        \
+    FS = BW_OFFSET(q_ - 3);                                                         \
   }
-#define BW_FLUSH(AS, AD)                                                            \
+#define BW_FLUSH(AS, FS)                                                            \
   _Pragma("unroll") for (int t = 0; t < TPW; ++t)                                   \
-    __hip_atomic_fetch_add(smem + obase[t] + (AD), AS[t], __ATOMIC_RELAXED,         \
+    __hip_atomic_fetch_add(smem + obase[t] + (FS), AS[t], __ATOMIC_RELAXED,         \
                            __HIP_MEMORY_SCOPE_WORKGROUP);
 #define BW_MMA(AS, BS)                                                              \
   {                                                                                 \
@@ -1142,48 +1153,54 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
     }                                                                               \
     __builtin_amdgcn_sched_group_barrier(0x008, NMF - TPW - KC, 0);                 \
   }
-// pair Q from set S (products AS); set N (pair Q - 1) takes the tables of Q + 2
-#define BW_STEP(BS, OS, TS, AS, AD, BN, ON, TN, Q)                                  \
-  BW_LOAD(BN, ON, TN, min((Q) + 2, npairs - 1));                                    \
-  if (FULL || ((TS) & d.mask) != 0) {                                               \
-    BW_FLUSH(AS, AD);                                                               \
-    AD = OS;                                                                        \
+// pair Q from set S (products AS, pending products of pair Q - 3 at FS); set N
+// (pair Q - 1) takes the tables of Q + 2 and the offset of pair Q - 1
+#define BW_STEP(BS, FS, TS, AS, BN, FN, TN, Q)                                      \
+  BW_LOAD(BN, FN, TN, min((Q) + 2, npairs - 1));                                    \
+  BW_FLUSH(AS, FS);                                                                 \
+  if (FULL || (__builtin_amdgcn_readfirstlane(TS) & d.mask) != 0) {                \
     BW_MMA(AS, BS);                                                                 \
     BW_INTERLEAVE();                                                                \
   } else {                                                                          \
-    BW_FLUSH(AS, AD);                                                               \
     _Pragma("unroll") for (int t = 0; t < TPW; ++t) AS[t] = 0.0;                    \
   }
-// at the end of a dz group: every set's products go in, then the barrier
+// at the end of a dz group: every set's products go in (the latest pair of
+// each set below QN, whose offset is loaded here), then the barrier
+#define BW_PENDING(X, QN) ((QN) - 1 - ((((QN) - 1 - (X)) % 3) + 3) % 3)
 #define BW_GROUP_END(QN)                                                            \
   if (__builtin_expect((QN) == gend, 0)) {                                          \
-    BW_FLUSH(acc0, ad0);                                                            \
-    BW_FLUSH(acc1, ad1);                                                            \
-    BW_FLUSH(acc2, ad2);                                                            \
+    f0 = BW_OFFSET(BW_PENDING(0, QN));                                              \
+    f1 = BW_OFFSET(BW_PENDING(1, QN));                                              \
+    f2 = BW_OFFSET(BW_PENDING(2, QN));                                              \
+    BW_FLUSH(acc0, f0);                                                             \
+    BW_FLUSH(acc1, f1);                                                             \
+    BW_FLUSH(acc2, f2);                                                             \
     _Pragma("unroll") for (int t = 0; t < TPW; ++t) acc0[t] = acc1[t] = acc2[t] = 0.0; \
     __syncthreads();   /* the next dz writes other planes of other waves */         \
     ++g;                                                                            \
     gend = __builtin_amdgcn_readfirstlane(s_gs[g + 1]);                             \
   }
-    BW_LOAD(b0, o0, tm0, 0);
-    BW_LOAD(b1, o1, tm1, min(1, npairs - 1));
+    BW_LOAD(b0, f0, tm0, 0);
+    BW_LOAD(b1, f1, tm1, min(1, npairs - 1));
     int g = 0, gend = __builtin_amdgcn_readfirstlane(s_gs[1]);
 #pragma unroll 1
     for (int q = 0; q < npairs; q += 3) {
-      BW_STEP(b0, o0, tm0, acc0, ad0, b2, o2, tm2, q);
+      BW_STEP(b0, f0, tm0, acc0, b2, f2, tm2, q);
       BW_GROUP_END(q + 1);
       if (__builtin_expect(q + 1 >= npairs, 0)) break;
-      BW_STEP(b1, o1, tm1, acc1, ad1, b0, o0, tm0, q + 1);
+      BW_STEP(b1, f1, tm1, acc1, b0, f0, tm0, q + 1);
       BW_GROUP_END(q + 2);
       if (__builtin_expect(q + 2 >= npairs, 0)) break;
-      BW_STEP(b2, o2, tm2, acc2, ad2, b1, o1, tm1, q + 2);
+      BW_STEP(b2, f2, tm2, acc2, b1, f1, tm1, q + 2);
       BW_GROUP_END(q + 3);
     }
+#undef BW_OFFSET
 #undef BW_LOAD
 #undef BW_FLUSH
 #undef BW_MMA
 #undef BW_INTERLEAVE
 #undef BW_STEP
+#undef BW_PENDING
 #undef BW_GROUP_END
     // write the round's components of dM (whole frame) and clear the accumulators
     if constexpr (HARM) {
@@ -1261,16 +1278,10 @@ __global__ void __launch_bounds__(kBwdThreads) m2l_bwd_kernel(
     const HOut* __restrict__ ho4, const double* __restrict__ pos = nullptr,
     double* __restrict__ dmass = nullptr) {
   __shared__ double smem[2 * kAccStride];
-  __shared__ int s_po[2 * kMaxPairs];     // output offsets of each pair's two offsets
   __shared__ int s_gs[16];                // first pair of each dz group, and the end
   __shared__ int s_item;
   static_assert(kP2MAdjRowsLds <= 2 * kAccStride && kBwdThreads == kP2MRowsThreads,
                 "the gradient phase fits the accumulator buffer and the workgroup");
-  for (int i = threadIdx.x; i < npairs; i += blockDim.x) {
-    const int4 o = pairs[i];
-    s_po[2 * i] = o.x;
-    s_po[2 * i + 1] = o.y;
-  }
   if (threadIdx.x < 14) s_gs[threadIdx.x] = gstart[threadIdx.x];
   // the mass gradients of item `it` (its dM complete), with `lds` as staging
   auto grads = [&](int it, double* lds) __attribute__((always_inline)) {
@@ -1298,16 +1309,16 @@ __global__ void __launch_bounds__(kBwdThreads) m2l_bwd_kernel(
     }();
     switch (d.p) {
       case 2:
-        if (full) bwd_subgrid<2, true, HARM>(d, dL, dM, B2, npairs, s_gs, ptouch, smem, s_po, hf2, ho2, hook);
-        else bwd_subgrid<2, false, HARM>(d, dL, dM, B2, npairs, s_gs, ptouch, smem, s_po, hf2, ho2, hook);
+        if (full) bwd_subgrid<2, true, HARM>(d, dL, dM, B2, npairs, s_gs, ptouch, smem, pairs, hf2, ho2, hook);
+        else bwd_subgrid<2, false, HARM>(d, dL, dM, B2, npairs, s_gs, ptouch, smem, pairs, hf2, ho2, hook);
         break;
       case 3:
-        if (full) bwd_subgrid<3, true, HARM>(d, dL, dM, B3, npairs, s_gs, ptouch, smem, s_po, hf3, ho3, hook);
-        else bwd_subgrid<3, false, HARM>(d, dL, dM, B3, npairs, s_gs, ptouch, smem, s_po, hf3, ho3, hook);
+        if (full) bwd_subgrid<3, true, HARM>(d, dL, dM, B3, npairs, s_gs, ptouch, smem, pairs, hf3, ho3, hook);
+        else bwd_subgrid<3, false, HARM>(d, dL, dM, B3, npairs, s_gs, ptouch, smem, pairs, hf3, ho3, hook);
         break;
       case 4:
-        if (full) bwd_subgrid<4, true, HARM>(d, dL, dM, B4, npairs, s_gs, ptouch, smem, s_po, hf4, ho4, hook);
-        else bwd_subgrid<4, false, HARM>(d, dL, dM, B4, npairs, s_gs, ptouch, smem, s_po, hf4, ho4, hook);
+        if (full) bwd_subgrid<4, true, HARM>(d, dL, dM, B4, npairs, s_gs, ptouch, smem, pairs, hf4, ho4, hook);
+        else bwd_subgrid<4, false, HARM>(d, dL, dM, B4, npairs, s_gs, ptouch, smem, pairs, hf4, ho4, hook);
         break;
       default: break;
     }
@@ -1536,7 +1547,15 @@ size_t bwd_pack_elems(int p, int npairs) {
 }
 
 // Offsets of one dz paired so that the two never send two cells of a 4x4
-// tile to the same output cell; the pairs are grouped by dz (13 groups).
+// tile to the same output cell (4 cells apart in x or y); the pairs are grouped
+// by dz (13 groups). The lanes of a tile's add hold 4 x, 4 y, 2 components and
+// the 2 offsets of the pair; with the accumulator rows 20 doubles apart and an
+// odd component stride, the add takes the fewest LDS cycles when the two
+// offsets' x differ by 2 mod 4 (measured: 8.2 cycles for a 64-lane ds_add_f64,
+// 16 to 20 for any other difference). So the offsets are first paired by a
+// maximum matching among such partners (a bipartite graph: x = 0, 1 mod 4
+// against x = 2, 3 mod 4), the rest greedily with any partner 4 cells away,
+// and what is left runs alone.
 void build_pairs(const std::vector<int>& st, std::vector<int4>* pairs, std::vector<int>* gstart) {
   gstart->clear();
   for (int dz = -kRad; dz <= kRad; ++dz) {
@@ -1544,22 +1563,50 @@ void build_pairs(const std::vector<int>& st, std::vector<int4>* pairs, std::vect
     std::vector<int> ids;
     for (int i = 0; i < kNStencil; ++i)
       if (st[3 * i + 2] == dz) ids.push_back(i);
-    std::vector<bool> used(ids.size(), false);
-    for (size_t a = 0; a < ids.size(); ++a) {
-      if (used[a]) continue;
-      used[a] = true;
-      int partner = -1;
-      for (size_t b = ids.size(); b-- > a + 1;) {
-        const int ia = ids[a], ib = ids[b];
-        if (!used[b] && (std::abs(st[3 * ia] - st[3 * ib]) >= 4 || std::abs(st[3 * ia + 1] - st[3 * ib + 1]) >= 4)) {
-          partner = (int)b;
-          break;
+    const int n = (int)ids.size();
+    auto dx = [&](int a) { return st[3 * ids[a]]; };
+    auto compatible = [&](int a, int b) {
+      return std::abs(dx(a) - dx(b)) >= 4 || std::abs(st[3 * ids[a] + 1] - st[3 * ids[b] + 1]) >= 4;
+    };
+    auto preferred = [&](int a, int b) { return compatible(a, b) && (((dx(a) - dx(b)) % 4) + 4) % 4 == 2; };
+    std::vector<int> mate(n, -1);
+    std::vector<char> seen(n);
+    // augmenting paths from the x = 0, 1 (mod 4) side
+    std::function<bool(int)> augment = [&](int a) {
+      for (int b = 0; b < n; ++b)
+        if (!seen[b] && preferred(a, b)) {
+          seen[b] = 1;
+          if (mate[b] < 0 || augment(mate[b])) {
+            mate[b] = a;
+            mate[a] = b;
+            return true;
+          }
         }
+      return false;
+    };
+    for (int a = 0; a < n; ++a)
+      if (((dx(a) % 4) + 4) % 4 < 2) {
+        std::fill(seen.begin(), seen.end(), 0);
+        augment(a);
       }
-      const int s1 = ids[a], s2 = partner >= 0 ? ids[partner] : -1;
-      if (partner >= 0) used[partner] = true;
+    for (int a = 0; a < n; ++a)
+      if (mate[a] < 0)
+        for (int b = n - 1; b > a; --b)
+          if (mate[b] < 0 && compatible(a, b)) {
+            mate[a] = b;
+            mate[b] = a;
+            break;
+          }
+    for (int a = 0; a < n; ++a) {
+      if (mate[a] >= 0 && mate[a] < a) continue;   // listed with its partner
+      const int s1 = ids[a], s2 = mate[a] >= 0 ? ids[mate[a]] : -1;
       const int o1 = st[3 * s1] + kWin * st[3 * s1 + 1] + kWin * kWin * st[3 * s1 + 2];
-      const int o2 = s2 >= 0 ? st[3 * s2] + kWin * st[3 * s2 + 1] + kWin * kWin * st[3 * s2 + 2] : o1;
+      // an offset without a partner: the second half's tables are zero, so its
+      // lanes add zeros; they go to the cells 2 away in x (toward the centre, so
+      // into the same row of the same wave's plane), where the add is as cheap
+      // as a preferred pair's
+      const int o2 = s2 >= 0 ? st[3 * s2] + kWin * st[3 * s2 + 1] + kWin * kWin * st[3 * s2 + 2]
+                             : o1 + (st[3 * s1] >= 0 ? -2 : 2);
       pairs->push_back(make_int4(o1, o2, s1, s2));
     }
   }
