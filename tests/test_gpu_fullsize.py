@@ -73,7 +73,8 @@ def test_uniform_4096_fp64_and_split(ctx, torch):
     ctx.m2l(desc, M, L2)
     torch.cuda.synchronize()
     assert torch.isfinite(L).all() and torch.equal(L, L2)
-    check_sampled(w, desc, L, [0, 1, 2047, 4095])
+    worst = check_sampled(w, desc, L, [0, 1, 2047, 4095])
+    print("4096 batch, dense FP64: max |dL|/Labs %.3g on sampled sub-grids" % worst)
     # split precision on the same moments: bounded error, everywhere finite
     Ls = torch.empty_like(L)
     ctx.m2l(desc, M, Ls, fmm.FMM_SPLIT_FP32)
@@ -87,6 +88,7 @@ def test_uniform_4096_fp64_and_split(ctx, torch):
         Lo, La = O.m2l(Mo, 3, 1.0), O.m2l_abs(Mo, 3, 1.0)
         rel.append((np.abs(Ls[o:o + 20 * 512].cpu().numpy().reshape(20, 8, 8, 8) - Lo) / La).ravel())
     rel = np.concatenate(rel)
+    print("4096 batch, split FP32: |dL|/Labs max %.3g, median %.3g" % (rel.max(), np.median(rel)))
     assert rel.max() < 1e-6 and np.median(rel) < 5e-8
     # the configuration the step is timed in: P2M over the rows holding the
     # reachable window, then the autotuned harmonic form, replayed from its graph
@@ -103,7 +105,8 @@ def test_uniform_4096_fp64_and_split(ctx, torch):
     ctx.m2l(desc, Mw, Lh2, fmm.FMM_FP64_HARMONIC)
     torch.cuda.synchronize()
     assert torch.isfinite(Lh).all() and torch.equal(Lh, Lh2)
-    check_sampled(w, desc, Lh, [0, 1, 2047, 4095])
+    worst = check_sampled(w, desc, Lh, [0, 1, 2047, 4095])
+    print("4096 batch, harmonic FP64 (the step's form): max |dL|/Labs %.3g on sampled sub-grids" % worst)
     # the step as the bench times it: one launch (fmm_p2m_m2l), replayed from its
     # graph: the same moments in the rows and the same L, bit for bit
     Mf = torch.full_like(M, float("nan"))
@@ -208,7 +211,8 @@ def test_uneven_6000(ctx, torch):
     nbits = np.array([bin(int(m)).count("1") for m in w.mask])
     sample.add(int(np.argmin(nbits)))
     sample.add(int(np.argmax(nbits)))
-    check_sampled(w, desc, L, sorted(sample))
+    worst = check_sampled(w, desc, L, sorted(sample))
+    print("uneven 6000: max |dL|/Labs %.3g on %d sampled sub-grids" % (worst, len(sample)))
 
 
 def test_gradient_2048_fd_and_oracle(ctx, torch):
@@ -259,6 +263,9 @@ def test_gradient_2048_fd_and_oracle(ctx, torch):
         c = O.cell_centres(1.0)[:, None, :]
         scale = O.p2m_adjoint(c + np.abs(pos_b - c), Ga, 3, 1.0)
         gb = g[b].cpu().numpy()
+        nz = scale > 0
+        print("gradient 2048, sub-grid %d: max |dg|/scale %.3g against the oracle"
+              % (b, float(np.max(np.abs(gb - go)[nz] / scale[nz]))))
         assert np.all(np.abs(gb - go) <= TOL * scale)
 
 

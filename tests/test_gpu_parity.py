@@ -137,6 +137,7 @@ def test_m2l_single_subgrid(ctx, torch, kernel):
     _, Lo, La = oracle_subgrid(w, 0, pos[0], mass[0])
     Lg = L.cpu().numpy().reshape(Lo.shape)
     assert_close(Lg, Lo, La, TOL, "L kernel %d" % kernel)
+    print("one p = 3 sub-grid, kernel %d: max |dL|/Labs %.3g" % (kernel, float(np.max(np.abs(Lg - Lo) / La))))
     assert 2600 < Lg[0].min() and Lg[0].max() < 2800
 
 
