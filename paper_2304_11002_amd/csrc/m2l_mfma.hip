@@ -1004,11 +1004,12 @@ __global__ void __launch_bounds__(512) m2l_fwd_split_kernel(
 // the 8^3 block only). One workgroup owns one sub-grid; for each pair of
 // output components ("round") the window's accumulators live in LDS. Wave w
 // holds target plane w (its dL values stay in registers for the whole
-// sub-grid) and applies the offsets of one dz at a time, so for a fixed dz
-// every output cell has one writing wave. One instruction multiplies
-// [16 targets x 4 dL components] by [4 components x (2 output components x
-// 2 offsets)]; the two offsets of a pair never map two cells of one 4x4 tile
-// to the same output cell (|dx2 - dx1| >= 4 or |dy2 - dy1| >= 4). Results
+// sub-grid) and applies the offsets of one group at a time (one dz, or two dz
+// at least 8 apart), so within a group every output cell has one writing wave.
+// One instruction multiplies [16 targets x 4 dL components] by [4 components
+// x (2 output components x 2 offsets)]; the two offsets of a pair never map
+// two cells of one 4x4 tile to the same output cell (|dx2 - dx1| >= 4 or
+// |dy2 - dy1| >= 4, or different dz). Results
 // are added with LDS atomic adds that return nothing; one wave's LDS
 // operations execute in issue order, so each cell's sum is taken in pair
 // order and the result is reproducible bit for bit.
@@ -1021,6 +1022,7 @@ constexpr int kBwdThreads = kBwdWaves * 64;
 // 64-lane ds_add_f64 in this kernel's address pattern)
 constexpr int kAccStride = kWinCells + 17;
 constexpr int kMaxPairs = 512;
+constexpr int kBwdGroups = 8;       // offset groups, between barriers (see build_pairs)
 
 // FULL: every neighbour block is present, so no pair is skipped and the pair
 // loop carries no branches.
@@ -1164,7 +1166,7 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
   } else {                                                                          \
     _Pragma("unroll") for (int t = 0; t < TPW; ++t) AS[t] = 0.0;                    \
   }
-// at the end of a dz group: every set's products go in (the latest pair of
+// at the end of an offset group: every set's products go in (the latest pair of
 // each set below QN, whose offset is loaded here), then the barrier
 #define BW_PENDING(X, QN) ((QN) - 1 - ((((QN) - 1 - (X)) % 3) + 3) % 3)
 #define BW_GROUP_END(QN)                                                            \
@@ -1176,7 +1178,7 @@ __device__ __forceinline__ void bwd_subgrid(const DevDesc& d, const double* __re
     BW_FLUSH(acc1, f1);                                                             \
     BW_FLUSH(acc2, f2);                                                             \
     _Pragma("unroll") for (int t = 0; t < TPW; ++t) acc0[t] = acc1[t] = acc2[t] = 0.0; \
-    __syncthreads();   /* the next dz writes other planes of other waves */         \
+    __syncthreads();   /* the next group writes other planes of other waves */      \
     ++g;                                                                            \
     gend = __builtin_amdgcn_readfirstlane(s_gs[g + 1]);                             \
   }
@@ -1278,11 +1280,12 @@ __global__ void __launch_bounds__(kBwdThreads) m2l_bwd_kernel(
     const HOut* __restrict__ ho4, const double* __restrict__ pos = nullptr,
     double* __restrict__ dmass = nullptr) {
   __shared__ double smem[2 * kAccStride];
-  __shared__ int s_gs[16];                // first pair of each dz group, and the end
+  __shared__ int s_gs[16];                // first pair of each offset group, and the end
+  static_assert(kBwdGroups + 2 <= 16, "the group starts, the end and one read past it");
   __shared__ int s_item;
   static_assert(kP2MAdjRowsLds <= 2 * kAccStride && kBwdThreads == kP2MRowsThreads,
                 "the gradient phase fits the accumulator buffer and the workgroup");
-  if (threadIdx.x < 14) s_gs[threadIdx.x] = gstart[threadIdx.x];
+  if (threadIdx.x < kBwdGroups + 1) s_gs[threadIdx.x] = gstart[threadIdx.x];
   // the mass gradients of item `it` (its dM complete), with `lds` as staging
   auto grads = [&](int it, double* lds) __attribute__((always_inline)) {
     const DevDesc dp = desc[items[it].sub];
@@ -1546,9 +1549,16 @@ size_t bwd_pack_elems(int p, int npairs) {
   return (size_t)ROUNDS * npairs * KC * 16;
 }
 
-// Offsets of one dz paired so that the two never send two cells of a 4x4
-// tile to the same output cell (4 cells apart in x or y); the pairs are grouped
-// by dz (13 groups). The lanes of a tile's add hold 4 x, 4 y, 2 components and
+// Offset groups of the adjoint: wave w writes output plane w + 6 + dz, so two
+// dz whose difference is at least 8 never make two of the 8 waves write one
+// plane, and their offsets can run between the same two barriers. The 13 dz
+// values make 8 groups (5 of two dz, 3 of one), 100 to 138 offsets each.
+constexpr int kBwdGroupDz[kBwdGroups][2] = {{-6, 2}, {-5, 3}, {-4, 4}, {-3, 5}, {-2, 6},
+                                            {-1, -1}, {0, 0}, {1, 1}};
+
+// Offsets of one group paired so that the two never send two cells of a 4x4
+// tile to the same output cell (4 cells apart in x or y, or different dz, so
+// different planes). The lanes of a tile's add hold 4 x, 4 y, 2 components and
 // the 2 offsets of the pair; with the accumulator rows 20 doubles apart and an
 // odd component stride, the add takes the fewest LDS cycles when the two
 // offsets' x differ by 2 mod 4 (measured: 8.2 cycles for a 64-lane ds_add_f64,
@@ -1558,15 +1568,16 @@ size_t bwd_pack_elems(int p, int npairs) {
 // and what is left runs alone.
 void build_pairs(const std::vector<int>& st, std::vector<int4>* pairs, std::vector<int>* gstart) {
   gstart->clear();
-  for (int dz = -kRad; dz <= kRad; ++dz) {
+  for (int gi = 0; gi < kBwdGroups; ++gi) {
     gstart->push_back((int)pairs->size());
     std::vector<int> ids;
     for (int i = 0; i < kNStencil; ++i)
-      if (st[3 * i + 2] == dz) ids.push_back(i);
+      if (st[3 * i + 2] == kBwdGroupDz[gi][0] || st[3 * i + 2] == kBwdGroupDz[gi][1]) ids.push_back(i);
     const int n = (int)ids.size();
     auto dx = [&](int a) { return st[3 * ids[a]]; };
     auto compatible = [&](int a, int b) {
-      return std::abs(dx(a) - dx(b)) >= 4 || std::abs(st[3 * ids[a] + 1] - st[3 * ids[b] + 1]) >= 4;
+      return st[3 * ids[a] + 2] != st[3 * ids[b] + 2] || std::abs(dx(a) - dx(b)) >= 4 ||
+             std::abs(st[3 * ids[a] + 1] - st[3 * ids[b] + 1]) >= 4;
     };
     auto preferred = [&](int a, int b) { return compatible(a, b) && (((dx(a) - dx(b)) % 4) + 4) % 4 == 2; };
     std::vector<int> mate(n, -1);
@@ -1880,7 +1891,7 @@ hipError_t mfma_tables_create(MfmaTables* t, double* const* d_T, const int* d_st
   std::vector<int4> pairs;
   std::vector<int> gstart;
   build_pairs(st, &pairs, &gstart);
-  if ((int)pairs.size() > kMaxPairs || gstart.size() != 14) return hipErrorInvalidValue;
+  if ((int)pairs.size() > kMaxPairs || gstart.size() != kBwdGroups + 1) return hipErrorInvalidValue;
   t->npairs = (int)pairs.size();
   std::vector<uint32_t> ptouch(8 * pairs.size(), 0u);
   for (int z = 0; z < 8; ++z)
