@@ -328,6 +328,14 @@ def bench_fwd_bwd(torch, fmm, ctx, K, W):
     try:
         wall_fb, seg_fb = timed(torch, step_fb, max(3, K // 2), W, marks=2)
         fwd_ms, bwd_ms = seg_fb[:, 0].mean(), seg_fb[:, 1].mean()
+
+        # the M2L adjoint alone (no mass-gradient phase), on the same dL
+        def step_adj(ev, i):
+            if ev: ev[0].record()
+            ctx.m2l_backward(d5, wt, dM5)
+            if ev: ev[1].record()
+        _, seg_adj = timed(torch, step_adj, max(3, K // 2), 1, marks=1)
+        adj_ms = seg_adj[:, 0].mean()
         ctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 0)
         _, seg_fbd = timed(torch, step_fb, max(3, K // 2), 1, marks=2)
         bwd_dense_ms = seg_fbd[:, 1].mean()
@@ -340,6 +348,7 @@ def bench_fwd_bwd(torch, fmm, ctx, K, W):
            "forward": "P2M + M2L (harmonic form), one launch (fmm_p2m_m2l)",
            "backward": "M2L adjoint (harmonic form) + P2M adjoint, one launch (fmm_m2l_p2m_backward)",
            "bwd_ms_dense_adjoint": float(bwd_dense_ms),
+           "m2l_adjoint_only_ms": float(adj_ms),
            "fwd_ms": float(fwd_ms), "bwd_ms": float(bwd_ms),
            "fwd_bwd_ms_per_batch": float(fwd_ms + bwd_ms),
            "bwd_over_fwd": float(bwd_ms / fwd_ms),
@@ -351,10 +360,12 @@ def bench_fwd_bwd(torch, fmm, ctx, K, W):
                         "bwd_achieved": fl_h / (bwd_ms * 1e-3) / 1e12,
                         "bwd_frac": fl_h / (bwd_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                         "bwd_dense_adjoint_frac": fl_d / (bwd_dense_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                        "m2l_adjoint_only_frac": fl_h / (adj_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                         "note": "executed matrix flops of the M2L (or its adjoint) over the whole launch, "
                                 "which also holds the HBM-bound moment (or mass-gradient) phase"}}
-    log("fwd+bwd 2048: fwd %.3f ms (%.1f%%), bwd %.3f ms (%.1f%%)"
-        % (fwd_ms, 100 * out["roofline"]["fwd_frac"], bwd_ms, 100 * out["roofline"]["bwd_frac"]))
+    log("fwd+bwd 2048: fwd %.3f ms (%.1f%%), bwd %.3f ms (%.1f%%); M2L adjoint alone %.3f ms (%.1f%%)"
+        % (fwd_ms, 100 * out["roofline"]["fwd_frac"], bwd_ms, 100 * out["roofline"]["bwd_frac"],
+           adj_ms, 100 * out["roofline"]["m2l_adjoint_only_frac"]))
     del pos5, mass5, wt, M5, L5, dM5, dm5
     torch.cuda.empty_cache()
     return out
