@@ -142,9 +142,11 @@ typedef struct {
 
 /* Create a context on HIP device `device`, or a host-only context with
  * device = -1 (argument checking and host queries only; compute calls then
- * return FMM_EUNSUPPORTED after their checks pass). Generates the stencil
- * tables T_d for p = 2, 3, 4 on the device (derivative recurrence in
- * float64), which makes this call synchronous. */
+ * return FMM_EUNSUPPORTED after their checks pass). Computes the derivatives
+ * of 1/r at the stencil offsets on the host (exact integer numerators, one
+ * final rounding to float64: within one unit in the last place of every
+ * entry), uploads them and forms the tables T_d for p = 2, 3, 4 and their
+ * packed forms on the device, which makes this call synchronous. */
 fmm_status fmm_create(fmm_ctx** out, int32_t device);
 
 /* Release everything the context owns; NULL is accepted. Synchronises the device. */
