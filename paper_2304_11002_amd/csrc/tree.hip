@@ -285,14 +285,15 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
 
   const int* dq = s_doff + wave * kTreeQuads * 4 + kk;
   // this thread's window cells: global index, or -1 outside the domain
-  int64_t wg[STAGE];
+  // (n^3 <= 2^21 cells per level, so a cell index fits 32 bits)
+  int wg[STAGE];
 #pragma unroll
   for (int i = 0; i < STAGE; ++i) {
     const int c = tid + i * kTreeThreads;
     const int gx = B0x - 5 + c % WX, gy = B0y - 5 + (c / WX) % kTreeW,
               gz = B0z - 5 + c / (WX * kTreeW);
     wg[i] = (c < WCELLS && gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n)
-                ? gx + (int64_t)n * gy + (int64_t)n * n * gz
+                ? gx + n * gy + n * n * gz
                 : -1;
   }
   for (int r = 0; r < ROUNDS; ++r) {
@@ -306,16 +307,25 @@ __global__ void __launch_bounds__(kTreeThreads) m2l_level_kernel(
       const HRound& rd = hround[r];
       s0 = ldexp(1.0, -lg * rd.ord0);
       s1 = rd.ord1 >= 0 ? ldexp(1.0, -lg * rd.ord1) : 0.0;
-      for (int u = 0; u < rd.nsup; ++u) {
-        const double* src = M + (int64_t)rd.comp[u] * n3;
+      // two components at a time, so both sets of loads are in flight together
+      // (an odd count's last pass reads its component twice, the second time
+      // with zero coefficients)
+      for (int u = 0; u < rd.nsup; u += 2) {
+        const int u1 = u + 1 < rd.nsup ? u + 1 : u;
+        const double* srcA = M + (int64_t)rd.comp[u] * n3;
+        const double* srcB = M + (int64_t)rd.comp[u1] * n3;
         const double a0 = rd.c0[u], a1 = rd.c1[u];
+        const double b0 = u1 != u ? rd.c0[u1] : 0.0, b1 = u1 != u ? rd.c1[u1] : 0.0;
+        double ma[STAGE], mb[STAGE];
 #pragma unroll
         for (int i = 0; i < STAGE; ++i) {
-          if (wg[i] >= 0) {
-            const double m = src[wg[i]];
-            v[i].x = __builtin_fma(a0, m, v[i].x);
-            v[i].y = __builtin_fma(a1, m, v[i].y);
-          }
+          ma[i] = wg[i] >= 0 ? srcA[wg[i]] : 0.0;
+          mb[i] = wg[i] >= 0 ? srcB[wg[i]] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < STAGE; ++i) {
+          v[i].x = __builtin_fma(b0, mb[i], __builtin_fma(a0, ma[i], v[i].x));
+          v[i].y = __builtin_fma(b1, mb[i], __builtin_fma(a1, ma[i], v[i].y));
         }
       }
     } else {
