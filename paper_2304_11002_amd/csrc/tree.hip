@@ -43,6 +43,7 @@ constexpr int kTreeList = 231;                     // interaction-list length pe
 constexpr int kTreeQuads = (kTreeList + 3) / 4;    // 58 (the last quad has one empty slot)
 constexpr int kTreeThreads = 512;
 constexpr int kTreeMaxLevels = 8;
+constexpr int kTreeWideMin = 64;                   // levels of at least this many cells per axis: NBLK = 2
 
 __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
@@ -569,36 +570,55 @@ hipError_t launch_tree_m2l(int p, const TreeTables& tt, const MfmaTables& mt, bo
                            const double* M, double* L, int nlev, const int* n, const int* lg,
                            const int64_t* off, hipStream_t s) {
   if (nlev < 1 || nlev > kTreeMaxLevels) return hipErrorInvalidValue;
-  TreeLevels lv{};
-  lv.nlev = nlev;
-  int total = 0;
-  const int nblk = p <= 3 ? 2 : 1;             // blocks per workgroup (registers at p = 4)
-  for (int i = 0; i < nlev; ++i) {            // coarsest level first
-    const int l = nlev - 1 - i;
-    const int nb = n[l] >= 8 ? n[l] / 8 : 1;
-    const int nbx = n[l] >= 8 * nblk ? n[l] / (8 * nblk) : 1;
-    lv.first[i] = total;
-    lv.n[i] = n[l];
-    lv.lg[i] = lg[l];
-    lv.off[i] = off[l];
-    total += nbx * nb * nb;
-  }
-  lv.first[nlev] = total;
-  const dim3 grid((unsigned)total), block(kTreeThreads);
-#define TREE_LAUNCH(P, H)                                                                              \
-  hipLaunchKernelGGL((m2l_level_kernel<P, H, (P <= 3 ? 2 : 1)>), grid, block, 0, s, M, L, lv,           \
+  // Two 8^3 blocks per workgroup (NBLK = 2) where a level has many of them, one
+  // (NBLK = 1) on the coarse levels and at p = 4 (registers). Each workgroup of a
+  // launch has the same work, at one workgroup per CU, so a launch whose count is
+  // just over a multiple of the CU count ends with a nearly idle wave: on 128^3,
+  // 2304 wide workgroups for the 128 and 64 levels (9 full waves) then the 32..4
+  // levels as 74 narrow ones (each ~0.6 of a wide one), instead of 2342 wide ones
+  // in one launch (a tenth wave of 38).
+  auto wide = [&](int l) { return p <= 3 && n[l] >= kTreeWideMin; };
+  for (int pass = 0; pass < 2; ++pass) {
+    const int nblk = pass == 0 ? 2 : 1;
+    TreeLevels lv{};
+    int total = 0, cnt = 0;
+    for (int i = 0; i < nlev; ++i) {            // coarsest level first
+      const int l = nlev - 1 - i;
+      if (wide(l) != (pass == 0)) continue;
+      const int nb = n[l] >= 8 ? n[l] / 8 : 1;
+      const int nbx = n[l] >= 8 * nblk ? n[l] / (8 * nblk) : 1;
+      lv.first[cnt] = total;
+      lv.n[cnt] = n[l];
+      lv.lg[cnt] = lg[l];
+      lv.off[cnt] = off[l];
+      total += nbx * nb * nb;
+      ++cnt;
+    }
+    if (cnt == 0) continue;
+    lv.nlev = cnt;
+    lv.first[cnt] = total;
+    const dim3 grid((unsigned)total), block(kTreeThreads);
+#define TREE_LAUNCH(P, H, NB)                                                                   \
+  hipLaunchKernelGGL((m2l_level_kernel<P, H, NB>), grid, block, 0, s, M, L, lv,                \
                      H ? tt.Bh[P] : tt.B[P], tt.doff, mt.hround[P], mt.hexp[P])
-  switch (p * 2 + (harmonic ? 1 : 0)) {
-    case 4: TREE_LAUNCH(2, false); break;
-    case 5: TREE_LAUNCH(2, true); break;
-    case 6: TREE_LAUNCH(3, false); break;
-    case 7: TREE_LAUNCH(3, true); break;
-    case 8: TREE_LAUNCH(4, false); break;
-    case 9: TREE_LAUNCH(4, true); break;
-    default: return hipErrorInvalidValue;
-  }
+    switch ((p * 2 + (harmonic ? 1 : 0)) * 2 + pass) {
+      case 8: TREE_LAUNCH(2, false, 2); break;
+      case 9: TREE_LAUNCH(2, false, 1); break;
+      case 10: TREE_LAUNCH(2, true, 2); break;
+      case 11: TREE_LAUNCH(2, true, 1); break;
+      case 12: TREE_LAUNCH(3, false, 2); break;
+      case 13: TREE_LAUNCH(3, false, 1); break;
+      case 14: TREE_LAUNCH(3, true, 2); break;
+      case 15: TREE_LAUNCH(3, true, 1); break;
+      case 17: TREE_LAUNCH(4, false, 1); break;
+      case 19: TREE_LAUNCH(4, true, 1); break;
+      default: return hipErrorInvalidValue;
+    }
 #undef TREE_LAUNCH
-  return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace fmm
