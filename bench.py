@@ -226,7 +226,7 @@ def bench_tree(torch, fmm, ctx, K, W):
            "upward_ms": up, "m2l_ms": m2l, "downward_ms": down, "evaluate_ms": ev,
            "m2l_pairs": pairs, "m2l_pairs_per_s": pairs / (m2l * 1e-3), "m2l_form": "harmonic",
            "m2l_dense_ms": m2l_dense, "m2l_dense_tflops": fl_dense / (m2l_dense * 1e-3) / 1e12,
-           "roofline_m2l": {"bound": "mfma", "kernel": "m2l_level_kernel<3, true> (v_mfma_f64_4x4x4, harmonic form, all levels)",
+           "roofline_m2l": {"bound": "mfma", "kernel": "m2l_level_kernel<3, true, 2> (levels 128, 64) + m2l_level_kernel<3, true, 1> (levels 32..4), v_mfma_f64_4x4x4, harmonic form; time of the fmm_tree_m2l call",
                             "achieved": fl / (m2l * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                             "frac": fl / (m2l * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
                             "executed_flops": fl, "flops_per_slot": harmonic_flops_per_pair(p),
