@@ -56,9 +56,9 @@ def check(got, want, scale, what):
         what, bad.sum(), np.nanmax(err / np.maximum(scale, 1e-300)))
 
 
-# (p, n, ppc, log2_h): orders 2-4, one to five levels below the top, two-block
-# workgroups (p <= 3) and single blocks (p = 4), and more than 8 particles per
-# cell (the evaluation's particle chunks)
+# (p, n, ppc, log2_h): orders 2-4, one to five levels below the top, and more
+# than 8 particles per cell (the evaluation's particle chunks); every level of
+# these domains runs in the one-block launch of the level M2L
 CASES = [(2, 16, 2, 0), (3, 16, 3, -1), (4, 8, 2, 1), (3, 32, 1, 0), (3, 8, 11, 0)]
 
 
@@ -144,6 +144,23 @@ def test_tree_solve_accuracy_against_the_direct_sum(ctx, torch):
     ex = T.direct_all(pos, mass)
     assert np.max(np.abs(E[0] - ex[0]) / ex[0]) < 5e-4
     assert np.median(np.abs(E[1:] - ex[1:]).max(axis=0) / np.abs(ex[1:]).max(axis=0)) < 1.5e-3
+
+
+def test_tree_m2l_wide_and_narrow_launches(ctx, torch):
+    # 64^3: the 64 level goes in the launch of two-block workgroups, the 32 .. 4
+    # levels in the one-block launch; every level of both forms against the oracle
+    p, n, ppc, h = 2, 64, 1, 1.0
+    pos, mass = synth.grid_particles(12, n, h, ppc)
+    Mo = T.upward(pos, mass, p, n, h)
+    Lo, La = T.m2l_levels(Mo, p, h), T.m2l_levels(Mo, p, h, absolute=True)
+    for harmonic in (0, 1):
+        tree = fmm.Tree(p, n, ppc, 0, harmonic)
+        _, elems = fmm.tree_size(tree)
+        L = torch.full((elems,), float("nan"), dtype=torch.float64, device="cuda")
+        ctx.tree_m2l(tree, to_dev(flatten(Mo)), L)
+        torch.cuda.synchronize()
+        for lvl, (g, w, s) in enumerate(zip(split_levels(L.cpu().numpy(), p, n), Lo, La)):
+            check(g, w, s, "64^3 L level %d (harmonic %d)" % (lvl, harmonic))
 
 
 # a seeded sweep over order, spacing (the extremes of log2_h), form and particle count
