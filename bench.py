@@ -738,7 +738,7 @@ def main():
         try:
             _, seg1s = timed(torch, step_one, K, W, marks=1)
         finally:
-            ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 0)
+            ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, -1)
         out["single_subgrid"] = {"workload": "single_subgrid_p3", "pairs": fmm.pair_count(d1),
                                  "step_ms_median": float(np.median(seg1[:, 0])),
                                  "step_ms_min": float(seg1[:, 0].min()),
@@ -767,13 +767,20 @@ def main():
         try:
             _, seg_ss = timed(torch, step_small, K, W, marks=1)
         finally:
-            ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 0)
+            ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, -1)
+        # and as the autotuner leaves it (it times the round split too at this size)
+        Lt128 = torch.empty_like(L128)
+        tuned128 = ctx.autotune(d128, M128, Lt128, fmm.FMM_FP64_HARMONIC)
+        del Lt128
+        _, seg_st = timed(torch, step_small, K, W, marks=1)
         out["small_uneven_batch"] = {"workload": "uneven_128_mixed_p (p 1:2:1, random masks, three spacings)",
                                      "pairs": fmm.pair_count(d128),
                                      "form": "harmonic", "m2l_ms": float(np.median(seg_sw[:, 0])),
-                                     "round_split_m2l_ms": float(np.median(seg_ss[:, 0]))}
-        log("uneven 128: M2L %.3f ms, %.3f ms with the rounds split over workgroups"
-            % (np.median(seg_sw[:, 0]), np.median(seg_ss[:, 0])))
+                                     "round_split_m2l_ms": float(np.median(seg_ss[:, 0])),
+                                     "autotuned_m2l_ms": float(np.median(seg_st[:, 0])),
+                                     "autotune_choice": tuned128}
+        log("uneven 128: M2L %.3f ms, %.3f ms with the rounds split over workgroups, %.3f ms autotuned"
+            % (np.median(seg_sw[:, 0]), np.median(seg_ss[:, 0]), np.median(seg_st[:, 0])))
         del p128, ms128, M128, L128
 
         # ---------------- CPU baseline (the oracle on the host cores)

@@ -133,12 +133,14 @@ typedef struct {
 #define FMM_OPT_SLICES      7  /* FMM_EXACT_SLICE: slices per operand S, 6, 7 (default) or 8 */
 #define FMM_OPT_ROUND_SPLIT 6  /* fmm_m2l (and the M2L of fmm_p2m_m2l when it runs as two
                                   launches) on batches of at most 256 sub-grids, with a configuration
-                                  with LDS-staged tables: 0 (default) one workgroup per sub-grid;
-                                  1 one workgroup per (sub-grid, round of two moment components),
-                                  each round's sums added in round order by a second kernel. For
-                                  batches that cannot fill the GPU, or whose longest sub-grid (p = 4)
-                                  would set the time; equal up to rounding; 140 KB of device memory
-                                  per (sub-grid, round) is held per descriptor set. */
+                                  with LDS-staged tables: 0 one workgroup per sub-grid; 1 one
+                                  workgroup per (sub-grid, round of two moment components), each
+                                  round's sums added in round order by a second kernel; -1 (default)
+                                  the choice fmm_autotune made for the descriptor set and precision
+                                  (one workgroup per sub-grid until it has run). For batches that
+                                  cannot fill the GPU, or whose longest sub-grid (p = 4) would set
+                                  the time; equal up to rounding; 140 KB of device memory per
+                                  (sub-grid, round) is held per descriptor set. */
 
 /* Create a context on HIP device `device`, or a host-only context with
  * device = -1 (argument checking and host queries only; compute calls then
@@ -333,6 +335,10 @@ fmm_status fmm_stencil_tables(fmm_ctx* ctx, int32_t p, double* out, void* stream
  * operand prefetch) on these descriptors and buffers (M read, L
  * overwritten) and keep the fastest for later calls with the same
  * descriptor set and precision; `chosen` (may be NULL) receives its index.
+ * On batches of at most 256 sub-grids whose chosen configuration stages its
+ * tables in LDS it also times the round split (FMM_OPT_ROUND_SPLIT) with that
+ * configuration, allocating its list as the option's first call does, and
+ * keeps it for later calls if it is faster and the option is -1.
  * Synchronises the stream. FMM_OPT_TILE_CONFIG >= 0 overrides the choice. */
 fmm_status fmm_autotune(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub,
                         const double* M, double* L, fmm_precision prec,

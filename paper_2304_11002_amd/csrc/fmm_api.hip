@@ -113,6 +113,7 @@ struct DescEntry {
   double* split_part[2] = {};
   bool part_even = true;          // every part_off even: particle blocks 16-byte aligned
   int tuned[4] = {-1, -1, -1, -1};   // autotuned configuration per precision
+  bool split_tuned[4] = {false, false, false, false};   // the autotuner chose the round split
   // FMM_EXACT_SLICE: the sub-grids' slice planes and exponents (one allocation)
   void* slice_dev = nullptr;
   size_t slice_bytes = 0;
@@ -148,7 +149,7 @@ struct fmm_ctx {
   int tile_config = -1;
   int adjoint_form = 0;     // FMM_OPT_ADJOINT_FORM
   int p2m_window = 0;       // FMM_OPT_P2M_WINDOW
-  int round_split = 0;      // FMM_OPT_ROUND_SPLIT
+  int round_split = -1;     // FMM_OPT_ROUND_SPLIT: -1 the autotuner's choice, 0 never, 1 always
   int slices = 7;           // FMM_OPT_SLICES
   // fmm_m2l_noalloc: this device's address of the static array, a pinned host
   // copy of its descriptor and work-list part, and the event after its upload
@@ -519,7 +520,7 @@ fmm_status fmm_set_option(fmm_ctx* ctx, int32_t option, int64_t value) {
       ctx->p2m_window = (int)value;
       return FMM_OK;
     case FMM_OPT_ROUND_SPLIT:
-      if (value != 0 && value != 1) return set_err(ctx, FMM_EINVAL, "FMM_OPT_ROUND_SPLIT value not 0/1");
+      if (value < -1 || value > 1) return set_err(ctx, FMM_EINVAL, "FMM_OPT_ROUND_SPLIT value not -1/0/1");
       ctx->round_split = (int)value;
       return FMM_OK;
     case FMM_OPT_SLICES:
@@ -885,7 +886,8 @@ static fmm_status run_m2l(fmm_ctx* ctx, DescEntry* e, const double* M, double* L
                           int cfg, hipStream_t s) {
   if (ctx->m2l_kernel == 1) return run_ref(ctx, e, false, M, L, s);
   if (prec == FMM_EXACT_SLICE) return run_slice(ctx, e, M, L, s);
-  if (ctx->round_split && (int64_t)e->host.size() <= kMaxSplitSubgrids && mfma_config_fusable(cfg))
+  const bool split = ctx->round_split > 0 || (ctx->round_split < 0 && e->split_tuned[prec]);
+  if (split && (int64_t)e->host.size() <= kMaxSplitSubgrids && mfma_config_fusable(cfg))
     return run_split(ctx, e, M, L, prec, cfg, s);
   return run_mfma(ctx, e, M, L, prec, cfg, s);
 }
@@ -1105,6 +1107,22 @@ fmm_status fmm_autotune(fmm_ctx* ctx, const fmm_subgrid* desc, int64_t nsub, con
       best = cfg;
       best_ms = cfg_ms;
     }
+  }
+  // small batches: the round split with the chosen configuration, timed the same way
+  e->split_tuned[prec] = false;
+  if (nsub <= kMaxSplitSubgrids && mfma_config_fusable(best) && ctx->m2l_kernel != 1) {
+    CHECK_OK(run_split(ctx, e, M, L, prec, best, s));
+    float split_ms = 1e30f;
+    for (int r = 0; r < 3; ++r) {
+      HIP_TRY(ctx, hipEventRecord(t0, s));
+      CHECK_OK(run_split(ctx, e, M, L, prec, best, s));
+      HIP_TRY(ctx, hipEventRecord(t1, s));
+      HIP_TRY(ctx, hipEventSynchronize(t1));
+      float ms = 0.f;
+      HIP_TRY(ctx, hipEventElapsedTime(&ms, t0, t1));
+      split_ms = std::min(split_ms, ms);
+    }
+    e->split_tuned[prec] = split_ms < best_ms;
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);

@@ -282,7 +282,7 @@ class Context:
 
     # the library's defaults (fmm.h), for get_option before any set_option
     _OPTION_DEFAULTS = {FMM_OPT_M2L_KERNEL: 0, FMM_OPT_USE_GRAPH: 1, FMM_OPT_TILE_CONFIG: -1,
-                        FMM_OPT_ADJOINT_FORM: 0, FMM_OPT_P2M_WINDOW: 0, FMM_OPT_ROUND_SPLIT: 0,
+                        FMM_OPT_ADJOINT_FORM: 0, FMM_OPT_P2M_WINDOW: 0, FMM_OPT_ROUND_SPLIT: -1,
                         FMM_OPT_SLICES: 7}
 
     def set_option(self, option, value):

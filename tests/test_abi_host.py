@@ -97,6 +97,7 @@ def test_pointer_and_option_validation(hctx):
                  lambda: hctx.set_option(99, 0),
                  lambda: hctx.set_option(fmm.FMM_OPT_P2M_WINDOW, 2),
                  lambda: hctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 2),
+                 lambda: hctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, -2),
                  lambda: hctx.stencil_tables(5, 8),
                  lambda: hctx.evaluate(desc, 8, 8, 0, 8, 8),
                  lambda: hctx.evaluate(desc, 8, 8, 65, 8, 8),
@@ -167,6 +168,10 @@ def test_harmonic_precision_checks(hctx):
     with pytest.raises(fmm.FMMError) as e:
         hctx.set_option(fmm.FMM_OPT_ADJOINT_FORM, 2)
     assert e.value.status == fmm.FMM_EINVAL
+    # the round split: -1 (the autotuner's choice, the default), 0 and 1
+    for v in (1, 0, -1):
+        hctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, v)
+    assert hctx.get_option(fmm.FMM_OPT_ROUND_SPLIT) == -1
 
 
 def test_null_context_and_create_errors(lib):

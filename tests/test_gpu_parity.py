@@ -411,11 +411,29 @@ def test_harmonic_form_deterministic_graphs_and_autotune(ctx, torch):
         torch.cuda.synchronize()
         assert torch.equal(L, L_plain), rep
         assert x.item() == 1000
-    chosen = ctx.autotune(desc, M, L_plain, HARM)
-    L = torch.full_like(L_plain, float("nan"))
-    ctx.m2l(desc, M, L, HARM)
-    torch.cuda.synchronize()
-    assert chosen >= 0 and torch.equal(L, L_plain)
+    # the autotuner, on a context of its own (its choice is kept per descriptor
+    # set): with FMM_OPT_ROUND_SPLIT = 0 the tuned call gives the same bits; at its
+    # default (-1) five sub-grids, far too few to fill the GPU, take the round
+    # split, which it times too: the bits of FMM_OPT_ROUND_SPLIT = 1
+    c2 = fmm.Context(0)
+    try:
+        Lt = torch.empty_like(L_plain)
+        chosen = c2.autotune(desc, M, Lt, HARM)
+        L = torch.full_like(L_plain, float("nan"))
+        c2.m2l(desc, M, L, HARM)
+        outs = {}
+        for opt in (0, 1):
+            c2.set_option(fmm.FMM_OPT_ROUND_SPLIT, opt)
+            outs[opt] = torch.full_like(L_plain, float("nan"))
+            c2.m2l(desc, M, outs[opt], HARM)
+        c2.set_option(fmm.FMM_OPT_ROUND_SPLIT, -1)
+        torch.cuda.synchronize()
+    finally:
+        c2.close()
+    assert chosen >= 0 and torch.equal(outs[0], L_plain)
+    assert torch.equal(L, outs[1])
+    scale = torch.abs(L_plain).max()
+    assert (torch.abs(L - L_plain) <= 1e-13 * scale).all()
 
 
 def test_harmonic_adjoint_matches_oracle_and_is_deterministic(ctx, torch):
@@ -520,7 +538,7 @@ def test_round_split_option(ctx, torch, prec, cfg):
         ctx.m2l(desc, M, L2, prec)
         torch.cuda.synchronize()
     finally:
-        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 0)
+        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, -1)
         ctx.set_option(fmm.FMM_OPT_TILE_CONFIG, -1)
     assert torch.equal(L1, L2)                       # deterministic
     Lg, L0v = split_views(L1.cpu().numpy(), desc, "L"), split_views(L0.cpu().numpy(), desc, "L")
@@ -539,7 +557,7 @@ def test_round_split_option(ctx, torch, prec, cfg):
         ctx.m2l(desc1, M1, L1s, prec)
         torch.cuda.synchronize()
     finally:
-        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 0)
+        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, -1)
     _, Lo, La = oracle_subgrid(w1, 0, p1[0], ms1[0])
     assert_close(L1s.cpu().numpy().reshape(Lo.shape), Lo, La, TOL, "round split single sub-grid")
     w = synth.config(3, nsub=257)
@@ -554,7 +572,7 @@ def test_round_split_option(ctx, torch, prec, cfg):
         ctx.m2l(desc, M, Lb_, prec)
         torch.cuda.synchronize()
     finally:
-        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 0)
+        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, -1)
     assert torch.equal(La_, Lb_)
 
 
@@ -576,7 +594,7 @@ def test_round_split_mid_size_uneven_batch(ctx, torch):
         ctx.m2l(desc, M, L1, HARM)
         torch.cuda.synchronize()
     finally:
-        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, 0)
+        ctx.set_option(fmm.FMM_OPT_ROUND_SPLIT, -1)
     Lg, L0v = split_views(L1.cpu().numpy(), desc, "L"), split_views(L0.cpu().numpy(), desc, "L")
     for b in range(n):
         scale = np.abs(L0v[b]).reshape(L0v[b].shape[0], -1).max(axis=1)[:, None, None, None]
