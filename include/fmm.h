@@ -49,8 +49,12 @@
  *       * with FMM_OPT_USE_GRAPH, capturing a 17th graph first releases the
  *         least recently used graph, after the host has waited for that
  *         graph's last launch (on whatever stream it ran);
- *       * the first FMM_OPT_ROUND_SPLIT call on a set allocates its round
- *         list and round sums, held with the set;
+ *       * the first call on a set that runs the round split (FMM_OPT_ROUND_SPLIT,
+ *         or fmm_autotune timing it) allocates its round list and round
+ *         sums, held with the set;
+ *       * the first FMM_EXACT_SLICE call on a set, or one with more slices
+ *         than before, allocates the slice planes (after waiting for the
+ *         set's last launch when it replaces them);
  *     fmm_create, fmm_destroy and fmm_autotune synchronise.
  *   - All argument checks run on the host before any HIP call: a call that
  *     returns FMM_EINVAL has touched neither the device nor the context's
